@@ -1,0 +1,50 @@
+"""Exact matvec g = K f on selected rows, FP64 (test infrastructure).
+
+Problem statement (Section 4, the potential g(x) = sum over xi of
+K(x, xi) f(xi); Section 5, eq. (eqn:1D-FIO)): the sum is plain, with no
+quadrature weight and no 1/N, and the kernel is
+K(x, xi) = alpha(x, xi) exp(2 pi i Phi(x, xi)) with alpha taken from its
+formula.  Rows are computed one block at a time and accumulated with a BLAS
+product in complex128.
+"""
+
+import numpy as np
+
+from .kernel import coords, expi_phase, amplitude
+
+
+def kernel_rows(dim, n, phase_kind, phase_params, amp_kind, rows):
+    """Rows ``rows`` of K as a complex128 array (len(rows), N)."""
+    N = n ** dim
+    ix = coords(np.asarray(rows), dim, n)[:, None, :]
+    jx = coords(np.arange(N), dim, n)[None, :, :]
+    K = expi_phase(phase_kind, phase_params, ix, jx, n)
+    if amp_kind != "one":
+        K = K * amplitude(amp_kind, ix, jx, n)
+    return K
+
+
+def dense_rows(dim, n, phase_kind, phase_params, amp_kind, f, rows,
+               block=8):
+    """g[v, rows] = sum_j K[rows, j] f[v, j] for every vector v of ``f``.
+
+    f: complex array [nvec][N].  Returns complex128 [nvec][len(rows)].
+    """
+    f = np.atleast_2d(np.asarray(f, np.complex128))
+    rows = np.asarray(rows, np.int64)
+    out = np.empty((f.shape[0], rows.size), np.complex128)
+    for s in range(0, rows.size, block):
+        K = kernel_rows(dim, n, phase_kind, phase_params, amp_kind,
+                        rows[s:s + block])
+        out[:, s:s + block] = f @ K.T
+    return out
+
+
+def rel_err(approx, exact):
+    """Relative l2 error over the sampled rows, per vector (Section 5,
+    definition of epsilon^b).  approx, exact: [nvec][rows]."""
+    approx = np.atleast_2d(approx)
+    exact = np.atleast_2d(exact)
+    num = np.sqrt(np.sum(np.abs(approx - exact) ** 2, axis=-1))
+    den = np.sqrt(np.sum(np.abs(exact) ** 2, axis=-1))
+    return num / den
