@@ -1,0 +1,177 @@
+/*
+ * bf.h -- C ABI of an MI355X (gfx950) interpolative butterfly apply for the
+ * oscillatory matvec g = K f, K(x, xi) = alpha(x, xi) exp(2 pi i Phi(x, xi)).
+ *
+ * Method: H. Yang, "A Unified Framework for Oscillatory Integral Transforms:
+ * When to use NUFFT or Butterfly Factorization?" (arXiv:1803.04128).
+ *   - problem statement: Section 4 (potential g(x) = sum_xi K(x, xi) f(xi))
+ *     and Section 5, eq. (eqn:1D-FIO) with the grid of eq. (eqn:1D-xandxi);
+ *   - amplitude split: eq. (eqn:tg), g = sum_k a_k * BF(b_k * f);
+ *   - factors: Algorithm 2 (interpolative low-rank approximation, Section
+ *     2.1) on the dyadic trees of Section 4;
+ *   - apply: the butterfly algorithm of Section 4 (Algorithm 4.1), with the
+ *     precomputed factors kept for many input vectors (Section 1 footnote
+ *     on reusing precomputation; Section 4 closing paragraph).
+ *
+ * Grid (per dimension, 0-based): x_i = i / n, xi_j = j - n/2, n a power of
+ * two.  dim = 1: N = n.  dim = 2: N = n * n and a point is addressed by its
+ * row-major index i1 * n + i2 (the tree order is internal).
+ *
+ * Complex data is interleaved single precision (re, im) on the device, and
+ * interleaved double precision on the host where stated.
+ *
+ * Errors: every call returns BF_OK (0) or a negative status; the message of
+ * the last failure on the calling thread is returned by bf_last_error().
+ * No C++ exception crosses this interface.  Kernel faults surface at the
+ * caller's next synchronisation of the stream.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BF_OK            0
+#define BF_EINVAL       -1   /* bad argument (shape, null pointer, aliasing) */
+#define BF_ENOMEM       -2   /* device or host allocation failed, or the
+                                request exceeds the configured memory cap */
+#define BF_EHIP         -3   /* a HIP runtime call failed */
+#define BF_EUNSUPPORTED -4   /* valid request this build does not implement */
+#define BF_EBUSY        -5   /* resource in use */
+
+/* ---- phase functions (evaluated in FP64 on the device) ------------------ */
+/* BF_PHASE_DFT:       Phi = x . xi                                 (no params)
+ * BF_PHASE_FIO1D:     Phi = x xi + c(x)|xi|, c(x) = (p0 + p1 sin 2 pi x)/p2
+ *                     (Section 5, eq. (eqn:1D-FIO-kernal) with general c)
+ * BF_PHASE_RADON2D:   Phi = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
+ *                     c1 = (p0 + p1 sin 2 pi x1 sin 2 pi x2) / p2,
+ *                     c2 = (p3 + p4 cos 2 pi x1 cos 2 pi x2) / p5
+ * BF_PHASE_SEPARABLE: Phi = p0 sin(2 pi x1)(1 + x2) + p1 |xi| + p2 |xi|^2/n
+ *                     (x2 = 0 in 1D; |xi| Euclidean), additively separable,
+ *                     for which the factorization is exact (R = 0 in
+ *                     eq. (eqn:RAB)).                                      */
+#define BF_PHASE_DFT        0
+#define BF_PHASE_FIO1D      1
+#define BF_PHASE_RADON2D    2
+#define BF_PHASE_SEPARABLE  3
+
+/* ---- arithmetic of the apply ------------------------------------------- */
+/* BF_FP32:   FP32 complex state and factors, FP32 vector arithmetic.
+ * BF_BF16X3: Lagrange matrices and the panel are split x = hi + lo in
+ *            bfloat16; the shared-matrix contraction runs on MFMA as
+ *            hi*hi + hi*lo + lo*hi with FP32 accumulation; twiddles,
+ *            switch blocks and the state stay FP32.
+ * BF_FP16X3: as BF_BF16X3 with IEEE half hi/lo parts (scaled per tile).    */
+#define BF_FP32    0
+#define BF_BF16X3  1
+#define BF_FP16X3  2
+
+typedef struct bf_grid {
+    int dim;   /* 1 or 2 */
+    int n;     /* points per dimension, a power of two, 2 <= n;
+                  1D: n <= 2^22, 2D: n <= 2^11 */
+} bf_grid;
+
+typedef struct bf_phase {
+    int kind;              /* BF_PHASE_* */
+    int nparams;           /* number of entries in params (0, 3 or 6) */
+    const double* params;  /* host, read during bf_plan only */
+} bf_phase;
+
+/* Low-rank amplitude alpha(x, xi) = sum_{k<r} a_k(x) b_k(xi) (eq. (eqn:tg)).
+ * a, b: host complex128 interleaved, layout [r][N] in user index order; read
+ * during bf_plan only.  r = 1 with a = b = NULL means alpha = 1.            */
+typedef struct bf_amplitude {
+    int r;             /* 1 <= r <= 16 */
+    const double* a;
+    const double* b;
+} bf_amplitude;
+
+typedef struct bf_plan_s* bf_plan_t;
+
+/* Plan and factor construction (synchronous).
+ *
+ * Builds the dyadic trees (Section 4), the interpolation points of every box
+ * (eqs. (eqn:gdA)/(eqn:gdB), read with the ascending Chebyshev node), the
+ * box centers, the Lagrange matrices (Section 2.1), and on the device in
+ * FP64 the twiddles and switch blocks of Algorithm 4.1 (eqs. (eqn:1),
+ * (eqn:2), the switch step and eq. (eqn:3), regrouped into unit-modulus
+ * diagonals times one shared real matrix per level and child).  All factor
+ * memory stays on the current device until bf_destroy.
+ *
+ * q: interpolation points per box and dimension, 2 <= q <= 16 (1D) or
+ *    2 <= q <= 8 (2D).
+ * precision: BF_FP32, BF_BF16X3 or BF_FP16X3.
+ * max_nvec: the largest nvec bf_apply will be called with (>= 1); the
+ *    default workspace is sized for it (in vector chunks when large).
+ * out: receives the plan handle.
+ * Returns BF_EINVAL on bad arguments, BF_ENOMEM when device memory (or the
+ * cap set by the environment variable BF_MEM_CAP_BYTES) does not suffice.  */
+int bf_plan(const bf_grid* grid, const bf_phase* phase,
+            const bf_amplitude* amp, int q, int precision, int max_nvec,
+            bf_plan_t* out);
+
+/* Apply: g[v] = sum_k a_k * BF(b_k * f[v]) for v < nvec (eq. (eqn:tg) with
+ * Algorithm 4.1).
+ * f, g: device complex64 interleaved, layout [nvec][N], contiguous, owned
+ *    by the caller; g must not overlap f.
+ * stream: a hipStream_t (NULL = the null stream).  The call is asynchronous
+ *    on that stream and allocates nothing; it uses the plan's workspace, so
+ *    applies of one plan must not overlap (use bf_apply_ws for that).
+ * Returns BF_EINVAL for nvec < 1, nvec > max_nvec, null or overlapping
+ * pointers.                                                               */
+int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream);
+
+/* Workspace bytes bf_apply_ws needs for nvec vectors. */
+int bf_workspace_bytes(bf_plan_t plan, int nvec, size_t* bytes);
+
+/* As bf_apply with a caller-owned device workspace of ws_bytes bytes
+ * (>= bf_workspace_bytes(plan, nvec)); applies of one plan with distinct
+ * workspaces may run concurrently on different streams.                   */
+int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Releases every device allocation of the plan after synchronising the
+ * device work the plan issued.  NULL is accepted.                         */
+int bf_destroy(bf_plan_t plan);
+
+typedef struct bf_plan_info {
+    int dim, n, L, h, q, r, precision;
+    long long N;
+    int first_xi_level;    /* first level with an interpolating xi step   */
+    int last_x_level;      /* last level with an interpolating x step     */
+    int n_steps;           /* computed steps: xi levels + switch + x levels */
+    int n_passes;          /* kernel passes per vector chunk              */
+    int max_rank;          /* largest number of coefficients per pair     */
+    int chunk_nvec;        /* vectors per workspace chunk                 */
+    size_t factor_bytes;   /* device bytes of twiddles, blocks, matrices  */
+    size_t workspace_bytes;/* default workspace (for chunk_nvec vectors)  */
+    double flops_per_column;  /* algorithmic flops per apply column       */
+    double factor_stream_bytes; /* factor bytes read per apply            */
+} bf_plan_info;
+
+int bf_query(bf_plan_t plan, bf_plan_info* info);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* bf_last_error(void);
+
+/* ---- host-only geometry (no device needed) ------------------------------
+ * Interpolation offsets of a box of box_size indices with q points
+ * (eqs. (eqn:gdA)/(eqn:gdB), ascending-node reading, ties rounded up, all
+ * indices when box_size <= q): writes min(q, box_size) 0-based offsets to
+ * out (capacity cap) and their count to *count.                          */
+int bf_points(int box_size, int q, int* out, int cap, int* count);
+
+/* Lagrange weights M_t(y) of the node set nodes[0..r) at points y[0..m):
+ * out[k * r + t] = prod_{j != t} (y_k - x_j) / (x_t - x_j), FP64 (Section
+ * 2.1).                                                                   */
+int bf_lagrange(const int* nodes, int r, const double* y, int m, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H */

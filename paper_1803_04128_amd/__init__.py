@@ -1,0 +1,140 @@
+"""MI355X (gfx950) interpolative butterfly apply for oscillatory transforms.
+
+g = K f with K(x, xi) = alpha(x, xi) exp(2 pi i Phi(x, xi)), computed as
+g = sum_k a_k * BF(b_k * f) (eq. (eqn:tg) of arXiv:1803.04128) with the
+butterfly factorization of Section 4.  This module is a thin ctypes binding
+of libbf.so (include/bf.h): it marshals arguments; every step of the apply
+runs in the library's HIP kernels.  PyTorch provides device memory and
+streams only.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BfError, PHASES, PRECISIONS  # noqa: F401
+
+__all__ = ["Plan", "BfError", "points", "lagrange", "load"]
+
+
+def load():
+    return _lib.load()
+
+
+def points(box_size, q):
+    """Host-only: 0-based interpolation offsets of a box (bf_points)."""
+    lib = _lib.load()
+    out = (C.c_int * 16)()
+    cnt = C.c_int()
+    _lib.check(lib.bf_points(int(box_size), int(q), out, 16, C.byref(cnt)))
+    return np.array(out[:cnt.value], dtype=np.int64)
+
+
+def lagrange(nodes, y):
+    """Host-only: Lagrange weights [len(y)][len(nodes)] (bf_lagrange)."""
+    lib = _lib.load()
+    nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros((y.size, nodes.size), np.float64)
+    _lib.check(lib.bf_lagrange(
+        nodes.ctypes.data_as(C.POINTER(C.c_int)), nodes.size,
+        y.ctypes.data_as(C.POINTER(C.c_double)), y.size,
+        out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+class Plan:
+    """A device-resident butterfly plan (bf_plan ... bf_destroy).
+
+    dim, n: grid (x_i = i/n, xi_j = j - n/2 per dimension).
+    phase: "dft" | "fio1d" | "radon2d" | "separable"; params: its numbers.
+    q: interpolation points per box and dimension.
+    amplitude: None (alpha = 1) or (a, b), complex arrays [r][N].
+    precision: "fp32" | "bf16x3" | "fp16x3".
+    """
+
+    def __init__(self, dim, n, phase, params=(), q=8, amplitude=None,
+                 precision="fp32", max_nvec=1):
+        self._lib = _lib.load()
+        self._h = C.c_void_p()
+        grid = _lib.BfGrid(int(dim), int(n))
+        self._params = (C.c_double * max(1, len(params)))(*params)
+        ph = _lib.BfPhase(PHASES[phase], len(params), self._params)
+        amp = None
+        self.r = 1
+        if amplitude is not None:
+            a, b = amplitude
+            a = np.ascontiguousarray(a, dtype=np.complex128)
+            b = np.ascontiguousarray(b, dtype=np.complex128)
+            if a.shape != b.shape or a.ndim != 2:
+                raise ValueError("amplitude factors must both be [r][N]")
+            self.r = a.shape[0]
+            amp = _lib.BfAmplitude(
+                self.r, a.ctypes.data_as(C.POINTER(C.c_double)),
+                b.ctypes.data_as(C.POINTER(C.c_double)))
+        _lib.check(self._lib.bf_plan(
+            C.byref(grid), C.byref(ph), C.byref(amp) if amp else None,
+            int(q), PRECISIONS[precision], int(max_nvec), C.byref(self._h)))
+        self.dim, self.n, self.q = dim, n, q
+        self.N = n ** dim
+        self.max_nvec = max_nvec
+        self.precision = precision
+
+    def info(self):
+        inf = _lib.BfPlanInfo()
+        _lib.check(self._lib.bf_query(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def workspace_bytes(self, nvec):
+        v = C.c_size_t()
+        _lib.check(self._lib.bf_workspace_bytes(self._h, int(nvec),
+                                                C.byref(v)))
+        return v.value
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return C.c_void_p(s.cuda_stream)
+
+    def apply(self, f, out=None, stream=None, workspace=None):
+        """g = K f for a complex64 CUDA tensor f [nvec][N] (or [N]).
+        Asynchronous on ``stream`` (default: torch's current stream)."""
+        import torch
+        if not (f.is_cuda and f.dtype == torch.complex64):
+            raise TypeError("f must be a complex64 CUDA tensor")
+        squeeze = f.dim() == 1
+        f2 = f.reshape(1, -1) if squeeze else f
+        if f2.shape[-1] != self.N or not f2.is_contiguous():
+            raise ValueError("f must be contiguous with N entries per vector")
+        if out is None:
+            out = torch.empty_like(f2)
+        nvec = f2.shape[0]
+        st = self._stream(stream)
+        if workspace is None:
+            _lib.check(self._lib.bf_apply(self._h, nvec, C.c_void_p(
+                f2.data_ptr()), C.c_void_p(out.data_ptr()), st))
+        else:
+            _lib.check(self._lib.bf_apply_ws(
+                self._h, nvec, C.c_void_p(f2.data_ptr()),
+                C.c_void_p(out.data_ptr()), C.c_void_p(workspace.data_ptr()),
+                workspace.numel() * workspace.element_size(), st))
+        return out.reshape(-1) if squeeze else out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(self._lib.bf_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,91 @@
+"""ctypes declarations of libbf.so (include/bf.h).  Loading fails loudly when
+the library has not been built: there is no fallback path."""
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbf.so")
+
+BF_OK, BF_EINVAL, BF_ENOMEM, BF_EHIP, BF_EUNSUPPORTED, BF_EBUSY = (
+    0, -1, -2, -3, -4, -5)
+PHASES = {"dft": 0, "fio1d": 1, "radon2d": 2, "separable": 3}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+
+
+class BfGrid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int)]
+
+
+class BfPhase(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nparams", C.c_int),
+                ("params", C.POINTER(C.c_double))]
+
+
+class BfAmplitude(C.Structure):
+    _fields_ = [("r", C.c_int), ("a", C.POINTER(C.c_double)),
+                ("b", C.POINTER(C.c_double))]
+
+
+class BfPlanInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int), ("L", C.c_int),
+                ("h", C.c_int), ("q", C.c_int), ("r", C.c_int),
+                ("precision", C.c_int), ("N", C.c_longlong),
+                ("first_xi_level", C.c_int), ("last_x_level", C.c_int),
+                ("n_steps", C.c_int), ("n_passes", C.c_int),
+                ("max_rank", C.c_int), ("chunk_nvec", C.c_int),
+                ("factor_bytes", C.c_size_t),
+                ("workspace_bytes", C.c_size_t),
+                ("flops_per_column", C.c_double),
+                ("factor_stream_bytes", C.c_double)]
+
+
+EXPORTS = ["bf_plan", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
+           "bf_destroy", "bf_query", "bf_last_error", "bf_points",
+           "bf_lagrange"]
+
+_lib = None
+
+
+class BfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def load():
+    """Load libbf.so once; raise ImportError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_1803_04128_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.bf_plan.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude), C.c_int,
+                            C.c_int, C.c_int, P(C.c_void_p)]
+    lib.bf_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                             C.c_void_p]
+    lib.bf_workspace_bytes.argtypes = [C.c_void_p, C.c_int, P(C.c_size_t)]
+    lib.bf_apply_ws.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.bf_destroy.argtypes = [C.c_void_p]
+    lib.bf_query.argtypes = [C.c_void_p, P(BfPlanInfo)]
+    lib.bf_last_error.restype = C.c_char_p
+    lib.bf_last_error.argtypes = []
+    lib.bf_points.argtypes = [C.c_int, C.c_int, P(C.c_int), C.c_int,
+                              P(C.c_int)]
+    lib.bf_lagrange.argtypes = [P(C.c_int), C.c_int, P(C.c_double), C.c_int,
+                                P(C.c_double)]
+    for name in EXPORTS:
+        getattr(lib, name).restype = (C.c_char_p if name == "bf_last_error"
+                                      else C.c_int)
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != BF_OK:
+        raise BfError(rc, load().bf_last_error().decode())
+    return rc

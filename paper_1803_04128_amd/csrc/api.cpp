@@ -1,0 +1,258 @@
+// C ABI entry points (include/bf.h): argument checks, plan construction,
+// workspace, apply, query, destroy and error reporting.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bf_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t env_bytes(const char* name, size_t dflt) {
+    const char* s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    char* end = nullptr;
+    unsigned long long v = std::strtoull(s, &end, 10);
+    return end && *end == 0 ? (size_t)v : dflt;
+}
+
+constexpr size_t kGiB = 1ull << 30;
+
+}  // namespace
+
+struct bf_plan_s {
+    bfi::Plan p;
+    unsigned magic = 0xbf00bf00u;
+};
+
+extern "C" {
+
+const char* bf_last_error(void) { return g_last_error.c_str(); }
+
+int bf_points(int box_size, int q, int* out, int cap, int* count) {
+    if (box_size < 1 || q < 2 || q > bfi::kMaxQ || !out || !count)
+        return fail(BF_EINVAL, "bf_points: bad argument");
+    int tmp[bfi::kMaxQ];
+    int c = bfi::mock_chebyshev(box_size, q, tmp);
+    if (c > cap) return fail(BF_EINVAL, "bf_points: capacity too small");
+    std::memcpy(out, tmp, sizeof(int) * c);
+    *count = c;
+    return BF_OK;
+}
+
+int bf_lagrange(const int* nodes, int r, const double* y, int m,
+                double* out) {
+    if (!nodes || !y || !out || r < 1 || m < 0)
+        return fail(BF_EINVAL, "bf_lagrange: bad argument");
+    for (int i = 0; i < r; ++i)
+        for (int j = i + 1; j < r; ++j)
+            if (nodes[i] == nodes[j])
+                return fail(BF_EINVAL, "bf_lagrange: repeated node");
+    bfi::lagrange_1d(nodes, r, y, m, out);
+    return BF_OK;
+}
+
+int bf_plan(const bf_grid* grid, const bf_phase* phase,
+            const bf_amplitude* amp, int q, int precision, int max_nvec,
+            bf_plan_t* out) {
+    if (!out) return fail(BF_EINVAL, "bf_plan: out is NULL");
+    *out = nullptr;
+    if (!grid || !phase) return fail(BF_EINVAL, "bf_plan: NULL grid/phase");
+    const int dim = grid->dim, n = grid->n;
+    if (dim != 1 && dim != 2) return fail(BF_EINVAL, "bf_plan: dim must be 1 or 2");
+    if (!is_pow2(n) || n < 2 || (dim == 1 && n > (1 << 22)) ||
+        (dim == 2 && n > (1 << 11)))
+        return fail(BF_EINVAL, "bf_plan: n must be a power of two in range");
+    if (q < 2 || q > (dim == 1 ? bfi::kMaxQ : bfi::kMaxQ2D))
+        return fail(BF_EINVAL, "bf_plan: q out of range");
+    if (precision != BF_FP32 && precision != BF_BF16X3 &&
+        precision != BF_FP16X3)
+        return fail(BF_EINVAL, "bf_plan: unknown precision");
+    if (max_nvec < 1) return fail(BF_EINVAL, "bf_plan: max_nvec < 1");
+    int need = -1;
+    switch (phase->kind) {
+        case BF_PHASE_DFT: need = 0; break;
+        case BF_PHASE_FIO1D: need = dim == 1 ? 3 : -1; break;
+        case BF_PHASE_RADON2D: need = dim == 2 ? 6 : -1; break;
+        case BF_PHASE_SEPARABLE: need = 3; break;
+        default: return fail(BF_EINVAL, "bf_plan: unknown phase kind");
+    }
+    if (need < 0) return fail(BF_EINVAL, "bf_plan: phase kind needs another dim");
+    if (phase->nparams != need || (need > 0 && !phase->params))
+        return fail(BF_EINVAL, "bf_plan: wrong number of phase parameters");
+    int r = 1;
+    const double *a = nullptr, *b = nullptr;
+    if (amp) {
+        r = amp->r;
+        a = amp->a;
+        b = amp->b;
+        if (r < 1 || r > bfi::kMaxAmp)
+            return fail(BF_EINVAL, "bf_plan: amplitude rank out of range");
+        if ((a == nullptr) != (b == nullptr))
+            return fail(BF_EINVAL, "bf_plan: give both a and b or neither");
+        if (!a && r != 1)
+            return fail(BF_EINVAL, "bf_plan: alpha = 1 needs r = 1");
+    }
+
+    bf_plan_s* h = new (std::nothrow) bf_plan_s();
+    if (!h) return fail(BF_ENOMEM, "bf_plan: host allocation");
+    bfi::Plan& p = h->p;
+    p.dim = dim;
+    p.n = n;
+    p.q = q;
+    p.r_amp = r;
+    p.precision = precision;
+    p.max_nvec = max_nvec;
+    p.has_amp = a != nullptr;
+    p.phase.kind = phase->kind;
+    p.phase.dim = dim;
+    p.phase.n = n;
+    for (int i = 0; i < need; ++i) p.phase.p[i] = phase->params[i];
+    const char* fenv = std::getenv("BF_FUSED");
+    p.fused = fenv ? std::atoi(fenv) != 0 : false;
+    if (hipGetDevice(&p.device) != hipSuccess) {
+        delete h;
+        return fail(BF_EHIP, "bf_plan: no HIP device");
+    }
+    std::string err = bfi::build_schedule(p);
+    if (!err.empty()) {
+        delete h;
+        return fail(BF_EUNSUPPORTED, "bf_plan: " + err);
+    }
+    // memory: factors + workspace under the cap
+    const size_t cap = env_bytes("BF_MEM_CAP_BYTES", (size_t)-1);
+    const size_t ws_cap = env_bytes("BF_WS_CAP_BYTES", 16 * kGiB);
+    size_t per_vec = 2 * (size_t)p.N * p.max_rank * p.r_amp * 8;
+    int chunk = (int)std::max<size_t>(1, std::min<size_t>(max_nvec,
+                                                         ws_cap / per_vec));
+    p.chunk_nvec = chunk;
+    size_t factor_est = (size_t)p.factor_stream_bytes +
+                        (p.has_amp ? 2 * (size_t)r * p.N * 8 : 0);
+    if (factor_est + per_vec * chunk > cap) {
+        delete h;
+        return fail(BF_ENOMEM, "bf_plan: plan exceeds BF_MEM_CAP_BYTES");
+    }
+    err = bfi::build_factors(p);
+    if (err.empty() && p.has_amp) err = bfi::upload_amplitude(p, a, b);
+    if (err.empty()) {
+        p.ws_bytes = bfi::workspace_bytes(p, max_nvec);
+        if (hipMalloc(&p.ws, p.ws_bytes) != hipSuccess) {
+            p.ws = nullptr;
+            err = "workspace allocation failed";
+        }
+    }
+    if (!err.empty()) {
+        if (p.arena) (void)hipFree(p.arena);
+        if (p.ws) (void)hipFree(p.ws);
+        (void)hipGetLastError();
+        delete h;
+        return fail(err.find("alloc") != std::string::npos ||
+                            err.find("Malloc") != std::string::npos
+                        ? BF_ENOMEM
+                        : BF_EHIP,
+                    "bf_plan: " + err);
+    }
+    *out = h;
+    return BF_OK;
+}
+
+static int check_plan(bf_plan_t plan) {
+    if (!plan || plan->magic != 0xbf00bf00u)
+        return fail(BF_EINVAL, "invalid plan handle");
+    return BF_OK;
+}
+
+static int check_apply(bf_plan_t plan, int nvec, const void* f,
+                       const void* g) {
+    if (int e = check_plan(plan)) return e;
+    const bfi::Plan& p = plan->p;
+    if (nvec < 1 || nvec > p.max_nvec)
+        return fail(BF_EINVAL, "bf_apply: nvec outside [1, max_nvec]");
+    if (!f || !g) return fail(BF_EINVAL, "bf_apply: NULL f or g");
+    const size_t bytes = (size_t)nvec * p.N * 8;
+    const char* fb = (const char*)f;
+    const char* gb = (const char*)g;
+    if (fb < gb + bytes && gb < fb + bytes)
+        return fail(BF_EINVAL, "bf_apply: f and g overlap");
+    return BF_OK;
+}
+
+int bf_workspace_bytes(bf_plan_t plan, int nvec, size_t* bytes) {
+    if (int e = check_plan(plan)) return e;
+    if (!bytes || nvec < 1) return fail(BF_EINVAL, "bad argument");
+    *bytes = bfi::workspace_bytes(plan->p, nvec);
+    return BF_OK;
+}
+
+int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
+                size_t ws_bytes, void* stream) {
+    if (int e = check_apply(plan, nvec, f, g)) return e;
+    if (!ws) return fail(BF_EINVAL, "bf_apply_ws: NULL workspace");
+    bfi::Plan& p = plan->p;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+        return fail(BF_EINVAL, "bf_apply: plan belongs to another device");
+    std::string err = bfi::launch_apply(p, nvec, f, g, ws, ws_bytes,
+                                        (hipStream_t)stream);
+    if (!err.empty()) return fail(BF_EHIP, "bf_apply: " + err);
+    return BF_OK;
+}
+
+int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream) {
+    if (int e = check_plan(plan)) return e;
+    return bf_apply_ws(plan, nvec, f, g, plan->p.ws, plan->p.ws_bytes, stream);
+}
+
+int bf_destroy(bf_plan_t plan) {
+    if (!plan) return BF_OK;
+    if (int e = check_plan(plan)) return e;
+    bfi::Plan& p = plan->p;
+    int rc = BF_OK;
+    if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
+    if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
+    if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
+    plan->magic = 0;
+    delete plan;
+    if (rc != BF_OK) return fail(rc, "bf_destroy: HIP error while freeing");
+    return BF_OK;
+}
+
+int bf_query(bf_plan_t plan, bf_plan_info* info) {
+    if (int e = check_plan(plan)) return e;
+    if (!info) return fail(BF_EINVAL, "bf_query: NULL info");
+    const bfi::Plan& p = plan->p;
+    std::memset(info, 0, sizeof(*info));
+    info->dim = p.dim;
+    info->n = p.n;
+    info->L = p.L;
+    info->h = p.h;
+    info->q = p.q;
+    info->r = p.r_amp;
+    info->precision = p.precision;
+    info->N = p.N;
+    info->first_xi_level = p.l0;
+    info->last_x_level = p.l1;
+    info->n_steps = (int)p.steps.size();
+    info->n_passes = p.fused ? (int)p.passes.size() : (int)p.steps.size() + 1;
+    info->max_rank = p.max_rank;
+    info->chunk_nvec = p.chunk_nvec;
+    info->factor_bytes = p.arena_bytes;
+    info->workspace_bytes = p.ws_bytes;
+    info->flops_per_column = p.flops_per_column;
+    info->factor_stream_bytes = p.factor_stream_bytes;
+    return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Device-side helpers shared by the library's kernels: box and point index
+// math on the dyadic trees (Section 4), the phase functions in FP64, and
+// complex arithmetic.
+//
+// Box numbering: a box at tree level l is named by its per-dimension box
+// coordinates; in 2D these are interleaved into a Morton index (first
+// coordinate on the odd bits) so that the children of box m are R m + c,
+// c = c1 * 2 + c2.  Pairs at level l are stored at p = a * R^(L-l) + b.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bf_internal.h"
+
+namespace bfi {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__host__ __device__ __forceinline__ unsigned spread_bits(unsigned v) {
+    v &= 0x0000ffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__host__ __device__ __forceinline__ unsigned compact_bits(unsigned v) {
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0f0f0f0fu;
+    v = (v | (v >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0x0000ffffu;
+    return v;
+}
+
+// box index -> per-dimension box coordinates
+__device__ __forceinline__ void box_coords(long long m, int dim, int* c) {
+    if (dim == 1) {
+        c[0] = (int)m;
+    } else {
+        c[0] = (int)compact_bits((unsigned)(m >> 1));
+        c[1] = (int)compact_bits((unsigned)m);
+    }
+}
+
+__device__ __forceinline__ long long box_index(const int* c, int dim) {
+    if (dim == 1) return c[0];
+    return ((long long)spread_bits((unsigned)c[0]) << 1) |
+           (long long)spread_bits((unsigned)c[1]);
+}
+
+// digit d (0 = first dimension) of a flattened tensor point index
+__device__ __forceinline__ int point_digit(int t, int r1, int dim, int d) {
+    return dim == 1 ? t : (d == 0 ? t / r1 : t % r1);
+}
+
+// grid index of point t of the box with coordinates bc
+__device__ __forceinline__ void point_grid(const int* bc, const Axis& ax,
+                                           int t, int dim, int* g) {
+    for (int d = 0; d < dim; ++d)
+        g[d] = bc[d] * ax.side + ax.off[point_digit(t, ax.r1, dim, d)];
+}
+
+__device__ __forceinline__ void center_grid(const int* bc, int side, int dim,
+                                            int* g) {
+    for (int d = 0; d < dim; ++d) g[d] = bc[d] * side + (side - 1) / 2;
+}
+
+__device__ __forceinline__ long long user_index(const int* g, int dim,
+                                                int n) {
+    return dim == 1 ? (long long)g[0] : (long long)g[0] * n + g[1];
+}
+
+// Phase Phi(x_ix, xi_jx) in FP64.  The bilinear part x . xi =
+// sum_d ix_d (jx_d - n/2) / n is reduced modulo 1 exactly in integers; only
+// the fractional part of Phi is ever used.
+__device__ __forceinline__ double phase_value(const PhaseSpec& P,
+                                              const int* ix, const int* jx) {
+    const int n = P.n;
+    const double invn = 1.0 / (double)n;
+    double bil = 0.0;
+    if (P.kind != BF_PHASE_SEPARABLE) {
+        long long acc = 0;
+        for (int d = 0; d < P.dim; ++d)
+            acc = (acc + (long long)ix[d] * (long long)(jx[d] - n / 2)) % n;
+        if (acc < 0) acc += n;
+        bil = (double)acc * invn;
+    }
+    switch (P.kind) {
+        case BF_PHASE_DFT:
+            return bil;
+        case BF_PHASE_FIO1D: {
+            double c = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
+            return bil + c * fabs((double)(jx[0] - n / 2));
+        }
+        case BF_PHASE_RADON2D: {
+            double u = 2.0 * ix[0] * invn, v = 2.0 * ix[1] * invn;
+            double c1 = (P.p[0] + P.p[1] * sinpi(u) * sinpi(v)) / P.p[2];
+            double c2 = (P.p[3] + P.p[4] * cospi(u) * cospi(v)) / P.p[5];
+            double x1 = (double)(jx[0] - n / 2), x2 = (double)(jx[1] - n / 2);
+            return bil + sqrt(c1 * c1 * x1 * x1 + c2 * c2 * x2 * x2);
+        }
+        default: {  // BF_PHASE_SEPARABLE
+            double x2 = P.dim > 1 ? ix[1] * invn : 0.0;
+            double px = P.p[0] * sinpi(2.0 * ix[0] * invn) * (1.0 + x2);
+            double nrm2 = 0.0;
+            for (int d = 0; d < P.dim; ++d) {
+                double x = (double)(jx[d] - n / 2);
+                nrm2 += x * x;
+            }
+            return px + P.p[1] * sqrt(nrm2) + P.p[2] * nrm2 * invn;
+        }
+    }
+}
+
+// exp(2 pi i v) with v reduced to [-1/2, 1/2] first (FP64), stored FP32
+__device__ __forceinline__ float2 expi_frac(double v) {
+    double t = v - rint(v);
+    double s, c;
+    sincospi(2.0 * t, &s, &c);
+    return make_float2((float)c, (float)s);
+}
+
+}  // namespace bfi

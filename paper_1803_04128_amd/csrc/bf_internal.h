@@ -1,0 +1,136 @@
+// Internal plan structures of the butterfly library (host side).
+//
+// Notation follows Section 4 of the paper: trees T_X and T_Omega of depth L
+// over an n^dim grid, tree level l, pairs (A, B) with A at level l of T_X and
+// B at level L - l of T_Omega, switch level h = floor(L / 2).  R = 2^dim is
+// the number of children of a box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bf.h"
+
+namespace bfi {
+
+constexpr int kMaxQ = 16;       // interpolation points per dimension (1D)
+constexpr int kMaxQ2D = 8;      // per dimension in 2D
+constexpr int kMaxRank = 64;    // coefficients per pair (8 x 8 in 2D)
+constexpr int kMaxAmp = 16;     // amplitude rank
+
+// Interpolation points of a box side, per dimension: `r1` 0-based offsets
+// inside a side of `side` indices.  A box's points are the tensor product of
+// these offsets over the dimensions, flattened row-major (t1 * r1 + t2).
+struct Axis {
+    int side;
+    int r1;
+    int off[kMaxQ];
+};
+
+enum StepKind { STEP_XI = 0, STEP_SWITCH = 1, STEP_X = 2 };
+
+// One computed step of the regrouped Algorithm 4.1.
+//
+// STEP_XI (recursion in xi, eq. (eqn:2)) at level l: a unit (a', b), with a'
+//   at level l-1 of T_X and b at level L-l of T_Omega, reads the R input
+//   pairs (a', R b + c) and writes the R output pairs (R a' + i, b):
+//     mu^{AB} = sum_c M_c (W_{A,C} . mu^{PC}),
+//   M_c[t][s] = M_t^B(xi_s^C) (real, shared by all units), W the twiddle
+//   exp(2 pi i [Phi(c_A, xi_s^C) - Phi(c_P, xi_s^C)]).  When the step reads
+//   f directly (the exact levels below it are copies), W is
+//   exp(2 pi i Phi(c_A, xi_s^C)).
+// STEP_SWITCH at level h: per pair, nu^{AB} = S_{AB} mu^{AB}, S the residual
+//   phase block exp(2 pi i [Phi(x_t^A, xi_s^B) - Phi(c_A, xi_s^B)
+//   - Phi(x_t^A, c_B)]); the second term is absent when the switch reads f,
+//   the third when no x step follows.
+// STEP_X (recursion in x, eq. (eqn:3)) at level l: same unit shape,
+//     nu^{AB} = sum_c T_{A,C} . (M_i nu^{PC}),
+//   M_i[t][s] = M_s^P(x_t^A) for A the i-th child of P, T the twiddle
+//   exp(2 pi i [Phi(x_t^A, c_C) - Phi(x_t^A, c_B)]); the last x step uses
+//   exp(2 pi i Phi(x_t^A, c_C)) and so emits lambda for the final sums.
+struct Step {
+    int kind = 0;
+    int level = 0;
+    int r_in = 0, r_out = 0;
+    bool reads_f = false;
+    bool writes_lambda = false;
+    Axis ax_in{}, ax_out{};
+    long long units = 0;        // N / R for XI and X, N for the switch
+    // device factors (inside the plan arena)
+    float2* tw = nullptr;       // [units][R][R][r] (r = r_in for XI, r_out X)
+    float* mats = nullptr;      // [R][r_out][r_in]
+    float2* S = nullptr;        // [N][r_out][r_in]
+    // split-precision copies of mats: hi and lo parts, 16-bit each
+    uint16_t* mats_hi = nullptr;
+    uint16_t* mats_lo = nullptr;
+    size_t tw_elems = 0, mat_elems = 0, S_elems = 0;
+    std::vector<double> mats_host;  // FP64 Lagrange matrices
+};
+
+struct PhaseSpec {
+    int kind;
+    int dim;
+    int n;
+    double p[6];
+};
+
+// A fused kernel pass: consecutive steps [first, last] executed by one
+// launch per vector chunk.
+struct Pass {
+    int first, last;
+    bool tail;        // ends with the final sums and the amplitude
+    int group_log;    // log_R of pairs per group
+};
+
+struct Plan {
+    int dim = 1, n = 0, L = 0, h = 0, R = 2, q = 0, r_amp = 1;
+    int precision = BF_FP32, max_nvec = 1;
+    long long N = 0;
+    PhaseSpec phase{};
+    int l0 = 0, l1 = 0, lend = 0;
+    int head_step_side = 1;   // side of the boxes the first step reads f over
+    int tail_side = 1;        // side of the T_X boxes summed in the tail
+    std::vector<Step> steps;
+    std::vector<Pass> passes;
+    int max_rank = 1;
+    // device memory
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    bool has_amp = false;     // false: alpha = 1 (r = 1)
+    float2* a_dev = nullptr;  // [r][N] complex64, nullptr when alpha = 1
+    float2* b_dev = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int chunk_nvec = 1;
+    int device = 0;
+    bool fused = true;        // level-fused passes (else one launch per step)
+    double flops_per_column = 0;
+    double factor_stream_bytes = 0;
+};
+
+// geometry.cpp
+int mock_chebyshev(int side, int q, int* off);
+void lagrange_1d(const int* nodes, int r, const double* y, int m, double* out);
+Axis make_axis(int side, int q);
+std::string build_schedule(Plan& p);   // "" on success, else a message
+
+// factors.hip
+std::string build_factors(Plan& p);
+std::string upload_amplitude(Plan& p, const double* a, const double* b);
+// apply.hip
+std::string launch_apply(Plan& p, int nvec, const void* f, void* g, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+size_t workspace_bytes(const Plan& p, int nvec);
+
+// tiny helpers
+inline int ilog2(long long v) {
+    int l = 0;
+    while ((1LL << (l + 1)) <= v) ++l;
+    return l;
+}
+
+}  // namespace bfi

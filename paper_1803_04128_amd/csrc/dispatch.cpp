@@ -1,0 +1,45 @@
+// Apply dispatch: vector chunking over the workspace and the choice between
+// the per-step launches and the level-fused passes.
+#include <algorithm>
+
+#include "apply_common.h"
+
+namespace bfi {
+
+std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
+                      float2* buf0, float2* buf1, hipStream_t st);
+
+// Two ping-pong state buffers of N * max_rank * (nv * r) complex64 each.
+static size_t state_bytes(const Plan& p, int nv) {
+    return (size_t)p.N * p.max_rank * (size_t)nv * p.r_amp * sizeof(float2);
+}
+
+size_t workspace_bytes(const Plan& p, int nvec) {
+    const int nv = std::min(nvec, p.chunk_nvec);
+    return 2 * state_bytes(p, nv);
+}
+
+std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
+                         void* ws, size_t ws_bytes, hipStream_t st) {
+    // vectors per chunk: as many as the workspace holds, at most chunk_nvec
+    int chunk = std::min(nvec, p.chunk_nvec);
+    while (chunk > 1 && 2 * state_bytes(p, chunk) > ws_bytes) --chunk;
+    if (2 * state_bytes(p, chunk) > ws_bytes)
+        return "workspace too small for one vector";
+    const float2* f = (const float2*)fv;
+    float2* g = (float2*)gv;
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+        const int nv = std::min(chunk, nvec - v0);
+        float2* b0 = (float2*)ws;
+        float2* b1 = (float2*)((char*)ws + state_bytes(p, nv));
+        std::string err =
+            p.fused ? run_fused(p, nv, f + (size_t)v0 * p.N,
+                                g + (size_t)v0 * p.N, b0, b1, st)
+                    : run_basic(p, nv, f + (size_t)v0 * p.N,
+                                g + (size_t)v0 * p.N, b0, b1, st);
+        if (!err.empty()) return err;
+    }
+    return "";
+}
+
+}  // namespace bfi

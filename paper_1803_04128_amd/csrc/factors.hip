@@ -1,0 +1,272 @@
+// Factor construction on the device, FP64 phase arithmetic.
+//
+// Kernel entries at interpolation points (Algorithm 2; Algorithm 4.1, eqs.
+// (eqn:1), (eqn:2), the switch step and eq. (eqn:3)) regrouped so that each
+// level stores unit-modulus diagonals (twiddles) and one real Lagrange
+// matrix per child position:
+//   xi level l:  W_{A,C}[s] = exp(2 pi i [Phi(c_A, xi_s^C) - Phi(c_P, xi_s^C)])
+//   switch:      S_{AB}[t][s] = exp(2 pi i [Phi(x_t^A, xi_s^B)
+//                               - Phi(c_A, xi_s^B) - Phi(x_t^A, c_B)])
+//   x level l:   T_{A,C}[t] = exp(2 pi i [Phi(x_t^A, c_C) - Phi(x_t^A, c_B)])
+// Each phase is evaluated in FP64, the difference is reduced modulo 1 and
+// only then passed to sincospi; the result is stored as FP32 complex.
+#include <cstring>
+#include <vector>
+
+#include <hip/hip_fp16.h>
+
+#include "bf_device.h"
+
+namespace bfi {
+
+struct TwArgs {
+    PhaseSpec P;
+    Axis ax_in, ax_out;
+    int L, level, reads_f, writes_lambda;
+    long long total;
+    float2* out;
+};
+
+constexpr int kFactorBlock = 256;
+
+// W (or D+ when the step reads f): [u][i][c][s]
+__global__ void xi_twiddles(TwArgs a) {
+    const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
+    const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
+    const int shiftB = dim * (a.L - a.level);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
+        int s = (int)(idx % r_in);
+        long long rest = idx / r_in;
+        int c = (int)(rest % R);
+        rest /= R;
+        int i = (int)(rest % R);
+        long long u = rest / R;
+        long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+        int Ac[2], Pc[2], Cc[2], xi[2], cA[2], cP[2];
+        box_coords(ap * R + i, dim, Ac);
+        box_coords(ap, dim, Pc);
+        box_coords(b * R + c, dim, Cc);
+        point_grid(Cc, a.ax_in, s, dim, xi);
+        center_grid(Ac, n >> a.level, dim, cA);
+        center_grid(Pc, n >> (a.level - 1), dim, cP);
+        double v = phase_value(a.P, cA, xi);
+        if (!a.reads_f) v -= phase_value(a.P, cP, xi);
+        a.out[idx] = expi_frac(v);
+    }
+}
+
+// T (or E+ on the last x step): [u][i][c][t]
+__global__ void x_twiddles(TwArgs a) {
+    const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
+    const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
+    const int shiftB = dim * (a.L - a.level);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
+        int t = (int)(idx % r_out);
+        long long rest = idx / r_out;
+        int c = (int)(rest % R);
+        rest /= R;
+        int i = (int)(rest % R);
+        long long u = rest / R;
+        long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+        int Ac[2], Bc[2], Cc[2], x[2], cB[2], cC[2];
+        box_coords(ap * R + i, dim, Ac);
+        box_coords(b, dim, Bc);
+        box_coords(b * R + c, dim, Cc);
+        point_grid(Ac, a.ax_out, t, dim, x);
+        center_grid(Cc, n >> (a.L - a.level + 1), dim, cC);
+        center_grid(Bc, n >> (a.L - a.level), dim, cB);
+        double v = phase_value(a.P, x, cC);
+        if (!a.writes_lambda) v -= phase_value(a.P, x, cB);
+        a.out[idx] = expi_frac(v);
+    }
+}
+
+// S: [p][t][s]
+__global__ void switch_blocks(TwArgs a) {
+    const int dim = a.P.dim, n = a.P.n;
+    const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
+    const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
+    const int shiftB = dim * (a.L - a.level);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
+        int s = (int)(idx % r_in);
+        long long rest = idx / r_in;
+        int t = (int)(rest % r_out);
+        long long p = rest / r_out;
+        long long am = p >> shiftB, bm = p & ((1LL << shiftB) - 1);
+        int Ac[2], Bc[2], x[2], xi[2], cA[2], cB[2];
+        box_coords(am, dim, Ac);
+        box_coords(bm, dim, Bc);
+        point_grid(Ac, a.ax_out, t, dim, x);
+        point_grid(Bc, a.ax_in, s, dim, xi);
+        center_grid(Ac, n >> a.level, dim, cA);
+        center_grid(Bc, n >> (a.L - a.level), dim, cB);
+        double v = phase_value(a.P, x, xi);
+        if (!a.reads_f) v -= phase_value(a.P, cA, xi);
+        if (!a.writes_lambda) v -= phase_value(a.P, x, cB);
+        a.out[idx] = expi_frac(v);
+    }
+}
+
+// complex128 host amplitude factors -> complex64 device
+__global__ void narrow_complex(const double2* in, float2* out, long long m) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         i < m; i += (long long)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// 16-bit hi/lo split of the FP32 Lagrange matrices (bfloat16 or half).
+__global__ void split_matrices(const float* m, uint16_t* hi, uint16_t* lo,
+                               long long count, int use_half) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         i < count; i += (long long)gridDim.x * blockDim.x) {
+        float v = m[i];
+        if (use_half) {
+            __half h = __float2half_rn(v);
+            float r = v - __half2float(h);
+            __half l = __float2half_rn(r);
+            hi[i] = __half_as_ushort(h);
+            lo[i] = __half_as_ushort(l);
+        } else {
+            // round-to-nearest-even bfloat16
+            unsigned u = __float_as_uint(v);
+            unsigned rh = u + 0x7fffu + ((u >> 16) & 1u);
+            unsigned hb = rh & 0xffff0000u;
+            float r = v - __uint_as_float(hb);
+            unsigned ul = __float_as_uint(r);
+            unsigned rl = ul + 0x7fffu + ((ul >> 16) & 1u);
+            hi[i] = (uint16_t)(hb >> 16);
+            lo[i] = (uint16_t)(rl >> 16);
+        }
+    }
+}
+
+static int grid_for(long long total) {
+    long long g = (total + kFactorBlock - 1) / kFactorBlock;
+    return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+#define HIPCHK(x)                                                       \
+    do {                                                                \
+        hipError_t e_ = (x);                                            \
+        if (e_ != hipSuccess)                                           \
+            return std::string(#x ": ") + hipGetErrorString(e_);        \
+    } while (0)
+
+std::string build_factors(Plan& p) {
+    // arena layout
+    size_t bytes = 0;
+    const bool split = p.precision != BF_FP32;
+    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo;
+    for (auto& s : p.steps) {
+        off_tw.push_back(bytes);
+        bytes = align_up(bytes + s.tw_elems * sizeof(float2));
+        off_S.push_back(bytes);
+        bytes = align_up(bytes + s.S_elems * sizeof(float2));
+        off_m.push_back(bytes);
+        bytes = align_up(bytes + s.mat_elems * sizeof(float));
+        off_hi.push_back(bytes);
+        if (split) bytes = align_up(bytes + s.mat_elems * 2);
+        off_lo.push_back(bytes);
+        if (split) bytes = align_up(bytes + s.mat_elems * 2);
+    }
+    size_t off_a = bytes;
+    const bool has_amp = p.has_amp;
+    if (has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
+    size_t off_b = bytes;
+    if (has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
+    p.arena_bytes = bytes;
+    HIPCHK(hipMalloc(&p.arena, bytes > 0 ? bytes : 256));
+    char* base = (char*)p.arena;
+
+    TwArgs t{};
+    t.P = p.phase;
+    t.L = p.L;
+    for (size_t k = 0; k < p.steps.size(); ++k) {
+        Step& s = p.steps[k];
+        s.tw = s.tw_elems ? (float2*)(base + off_tw[k]) : nullptr;
+        s.S = s.S_elems ? (float2*)(base + off_S[k]) : nullptr;
+        s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
+        if (split && s.mat_elems) {
+            s.mats_hi = (uint16_t*)(base + off_hi[k]);
+            s.mats_lo = (uint16_t*)(base + off_lo[k]);
+        }
+        t.ax_in = s.ax_in;
+        t.ax_out = s.ax_out;
+        t.level = s.level;
+        t.reads_f = s.reads_f;
+        t.writes_lambda = s.writes_lambda;
+        if (s.kind == STEP_XI) {
+            t.total = (long long)s.tw_elems;
+            t.out = s.tw;
+            hipLaunchKernelGGL(xi_twiddles, dim3(grid_for(t.total)),
+                               dim3(kFactorBlock), 0, 0, t);
+        } else if (s.kind == STEP_X) {
+            t.total = (long long)s.tw_elems;
+            t.out = s.tw;
+            hipLaunchKernelGGL(x_twiddles, dim3(grid_for(t.total)),
+                               dim3(kFactorBlock), 0, 0, t);
+        } else {
+            t.total = (long long)s.S_elems;
+            t.out = s.S;
+            hipLaunchKernelGGL(switch_blocks, dim3(grid_for(t.total)),
+                               dim3(kFactorBlock), 0, 0, t);
+        }
+        HIPCHK(hipGetLastError());
+        if (s.mat_elems) {
+            std::vector<float> mf(s.mat_elems);
+            for (size_t e = 0; e < s.mat_elems; ++e)
+                mf[e] = (float)s.mats_host[e];
+            HIPCHK(hipMemcpy(s.mats, mf.data(), s.mat_elems * sizeof(float),
+                             hipMemcpyHostToDevice));
+            if (split) {
+                hipLaunchKernelGGL(split_matrices,
+                                   dim3(grid_for((long long)s.mat_elems)),
+                                   dim3(kFactorBlock), 0, 0, s.mats,
+                                   s.mats_hi, s.mats_lo,
+                                   (long long)s.mat_elems,
+                                   p.precision == BF_FP16X3 ? 1 : 0);
+                HIPCHK(hipGetLastError());
+            }
+        }
+    }
+    HIPCHK(hipDeviceSynchronize());
+    if (has_amp) {
+        p.a_dev = (float2*)(base + off_a);
+        p.b_dev = (float2*)(base + off_b);
+    }
+    return "";
+}
+
+// Upload and narrow the amplitude factors (host complex128 [r][N]).
+std::string upload_amplitude(Plan& p, const double* a, const double* b) {
+    const long long m = (long long)p.r_amp * p.N;
+    void* tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, (size_t)m * sizeof(double2)));
+    const double* src[2] = {a, b};
+    float2* dst[2] = {p.a_dev, p.b_dev};
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipMemcpy(tmp, src[k], (size_t)m * sizeof(double2),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return std::string("hipMemcpy amplitude: ") + hipGetErrorString(e);
+        }
+        hipLaunchKernelGGL(narrow_complex, dim3(grid_for(m)),
+                           dim3(kFactorBlock), 0, 0, (const double2*)tmp,
+                           dst[k], m);
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return std::string("narrow amplitude: ") + hipGetErrorString(e);
+        }
+    }
+    HIPCHK(hipFree(tmp));
+    return "";
+}
+
+}  // namespace bfi

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP apply (through the C ABI) against the FP64 oracle.
+
+Bars (FP32 apply): relative l2 <= 1e-5 per vector against the oracle's
+step-by-step butterfly on the same points (the same factorization), and
+<= eps_BF + 1e-5 against the dense matvec, eps_BF being the oracle
+butterfly's own error on the same rows.  Exact cases (small grids, separable
+phases) must match the dense matvec to <= 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+from _util import inputs, gpu_apply, rel, log
+from oracle.butterfly import butterfly_apply, butterfly_matvec
+from oracle.dense import dense_rows
+from synthetic import sample_rows, PHASE_PARAMS, CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _plan(dim, n, kind, q, ab=None, nvec=1, precision="fp32", phase=None):
+    import paper_1803_04128_amd as bfm
+    params = PHASE_PARAMS[phase or kind]
+    return bfm.Plan(dim, n, kind, params, q=q, amplitude=ab,
+                    precision=precision, max_nvec=nvec)
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("kind", ["fio1d", "dft", "separable"])
+def test_exact_small_1d(n, kind):
+    log(f"case exact_small_1d n={n} kind={kind}")
+    f32, f, _ = inputs(1, n, 3, 100 + n)
+    with _plan(1, n, kind, 8, nvec=3) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = dense_rows(1, n, kind, PHASE_PARAMS[kind], "one", f, np.arange(n))
+    assert np.max(rel(g, ref)) < TOL
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+@pytest.mark.parametrize("kind", ["radon2d", "dft"])
+def test_exact_small_2d(n, kind):
+    log(f"case exact_small_2d n={n} kind={kind}")
+    f32, f, _ = inputs(2, n, 2, 200 + n)
+    with _plan(2, n, kind, 7, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = dense_rows(2, n, kind, PHASE_PARAMS[kind], "one", f,
+                     np.arange(n * n))
+    assert np.max(rel(g, ref)) < TOL
+
+
+@pytest.mark.parametrize("n,q", [(1024, 6), (1024, 8), (2048, 8), (4096, 10),
+                                 (8192, 12), (512, 16), (16384, 8)])
+@pytest.mark.parametrize("kind", ["fio1d", "dft"])
+def test_parity_vs_oracle_butterfly_1d(n, q, kind):
+    log(f"case parity_1d n={n} q={q} kind={kind}")
+    f32, f, _ = inputs(1, n, 2, 300 + q)
+    with _plan(1, n, kind, q, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_apply(1, n, kind, PHASE_PARAMS[kind], q, f)
+    assert np.max(rel(g, ref)) < TOL
+
+
+@pytest.mark.parametrize("n,q,r", [(1024, 8, 2), (4096, 10, 4), (2048, 6, 3)])
+def test_parity_amplitude_1d(n, q, r):
+    log(f"case parity_amp_1d n={n} q={q} r={r}")
+    f32, f, ab = inputs(1, n, 3, 400 + r, amp="sincos", r=r)
+    with _plan(1, n, "fio1d", q, ab=ab, nvec=3) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_matvec(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, ab[0],
+                           ab[1], f)
+    assert np.max(rel(g, ref)) < TOL
+
+
+@pytest.mark.parametrize("n,q", [(32, 7), (64, 7), (128, 5), (64, 4),
+                                 (128, 7)])
+def test_parity_vs_oracle_butterfly_2d(n, q):
+    log(f"case parity_2d n={n} q={q}")
+    f32, f, _ = inputs(2, n, 2, 500 + n)
+    with _plan(2, n, "radon2d", q, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_apply(2, n, "radon2d", PHASE_PARAMS["radon2d"], q, f)
+    assert np.max(rel(g, ref)) < TOL
+
+
+def test_parity_amplitude_2d():
+    log("case parity_amp_2d")
+    n, q = 64, 7
+    f32, f, ab = inputs(2, n, 2, 600, amp="sincos", r=2)
+    with _plan(2, n, "radon2d", q, ab=ab, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_matvec(2, n, "radon2d", PHASE_PARAMS["radon2d"], q,
+                           ab[0], ab[1], f)
+    assert np.max(rel(g, ref)) < TOL
+
+
+@pytest.mark.parametrize("dim,n,q", [(1, 1 << 18, 10), (1, 1 << 20, 8),
+                                     (2, 256, 7), (2, 512, 7)])
+def test_separable_phase_exact_at_full_size(dim, n, q):
+    # exact factorization at any size: compare with the dense matvec on
+    # sampled rows (every level's twiddles and index math at full size)
+    log(f"case separable_full dim={dim} n={n} q={q}")
+    N = n ** dim
+    f32, f, _ = inputs(dim, n, 2, 700 + dim)
+    with _plan(dim, n, "separable", q, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    rows = sample_rows(N, 256, 701)
+    ref = dense_rows(dim, n, "separable", PHASE_PARAMS["separable"], "one", f,
+                     rows)
+    assert np.max(rel(g[:, rows], ref)) < TOL
+
+
+def test_dft_against_fft_full_size():
+    n, q = 1 << 16, 10
+    log(f"case dft_fft n={n} q={q}")
+    f32, f, _ = inputs(1, n, 1, 800)
+    with _plan(1, n, "dft", q) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = ((-1.0) ** np.arange(n)) * n * np.fft.ifft(f, axis=-1)
+    rows = sample_rows(n, 256, 801)
+    e_bf = rel(butterfly_apply(1, 4096, "dft", (), q, f[:, :4096]),
+               ((-1.0) ** np.arange(4096)) * 4096 *
+               np.fft.ifft(f[:, :4096], axis=-1))[0]
+    assert rel(g, ref)[0] < max(10 * e_bf, 1e-6) + TOL
+
+
+def test_config_fio1d_n1024():
+    w = CONFIGS["fio1d_n1024"]
+    log(f"case config {w.name}")
+    f32, f, _ = inputs(w.dim, w.n, w.nvec, w.seed)
+    with _plan(w.dim, w.n, w.phase_kind, w.q, nvec=w.nvec,
+               phase=w.phase) as pl:
+        g, _ = gpu_apply(pl, f32)
+    rows = np.arange(w.N)
+    dense = dense_rows(w.dim, w.n, w.phase_kind, w.phase_params, "one", f,
+                       rows)
+    bf = butterfly_apply(w.dim, w.n, w.phase_kind, w.phase_params, w.q, f)
+    eps_bf = np.max(rel(bf, dense))
+    log(f"  eps_BF={eps_bf:.3e} gpu-vs-bf={np.max(rel(g, bf)):.3e} "
+        f"gpu-vs-dense={np.max(rel(g, dense)):.3e}")
+    assert np.max(rel(g, bf)) < TOL
+    assert np.max(rel(g, dense)) < eps_bf + TOL
+
+
+def test_batch_invariance_and_chunking(monkeypatch):
+    # each column of a batched apply equals the vector applied alone (same
+    # kernels, so bitwise), and a workspace cap that forces ragged vector
+    # chunks changes nothing
+    import paper_1803_04128_amd as bfm
+    n, q, nvec = 4096, 10, 7
+    log("case batch_invariance")
+    f32, f, ab = inputs(1, n, nvec, 900, amp="sincos", r=4)
+    with _plan(1, n, "fio1d", q, ab=ab, nvec=nvec) as pl:
+        g_all, _ = gpu_apply(pl, f32)
+        singles = [gpu_apply(pl, f32[v:v + 1])[0] for v in range(nvec)]
+    for v in range(nvec):
+        assert np.array_equal(g_all[v], singles[v][0])
+    per_vec = 2 * n * 10 * 4 * 8
+    monkeypatch.setenv("BF_WS_CAP_BYTES", str(3 * per_vec))
+    with _plan(1, n, "fio1d", q, ab=ab, nvec=nvec) as pl:
+        assert pl.info()["chunk_nvec"] == 3
+        g_chunk, _ = gpu_apply(pl, f32)
+    assert np.array_equal(g_all, g_chunk)
+
+
+def test_apply_rejects_overlap_and_bad_nvec():
+    import torch
+    import paper_1803_04128_amd as bfm
+    log("case apply_errors")
+    with _plan(1, 1024, "fio1d", 8, nvec=2) as pl:
+        f = torch.zeros((2, 1024), dtype=torch.complex64, device="cuda")
+        with pytest.raises(bfm.BfError) as e:
+            pl.apply(f, out=f)
+        assert e.value.code == -1
+        with pytest.raises(bfm.BfError):
+            pl.apply(torch.zeros((3, 1024), dtype=torch.complex64,
+                                 device="cuda"))

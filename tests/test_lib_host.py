@@ -1,0 +1,104 @@
+"""Host-side checks of libbf.so that need no GPU: the library loads, exports
+every symbol include/bf.h declares, its plan geometry matches the oracle's
+(independently written) geometry, and argument errors are reported through
+status codes."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1803_04128_amd as bfm
+from paper_1803_04128_amd import _lib
+from oracle.butterfly import mock_chebyshev, lagrange_1d
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(
+    os.path.abspath(__file__))), "include", "bf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(bf_\w+)\s*\(",
+                                 src, re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert "bf_plan" in names and "bf_apply" in names and len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+@pytest.mark.parametrize("q", range(2, 17))
+def test_points_match_oracle(q):
+    for L in range(0, 23):
+        size = 1 << L
+        assert np.array_equal(bfm.points(size, q), mock_chebyshev(size, q)), \
+            (size, q)
+
+
+@pytest.mark.parametrize("size,q", [(16, 8), (1024, 10), (64, 7), (8, 5)])
+def test_lagrange_matches_oracle(size, q):
+    nodes = mock_chebyshev(size, q)
+    y = np.arange(-3, 2 * size + 3, dtype=float)
+    ours = bfm.lagrange(nodes, y)
+    ref = lagrange_1d(nodes, y)
+    assert np.allclose(ours, ref, rtol=1e-13, atol=1e-13)
+
+
+def _plan_rc(dim=1, n=64, kind=1, params=(2.0, 1.0, 8.0), q=8, prec=0,
+             max_nvec=1, amp=None):
+    lib = _lib.load()
+    g = _lib.BfGrid(dim, n)
+    arr = (C.c_double * max(1, len(params)))(*params)
+    ph = _lib.BfPhase(kind, len(params), arr)
+    h = C.c_void_p()
+    rc = lib.bf_plan(C.byref(g), C.byref(ph), C.byref(amp) if amp else None,
+                     q, prec, max_nvec, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=3), dict(n=100), dict(n=1), dict(q=1), dict(q=17),
+    dict(dim=2, n=16, kind=2, params=(2, 1, 16, 2, 1, 16), q=9),
+    dict(prec=7), dict(max_nvec=0), dict(kind=9), dict(params=(1.0,)),
+    dict(kind=2, params=(2, 1, 16, 2, 1, 16)),   # radon phase needs 2D
+])
+def test_plan_rejects_bad_arguments(kw):
+    rc, h = _plan_rc(**kw)
+    assert rc == _lib.BF_EINVAL
+    assert not h.value
+    assert len(_lib.load().bf_last_error()) > 0
+
+
+def test_amplitude_arguments_checked():
+    a = np.ones(2 * 64, np.float64)
+    amp = _lib.BfAmplitude(2, None, None)          # alpha = 1 needs r = 1
+    rc, _ = _plan_rc(amp=amp)
+    assert rc == _lib.BF_EINVAL
+    amp = _lib.BfAmplitude(1, a.ctypes.data_as(C.POINTER(C.c_double)), None)
+    rc, _ = _plan_rc(amp=amp)
+    assert rc == _lib.BF_EINVAL
+
+
+def test_null_handles():
+    lib = _lib.load()
+    assert lib.bf_destroy(None) == _lib.BF_OK
+    assert lib.bf_apply(None, 1, None, None, None) == _lib.BF_EINVAL
+    info = _lib.BfPlanInfo()
+    assert lib.bf_query(None, C.byref(info)) == _lib.BF_EINVAL
+    sz = C.c_size_t()
+    assert lib.bf_workspace_bytes(None, 1, C.byref(sz)) == _lib.BF_EINVAL
+
+
+def test_no_device_is_an_error_not_a_crash():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h = _plan_rc()
+    assert rc in (_lib.BF_EHIP, _lib.BF_ENOMEM)
+    assert not h.value
