@@ -61,6 +61,13 @@ def load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
             "`python -m paper_1803_04128_amd.build` (hipcc, gfx950)")
+    # PyTorch ships its own HIP runtime (same soname as the system one).
+    # Import it first so libbf.so binds to that runtime: two HIP runtimes in
+    # one process do not share devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER
     lib.bf_plan.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude), C.c_int,
