@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Throughput of g = K f applies on one MI355X.
+
+Workload (default): the 1D FIO batched case, N = 2^18, Phi = x xi + c(x)|xi|
+with c(x) = (2 + sin 2 pi x)/8, amplitude alpha = 1 + 0.5 sin(2 pi x)
+cos(2 pi xi / N) as r = 4 separable terms, q = 10 interpolation points, 64
+complex64 Gaussian vectors applied in one call.  A step is one bf_apply of
+all 64 vectors with the inputs resident in HBM.
+
+Prints one JSON line: N*nvec/s over the timed steps, p50/p99 per-apply
+latency, the roofline of the dominant kernel (library-side HIP events over
+the timed region), and the oracle timed on the host on a bounded sample
+(its result also gives the error of the GPU apply on that sample).
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector / matrix (published)
+BF16_PEAK_TFLOPS = 2500.0      # dense MFMA bf16 / fp16
+
+WORKLOADS = {
+    "fio1d_n262144_batched": dict(precision="fp32"),
+    "fio1d_n1024": dict(precision="fp32"),
+    "radon2d_n256": dict(precision="fp32"),
+    "fio1d_n1048576_sweep": dict(precision="fp32"),
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_04128_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload, precision, kernel):
+    """HBM bytes per launch measured with rocprofv3 counters, if recorded for
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    key = f"{workload}/{precision}/{kernel}"
+    ent = rec.get(key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, f64, ab, g_gpu):
+    """The oracle's FP64 butterfly on the first vector (all r amplitude
+    columns) of the workload, timed on the host; returns (report, rel err of
+    the GPU result for that vector)."""
+    import numpy as np
+    from oracle.butterfly import butterfly_apply, butterfly_matvec
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] +
+                    [1])
+    except Exception:
+        cores = 1
+    t0 = time.perf_counter()
+    if ab is None:
+        ref = butterfly_apply(w.dim, w.n, w.phase_kind, w.phase_params, w.q,
+                              f64[:1])
+    else:
+        ref = butterfly_matvec(w.dim, w.n, w.phase_kind, w.phase_params, w.q,
+                               ab[0], ab[1], f64[:1])
+    dt = time.perf_counter() - t0
+    err = float(np.linalg.norm(g_gpu[0] - ref[0]) / np.linalg.norm(ref[0]))
+    rep = {"value": w.N * 1 / dt, "unit": "N·nvec/s", "cores": int(cores),
+           "kind": "oracle",
+           "sample": f"FP64 step-by-step butterfly (NumPy), 1 of {w.nvec} "
+                     f"vectors x {w.r} amplitude terms, full N={w.N}; "
+                     f"{dt:.1f} s"}
+    return rep, err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fio1d_n262144_batched",
+                    choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None,
+                    choices=["fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--nvec", type=int, default=None,
+                    help="override the workload's vector count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy before the timed "
+                         "region (reference for hardware byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1803_04128_amd as bfm
+    from synthetic import CONFIGS, gaussian_vectors, amplitude_factors
+
+    w = CONFIGS[args.workload]
+    precision = args.precision or WORKLOADS[args.workload]["precision"]
+    nvec = args.nvec or w.nvec
+    f64 = gaussian_vectors(w.N, nvec, w.seed)
+    f32 = f64.astype(np.complex64)
+    ab = None
+    if w.amplitude != "one":
+        ab = amplitude_factors(w.amplitude, w.dim, w.n, w.r, w.amp_seed)
+        ab = tuple(x.astype(np.complex64).astype(np.complex128) for x in ab)
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    f = torch.from_numpy(f32).to(dev)
+    g = torch.empty_like(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = bfm.Plan(w.dim, w.n, w.phase_kind, w.phase_params, q=w.q,
+                    amplitude=ab, precision=precision, max_nvec=nvec)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+
+    for _ in range(args.warmup):
+        plan.apply(f, out=g)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    plan.profile(True)
+    plan.profile_read()                      # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        plan.apply(f, out=g, stream=stream)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.profile(False)
+    kstats = plan.profile_read()
+    lat = np.array([evs[k].elapsed_time(evs[k + 1])
+                    for k in range(args.steps)])
+
+    value = w.N * nvec * args.steps / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # dominant kernel: largest total time over the timed region
+    name, st = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
+    per_launch_ms = st["total_ms"] / st["launches"]
+    ai = st["flops"] / max(st["bytes"], 1.0)
+    if precision == "fp32":
+        peak_c, unit_c = FP32_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        peak_c, unit_c = BF16_PEAK_TFLOPS, "TFLOP/s"
+    ridge = peak_c * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = traffic_from_profiles(args.workload, precision, name)
+    if ai >= ridge:
+        achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu" if precision == "fp32" else "mfma",
+                "achieved": achieved, "peak": peak_c, "unit": unit_c,
+                "frac": achieved / peak_c, "traffic": traffic}
+    else:
+        achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic}
+    roof.update({"kernel": name, "launch_ms": per_launch_ms,
+                 "alg_bytes_per_launch": st["bytes"] / st["launches"],
+                 "alg_flops_per_launch": st["flops"] / st["launches"]})
+
+    out = {
+        "metric": "Kf applies: N·nvec/s",
+        "value": value,
+        "unit": "N·nvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3+f32",
+                  "fp16x3": "f16x3+f32"}[precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "dim": w.dim, "N": w.N, "nvec": nvec,
+                   "r": w.r, "q": w.q, "phase": w.phase,
+                   "precision": precision},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                       "p99": float(np.percentile(lat, 99))},
+        "plan_s": plan_s,
+        "kernels": {k: {"launches": v["launches"],
+                        "ms_per_launch": v["total_ms"] / v["launches"]}
+                    for k, v in kstats.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        g_host = g[:1].cpu().numpy().astype(np.complex128)
+        rep, err = cpu_baseline(w, f64.astype(np.complex64).astype(
+            np.complex128), ab, g_host)
+        out["cpu_baseline"] = rep
+        out["rel_err_vs_oracle"] = err
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,27 @@ typedef struct bf_plan_info {
 
 int bf_query(bf_plan_t plan, bf_plan_info* info);
 
+/* ---- kernel timing (diagnostics) ---------------------------------------
+ * bf_profile(plan, 1): every later apply of this plan records a hipEvent
+ * pair around each kernel launch it issues, on the apply stream (at most
+ * 65536 launches are kept; later ones are not timed).  bf_profile(plan, 0)
+ * stops recording.  bf_profile_read synchronises the recorded events and
+ * returns one entry per kernel class: launches, total milliseconds, and the
+ * algorithmic bytes (inputs, outputs and factors each counted once) and
+ * flops of those launches; it then clears the records.  stats: caller
+ * array of cap entries; *count receives the number of classes.            */
+typedef struct bf_kernel_stat {
+    char name[48];
+    int launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} bf_kernel_stat;
+
+int bf_profile(bf_plan_t plan, int enable);
+int bf_profile_read(bf_plan_t plan, bf_kernel_stat* stats, int cap,
+                    int* count);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* bf_last_error(void);
 

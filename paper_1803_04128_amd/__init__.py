@@ -122,6 +122,24 @@ class Plan:
                 workspace.numel() * workspace.element_size(), st))
         return out.reshape(-1) if squeeze else out
 
+    def profile(self, enable=True):
+        """Start (or stop) per-launch event timing inside the library."""
+        _lib.check(self._lib.bf_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per-kernel-class totals since the last read (synchronises)."""
+        cap = 64
+        arr = (_lib.BfKernelStat * cap)()
+        cnt = C.c_int()
+        _lib.check(self._lib.bf_profile_read(self._h, arr, cap,
+                                             C.byref(cnt)))
+        out = {}
+        for k in arr[:min(cnt.value, cap)]:
+            out[k.name.decode()] = dict(launches=k.launches,
+                                        total_ms=k.total_ms, bytes=k.bytes,
+                                        flops=k.flops)
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(self._lib.bf_destroy(self._h))

@@ -39,9 +39,15 @@ class BfPlanInfo(C.Structure):
                 ("factor_stream_bytes", C.c_double)]
 
 
+class BfKernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int),
+                ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
 EXPORTS = ["bf_plan", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
-           "bf_lagrange"]
+           "bf_lagrange", "bf_profile", "bf_profile_read"]
 
 _lib = None
 
@@ -85,6 +91,9 @@ def load():
                               P(C.c_int)]
     lib.bf_lagrange.argtypes = [P(C.c_int), C.c_int, P(C.c_double), C.c_int,
                                 P(C.c_double)]
+    lib.bf_profile.argtypes = [C.c_void_p, C.c_int]
+    lib.bf_profile_read.argtypes = [C.c_void_p, P(BfKernelStat), C.c_int,
+                                    P(C.c_int)]
     for name in EXPORTS:
         getattr(lib, name).restype = (C.c_char_p if name == "bf_last_error"
                                       else C.c_int)

@@ -121,7 +121,7 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     p.phase.n = n;
     for (int i = 0; i < need; ++i) p.phase.p[i] = phase->params[i];
     const char* fenv = std::getenv("BF_FUSED");
-    p.fused = fenv ? std::atoi(fenv) != 0 : false;
+    p.fused = fenv ? std::atoi(fenv) != 0 : true;
     if (hipGetDevice(&p.device) != hipSuccess) {
         delete h;
         return fail(BF_EHIP, "bf_plan: no HIP device");
@@ -134,7 +134,7 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     // memory: factors + workspace under the cap
     const size_t cap = env_bytes("BF_MEM_CAP_BYTES", (size_t)-1);
     const size_t ws_cap = env_bytes("BF_WS_CAP_BYTES", 16 * kGiB);
-    size_t per_vec = 2 * (size_t)p.N * p.max_rank * p.r_amp * 8;
+    size_t per_vec = 2 * (size_t)p.N * p.max_rank * p.r_amp * 8 + 64;
     int chunk = (int)std::max<size_t>(1, std::min<size_t>(max_nvec,
                                                          ws_cap / per_vec));
     p.chunk_nvec = chunk;
@@ -223,9 +223,64 @@ int bf_destroy(bf_plan_t plan) {
     if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
     if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
     if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
+    for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
     plan->magic = 0;
     delete plan;
     if (rc != BF_OK) return fail(rc, "bf_destroy: HIP error while freeing");
+    return BF_OK;
+}
+
+int bf_profile(bf_plan_t plan, int enable) {
+    if (int e = check_plan(plan)) return e;
+    bfi::Profiler& pr = plan->p.prof;
+    if (enable && pr.pool.empty()) {
+        const int cap = 8192;
+        pr.pool.resize(cap);
+        for (int i = 0; i < cap; ++i) {
+            if (hipEventCreate(&pr.pool[i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(pr.pool[j]);
+                pr.pool.clear();
+                return fail(BF_EHIP, "bf_profile: hipEventCreate failed");
+            }
+        }
+    }
+    pr.on = enable != 0;
+    return BF_OK;
+}
+
+int bf_profile_read(bf_plan_t plan, bf_kernel_stat* stats, int cap,
+                    int* count) {
+    if (int e = check_plan(plan)) return e;
+    if (!count || (cap > 0 && !stats))
+        return fail(BF_EINVAL, "bf_profile_read: bad argument");
+    bfi::Profiler& pr = plan->p.prof;
+    std::vector<bf_kernel_stat> acc(pr.names.size());
+    for (size_t i = 0; i < pr.names.size(); ++i) {
+        std::memset(&acc[i], 0, sizeof(bf_kernel_stat));
+        std::snprintf(acc[i].name, sizeof(acc[i].name), "%s",
+                      pr.names[i].c_str());
+    }
+    for (const auto& r : pr.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pr.pool[r.ev1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, pr.pool[r.ev0], pr.pool[r.ev1]) !=
+                hipSuccess)
+            return fail(BF_EHIP, "bf_profile_read: event query failed");
+        bf_kernel_stat& k = acc[r.cls];
+        k.launches += 1;
+        k.total_ms += ms;
+        k.bytes += r.bytes;
+        k.flops += r.flops;
+    }
+    int n = 0;
+    for (const auto& k : acc) {
+        if (k.launches == 0) continue;
+        if (n < cap) stats[n] = k;
+        ++n;
+    }
+    *count = n;
+    pr.recs.clear();
+    pr.used = 0;
     return BF_OK;
 }
 

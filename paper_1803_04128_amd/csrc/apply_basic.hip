@@ -199,8 +199,28 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
     const float2* cur = nullptr;
     float2* bufs[2] = {buf0, buf1};
     int which = 0;
+    const double N = (double)p.N, c8 = 8.0 * Vc;
+    const double head_bytes = N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0);
     for (auto& s : p.steps) {
         StepArgs a = make_step_args(p, s, Vc, f, cur, bufs[which]);
+        double bytes = (s.reads_f ? head_bytes : N * s.r_in * c8) +
+                       N * s.r_out * c8 + s.tw_elems * 8.0 + s.S_elems * 8.0 +
+                       s.mat_elems * 4.0;
+        double flops;
+        const char* name;
+        if (s.kind == STEP_XI) {
+            flops = (double)s.units * p.R * Vc *
+                    (p.R * s.r_in * 6.0 + (double)p.R * s.r_out * s.r_in * 4.0);
+            name = "xi_step_basic";
+        } else if (s.kind == STEP_X) {
+            flops = (double)s.units * p.R * Vc *
+                    ((double)p.R * s.r_out * s.r_in * 4.0 + p.R * s.r_out * 8.0);
+            name = "x_step_basic";
+        } else {
+            flops = N * Vc * s.r_out * (double)s.r_in * 8.0;
+            name = "switch_basic";
+        }
+        ProfScope ps(p, st);
         if (p.dim == 1) {
             if (p.max_rank <= 16) launch_step_basic<2, 16>(s, a, st);
             else return "1D rank above 16";
@@ -212,15 +232,20 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return std::string("step launch: ") + hipGetErrorString(e);
+        ps.end(name, bytes, flops);
         cur = bufs[which];
         which ^= 1;
     }
     TailArgs t = make_tail_args(p, nv, cur, g);
+    ProfScope ps(p, st);
     hipLaunchKernelGGL(tail_basic, dim3(blocks_for(p.N * nv)), dim3(256), 0,
                        st, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("tail launch: ") + hipGetErrorString(e);
+    ps.end("tail_basic", N * t.r * c8 + N * nv * 8.0 +
+                             (p.has_amp ? N * p.r_amp * 8.0 : 0),
+           N * Vc * (double)t.nb * 2.0 + N * nv * p.r_amp * 8.0);
     return "";
 }
 

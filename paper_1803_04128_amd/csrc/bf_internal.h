@@ -86,6 +86,27 @@ struct Pass {
     int group_log;    // log_R of pairs per group
 };
 
+// Timing records of kernel launches (bf_profile).
+struct ProfRec {
+    int cls;          // index into Profiler::names
+    int ev0, ev1;     // indices into the event pool
+    double bytes, flops;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    int used = 0;
+    std::vector<std::string> names;
+    std::vector<ProfRec> recs;
+    int cls_of(const std::string& n) {
+        for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == n) return (int)i;
+        names.push_back(n);
+        return (int)names.size() - 1;
+    }
+};
+
 struct Plan {
     int dim = 1, n = 0, L = 0, h = 0, R = 2, q = 0, r_amp = 1;
     int precision = BF_FP32, max_nvec = 1;
@@ -110,6 +131,16 @@ struct Plan {
     bool fused = true;        // level-fused passes (else one launch per step)
     double flops_per_column = 0;
     double factor_stream_bytes = 0;
+    Profiler prof;
+};
+
+// Wraps a kernel launch with timing events when profiling is on.
+struct ProfScope {
+    Plan& p;
+    hipStream_t st;
+    int ev0 = -1;
+    ProfScope(Plan& pl, hipStream_t s);
+    void end(const std::string& name, double bytes, double flops);
 };
 
 // geometry.cpp

@@ -6,11 +6,27 @@
 
 namespace bfi {
 
+ProfScope::ProfScope(Plan& pl, hipStream_t s) : p(pl), st(s) {
+    if (!p.prof.on || p.prof.used + 2 > (int)p.prof.pool.size()) return;
+    ev0 = p.prof.used++;
+    if (hipEventRecord(p.prof.pool[ev0], st) != hipSuccess) ev0 = -1;
+}
+
+void ProfScope::end(const std::string& name, double bytes, double flops) {
+    if (ev0 < 0) return;
+    const int ev1 = p.prof.used++;
+    if (hipEventRecord(p.prof.pool[ev1], st) != hipSuccess) return;
+    p.prof.recs.push_back({p.prof.cls_of(name), ev0, ev1, bytes, flops});
+}
+
 std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
                       float2* buf0, float2* buf1, hipStream_t st);
+size_t fused_state_bytes(const Plan& p, int Vs);
 
-// Two ping-pong state buffers of N * max_rank * (nv * r) complex64 each.
+// Two ping-pong state buffers of N * max_rank * (nv * r) complex64 each
+// (the fused passes pad the columns to whole tiles).
 static size_t state_bytes(const Plan& p, int nv) {
+    if (p.fused) return fused_state_bytes(p, nv * p.r_amp);
     return (size_t)p.N * p.max_rank * (size_t)nv * p.r_amp * sizeof(float2);
 }
 

@@ -20,6 +20,14 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
+@pytest.fixture(autouse=True, params=["fused", "per_step"])
+def apply_path(request, monkeypatch):
+    """Run every parity case through the level-fused passes and through the
+    one-launch-per-level path (BF_FUSED is read when a plan is built)."""
+    monkeypatch.setenv("BF_FUSED", "1" if request.param == "fused" else "0")
+    return request.param
+
+
 def _plan(dim, n, kind, q, ab=None, nvec=1, precision="fp32", phase=None):
     import paper_1803_04128_amd as bfm
     params = PHASE_PARAMS[phase or kind]
@@ -156,7 +164,7 @@ def test_batch_invariance_and_chunking(monkeypatch):
         singles = [gpu_apply(pl, f32[v:v + 1])[0] for v in range(nvec)]
     for v in range(nvec):
         assert np.array_equal(g_all[v], singles[v][0])
-    per_vec = 2 * n * 10 * 4 * 8
+    per_vec = 2 * n * 10 * 4 * 8 + 64
     monkeypatch.setenv("BF_WS_CAP_BYTES", str(3 * per_vec))
     with _plan(1, n, "fio1d", q, ab=ab, nvec=nvec) as pl:
         assert pl.info()["chunk_nvec"] == 3
