@@ -345,6 +345,7 @@ __global__ void __launch_bounds__(kPassThreads) x_pass(PassArgs a) {
 // ----------------------------------------------------------- host planning
 
 constexpr size_t kLdsBudget = 96 * 1024;
+constexpr size_t kMfmaLdsBudget = 150 * 1024;
 
 struct Tiling {
     int TB, MAXIT;
@@ -373,7 +374,10 @@ static bool mfma_mode(const Plan& p, int Vt) {
 // MFMA passes the width is a power of two, lowered (not below r) until the
 // larger half of the levels fits one pass (Gk * Vt <= 512).
 int fused_tile_cols(const Plan& p, int Vs) {
+    // BF_TILE_COLS overrides the width (a multiple of r; tuning experiments)
+    static const char* env = std::getenv("BF_TILE_COLS");
     int tv = std::max(1, 8 / p.r_amp);
+    if (env && std::atoi(env) >= p.r_amp) tv = std::atoi(env) / p.r_amp;
     int vt = std::min(tv * p.r_amp, Vs);
     if (p.dim == 1 && pow2_le8(p.r_amp)) {
         int v2 = 1;
@@ -405,9 +409,10 @@ static bool pass_fits(const Plan& p, int s0, int s1, int Vt, bool head,
     if (k > kMaxPassLevels) return false;
     if (mfma_mode(p, Vt) && p.steps[s0].kind != STEP_SWITCH) {
         const int hr1 = p.head_step_side;
-        const size_t lds = (size_t)Gk * rmax * Vt * 8 + (size_t)2 * Gk * rmax * 8 +
+        // two tiles, two twiddle buffers, and the f tile of the head pass
+        const size_t lds = 2 * ((size_t)Gk * rmax * Vt * 8 + (size_t)2 * Gk * rmax * 8) +
                            (head ? (size_t)Gk * hr1 * Vt * 8 : 0);
-        return lds <= kLdsBudget && Gk * Vt <= (long long)kMfmaTileCap * 8;
+        return lds <= kMfmaLdsBudget && Gk * Vt <= (long long)kMfmaTileCap * 8;
     }
     size_t lds = (size_t)Gk * rmax * Vt * 8;
     const int hr = p.head_step_side == 1 ? 1 :
@@ -635,8 +640,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             mfma_mode(p, Vt) && (is_xi || (k > 0 && !a.has_head)) &&
             (long long)a.Gk * Vt <= (long long)kMfmaTileCap * 8;
         if (use_mfma) {
-            lds = (size_t)a.Gk * a.rmax * Vt * 8 + (size_t)2 * a.Gk * a.rmax * 8 +
-                  (is_xi && a.has_head ? (size_t)a.Gk * hr * Vt * 8 : 0);
+            lds = mfma_pass_lds(a, is_xi);
             if (lds > 160 * 1024) return "MFMA pass does not fit in LDS";
         }
         ProfScope prof(p, st);

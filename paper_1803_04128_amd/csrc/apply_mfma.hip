@@ -16,6 +16,9 @@
 //   switch (Algorithm 4.1 step 4 regrouped): per pair, A = Re S and A = Im S
 //     against 16 real columns (Re mu, Im mu of 8 columns); the other half of
 //     each product comes from the neighbouring lane.
+// Levels ping-pong between two LDS tiles (outputs go straight to the other
+// tile) and the next level's twiddles are staged into the second twiddle
+// buffer while a level computes, so a level needs one workgroup barrier.
 // K steps past the end use A = 0 and read valid (finite) data, so the loads
 // need no guards.  R = 2, r <= 16, VT (columns per tile) in {1, 2, 4, 8}.
 #include "fused_common.h"
@@ -40,121 +43,102 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
 
 // Twiddles of local level j for the group's units into LDS:
 // twl[unit_loc][i][c][r], unit_loc = apl 2^(k-j) + bl, contiguous per apl.
-__device__ __forceinline__ void stage_twiddles(const PassArgs& a,
-                                               const PassLevel& lv, int rr,
-                                               float2* twl, int j,
-                                               long long ap_grp,
-                                               long long bg) {
+__device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
+                                               float2* twl, long long ap_grp,
+                                               long long bg, bool xi) {
+    const PassLevel& lv = a.lv[j - 1];
+    const int rr = xi ? lv.r_in : lv.r_out;
     const int kj = a.k - j;
     const int per_unit = 4 * rr;
     const int total = (a.Gk >> 1) * per_unit;
     const int shiftB = a.L - (a.la + j - 1);
+    // unit index u = (apg << shiftB) + bgl < N/2, and u * per_unit < 2^31
+    const unsigned apg0 = (unsigned)(ap_grp << (j - 1));
+    const unsigned bg0 = (unsigned)(bg << kj);
     Walk2 w(threadIdx.x, per_unit);
     for (int e = threadIdx.x; e < total; e += blockDim.x, w.next()) {
-        const int unit = w.hi;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const long long apg = (ap_grp << (j - 1)) + apl;
-        const long long bgl = (bg << kj) + bl;
-        const long long u = (apg << shiftB) + bgl;
-        twl[e] = lv.tw[u * per_unit + w.lo];
+        const unsigned unit = (unsigned)w.hi;
+        const unsigned apl = unit >> kj, bl = unit & ((1u << kj) - 1);
+        const unsigned u = ((apg0 + apl) << shiftB) + bg0 + bl;
+        twl[e] = lv.tw[u * (unsigned)per_unit + (unsigned)w.lo];
     }
 }
 
+// One xi level: src (stride src_r coefficients per slot) -> dst.
 template <int VT>
-__device__ __forceinline__ void mfma_xi_level(const PassArgs& a, float2* tile,
-                                              const float2* ftile, float2* twl,
-                                              int j, long long ap_grp,
-                                              long long bg) {
+__device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
+                                              const float2* src, int src_r,
+                                              float2* dst, const float2* twl,
+                                              int j) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int K = 2 * r_in, nks = (K + 3) / 4;
     const int kj = a.k - j;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    stage_twiddles(a, lv, r_in, twl, j, ap_grp, bg);
     const int g = lane >> 4, tA = lane & 15;
     const int n = lane & 15;
     constexpr int CPT = 16 / VT;             // (unit, i) combinations per tile
     const int sub = n / VT, col = n & (VT - 1);
-    const bool from_f = a.has_head && j == 1;
-    const float2* src = from_f ? ftile : tile;
-    const int RS = (from_f ? a.head_r : a.rmax) * VT;   // slot stride
-    // per-lane K-step tables: k = 4 kk + g -> child kc, point ks; the A
-    // operand for the whole level; LDS offsets of x and of the twiddle
+    const int RS = src_r * VT;               // source slot stride
+    // the two children's slots differ by 2^(j-1) slots whatever the unit,
+    // so x offsets fold the child in: xo = c 2^(j-1) RS + s VT + col
+    const int cstride = (1 << (j - 1)) * RS;
     float aM[8];
-    int kc[8], xo[8], wo[8];
+    int xo[8], wo[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
         const int k = 4 * kk + g;
         const bool v = kk < nks && k < K;
         const int c = (v && k >= r_in) ? 1 : 0;
         const int s = v ? k - c * r_in : 0;
-        kc[kk] = c;
-        xo[kk] = s * VT + col;
+        xo[kk] = c * cstride + s * VT + col;
         wo[kk] = c * r_in + s;
         aM[kk] = (v && tA < r_out) ? lv.mats[(c * r_out + tA) * r_in + s] : 0.f;
     }
     const int ntiles = (a.Gk + CPT - 1) / CPT;
-    __syncthreads();
-    floatx4 kr[kWaveTiles], ki[kWaveTiles];
-#pragma unroll
-    for (int m = 0; m < kWaveTiles; ++m) {
-        const int tau = wave + m * nwaves;
-        if (tau >= ntiles) break;
+    const int DS = a.rmax * VT;
+    for (int tau = wave; tau < ntiles; tau += nwaves) {
         int ui = tau * CPT + sub;
-        if (ui >= a.Gk) ui = 0;                 // padding column: any valid data
+        const bool ok = ui < a.Gk;
+        if (!ok) ui = 0;                        // padding column: any valid data
         const int unit = ui >> 1, i = ui & 1;
         const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
         const int rv = digit_rev(apl, j - 1, 1);
-        const int sb0 = (((bl * 2) << (j - 1)) + rv) * RS;
-        const int sb1 = (((bl * 2 + 1) << (j - 1)) + rv) * RS;
-        const int twb = (unit * 4 + i * 2) * r_in;
+        const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS;
+        const float2* wp = twl + (unit * 4 + i * 2) * r_in;
         float2 xs[8], ws[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
             if (kk >= nks) break;
-            xs[kk] = src[(kc[kk] ? sb1 : sb0) + xo[kk]];
-            ws[kk] = twl[twb + wo[kk]];
+            xs[kk] = xp[xo[kk]];
+            ws[kk] = wp[wo[kk]];
         }
         floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
             if (kk >= nks) break;
             const float2 x = xs[kk], w = ws[kk];
-            const float zr = w.x * x.x - w.y * x.y;
-            const float zi = w.x * x.y + w.y * x.x;
-            accr = mfma4(aM[kk], zr, accr);
-            acci = mfma4(aM[kk], zi, acci);
+            accr = mfma4(aM[kk], w.x * x.x - w.y * x.y, accr);
+            acci = mfma4(aM[kk], w.x * x.y + w.y * x.x, acci);
         }
-        kr[m] = accr;
-        ki[m] = acci;
-    }
-    __syncthreads();
+        if (ok) {
+            float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
 #pragma unroll
-    for (int m = 0; m < kWaveTiles; ++m) {
-        const int tau = wave + m * nwaves;
-        if (tau >= ntiles) break;
-        const int ui = tau * CPT + sub;
-        if (ui >= a.Gk) continue;
-        const int unit = ui >> 1, i = ui & 1;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const int slot_out = ((bl * 2 + i) << (j - 1)) + digit_rev(apl, j - 1, 1);
-        const int base = slot_out * a.rmax * VT + col;
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int t = 4 * g + jj;
-            if (t < r_out) tile[base + t * VT] = make_float2(kr[m][jj], ki[m][jj]);
+            for (int jj = 0; jj < 4; ++jj) {
+                const int t = 4 * g + jj;
+                if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
+            }
         }
     }
-    __syncthreads();
 }
 
-// x level; on the last level of a tail pass the outputs are added into
-// tacc (same lane mapping on every sub-iteration) instead of the tile.
+// One x level: src -> dst, or (last level of a tail pass) added into tacc,
+// whose lane mapping is the same on every sub-iteration.
 template <int VT>
-__device__ __forceinline__ void mfma_x_level(const PassArgs& a, float2* tile,
-                                             float2* twl, int j,
-                                             long long ap_grp, long long bg,
+__device__ __forceinline__ void mfma_x_level(const PassArgs& a,
+                                             const float2* src, float2* dst,
+                                             const float2* twl, int j,
                                              bool to_tail, floatx4* tacc) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
@@ -162,7 +146,6 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a, float2* tile,
     const int kj = a.k - j;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    stage_twiddles(a, lv, r_out, twl, j, ap_grp, bg);
     const int g = lane >> 4, tA = lane & 15;
     const int n = lane & 15;
     constexpr int UPT = 16 / VT;             // units per tile
@@ -182,9 +165,6 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a, float2* tile,
     }
     const int nunits = a.Gk >> 1;
     const int ntiles = (nunits + UPT - 1) / UPT;
-    __syncthreads();
-    // keep[m][i]: (re, im) accumulators of output child i
-    floatx4 kr[kWaveTiles / 2][2], ki[kWaveTiles / 2][2];
 #pragma unroll
     for (int m = 0; m < kWaveTiles / 2; ++m) {
         const int tau = wave + m * nwaves;
@@ -194,14 +174,14 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a, float2* tile,
         if (!ok) unit = 0;
         const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
         const int rv = digit_rev(apl, j - 1, 1);
-        const int sb0 = (((bl * 2) << (j - 1)) + rv) * RS;
-        const int sb1 = (((bl * 2 + 1) << (j - 1)) + rv) * RS;
+        const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS;
+        const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
         float2 x0[4], x1[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             if (kk >= nks) break;
-            x0[kk] = tile[sb0 + xo[kk]];
-            x1[kk] = tile[sb1 + xo[kk]];
+            x0[kk] = xp0[xo[kk]];
+            x1[kk] = xp1[xo[kk]];
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -215,54 +195,31 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a, float2* tile,
                 y1r = mfma4(am, x1[kk].x, y1r);
                 y1i = mfma4(am, x1[kk].y, y1i);
             }
-            const int twb = (unit * 4 + i * 2) * r_out;
+            const float2* tp = twl + (unit * 4 + i * 2) * r_out;
             floatx4 orr, oii;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 int t = 4 * g + jj;
                 if (t >= r_out) t = 0;
-                const float2 T0 = twl[twb + t];
-                const float2 T1 = twl[twb + r_out + t];
+                const float2 T0 = tp[t];
+                const float2 T1 = tp[r_out + t];
                 orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
                 oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
             }
-            kr[m][i] = orr;
-            ki[m][i] = oii;
-        }
-    }
-    __syncthreads();
-    if (to_tail) {
+            if (to_tail) {
+                // fixed (tau, lane) -> (A box, point, column) across subs
+                tacc[4 * m + 2 * i] += orr;
+                tacc[4 * m + 2 * i + 1] += oii;
+            } else if (ok) {
+                float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
 #pragma unroll
-        for (int m = 0; m < kWaveTiles / 2; ++m) {
-            const int tau = wave + m * nwaves;
-            if (tau >= ntiles) break;
-            tacc[4 * m + 0] += kr[m][0];
-            tacc[4 * m + 1] += ki[m][0];
-            tacc[4 * m + 2] += kr[m][1];
-            tacc[4 * m + 3] += ki[m][1];
-        }
-        return;
-    }
-#pragma unroll
-    for (int m = 0; m < kWaveTiles / 2; ++m) {
-        const int tau = wave + m * nwaves;
-        if (tau >= ntiles) break;
-        const int unit = tau * UPT + sub;
-        if (unit >= nunits) continue;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const int rv = digit_rev(apl, j - 1, 1);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int slot_out = ((bl * 2 + i) << (j - 1)) + rv;
-            const int base = slot_out * RS + col;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int t = 4 * g + jj;
-                if (t < r_out) tile[base + t * VT] = make_float2(kr[m][i][jj], ki[m][i][jj]);
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int t = 4 * g + jj;
+                    if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
+                }
             }
         }
     }
-    __syncthreads();
 }
 
 // nu = S mu per pair, in place (pairs are independent, so each wave reads
@@ -290,10 +247,10 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
         sv_ok[kk] = kk < nks && s < r_in && tA < r_out;
         so[kk] = ((s < r_in ? s : 0) * VT + colc) * 2 + reim;
     }
+    const float2* S0 = a.S + (size_t)((a0 << shiftB) + bfix) * r_out * r_in;
     for (int slot = wave; slot < a.Gk; slot += nwaves) {
-        const long long A = a0 + digit_rev(slot, a.k, 1);
-        const long long P = (A << shiftB) + bfix;
-        const float2* S = a.S + (size_t)P * r_out * r_in;
+        const unsigned dA = (unsigned)digit_rev(slot, a.k, 1);
+        const float2* S = S0 + (dA << shiftB) * (unsigned)(r_out * r_in);
         const int base = slot * a.rmax * VT * 2;
         float2 sv[4];
         float bv[4];
@@ -322,12 +279,15 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
     __syncthreads();
 }
 
+// LDS of an MFMA pass: tiles[2] (Gk x rmax x VT), twiddles[2] (2 Gk rmax),
+// then the f tile (Gk x head_r x VT) when the pass starts from f.
 template <int VT>
 __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
-    float2* tile = lds;
-    float2* twl = lds + (size_t)a.Gk * a.rmax * VT;
-    float2* ftile = twl + (size_t)2 * a.Gk * a.rmax;
+    const size_t tsz = (size_t)a.Gk * a.rmax * VT, wsz = (size_t)2 * a.Gk * a.rmax;
+    float2* tiles[2] = {lds, lds + tsz};
+    float2* twl[2] = {lds + 2 * tsz, lds + 2 * tsz + wsz};
+    float2* ftile = lds + 2 * tsz + 2 * wsz;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
@@ -335,19 +295,30 @@ __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
     const long long bg = spatial % a.nbg;
     const long long ap_base = spatial / a.nbg;
     // the f tile is shared by every sub-iteration (the T_X boxes at level
-    // l0 - 1 all see the same input); the barrier inside the first level
-    // orders these loads before their use
+    // l0 - 1 all see the same input)
     if (a.has_head) load_head(a, ftile, bg * a.Gk, chunk);
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-            load_tile(a, tile, p0, a.lv[0].r_in, chunk);
+            load_tile(a, tiles[0], p0, a.lv[0].r_in, chunk);
         }
-        for (int j = 1; j <= a.k; ++j)
-            mfma_xi_level<VT>(a, tile, ftile, twl, j, ap_grp, bg);
-        if (a.has_switch) mfma_switch<VT>(a, tile, ap_grp * a.Gk, bg);
-        store_tile(a, tile, ap_grp * a.Gk, bg, chunk);
+        stage_twiddles(a, 1, twl[0], ap_grp, bg, true);
+        __syncthreads();
+        const float2* src = a.has_head ? ftile : tiles[0];
+        int src_r = a.has_head ? a.head_r : a.rmax;
+        int out = a.has_head ? 0 : 1;
+        for (int j = 1; j <= a.k; ++j) {
+            if (j < a.k) stage_twiddles(a, j + 1, twl[j & 1], ap_grp, bg, true);
+            mfma_xi_level<VT>(a, src, src_r, tiles[out], twl[(j - 1) & 1], j);
+            __syncthreads();
+            src = tiles[out];
+            src_r = a.rmax;
+            out ^= 1;
+        }
+        float2* cur = tiles[out ^ 1];
+        if (a.has_switch) mfma_switch<VT>(a, cur, ap_grp * a.Gk, bg);
+        store_tile(a, cur, ap_grp * a.Gk, bg, chunk);
         __syncthreads();
     }
 }
@@ -355,8 +326,9 @@ __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
 template <int VT>
 __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
-    float2* tile = lds;
-    float2* twl = lds + (size_t)a.Gk * a.rmax * VT;
+    const size_t tsz = (size_t)a.Gk * a.rmax * VT, wsz = (size_t)2 * a.Gk * a.rmax;
+    float2* tiles[2] = {lds, lds + tsz};
+    float2* twl[2] = {lds + 2 * tsz, lds + 2 * tsz + wsz};
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
@@ -369,17 +341,26 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-        load_tile(a, tile, p0, a.lv[0].r_in, chunk);
-        // (the barrier inside the first level orders the tile loads)
-        for (int j = 1; j <= a.k; ++j)
-            mfma_x_level<VT>(a, tile, twl, j, ap_grp, bg,
-                             a.has_tail && j == a.k, tacc);
-        if (!a.has_tail) store_tile(a, tile, ap_grp * a.Gk, bg, chunk);
+        load_tile(a, tiles[0], p0, a.lv[0].r_in, chunk);
+        stage_twiddles(a, 1, twl[0], ap_grp, bg, false);
         __syncthreads();
+        int out = 1;
+        for (int j = 1; j <= a.k; ++j) {
+            if (j < a.k) stage_twiddles(a, j + 1, twl[j & 1], ap_grp, bg, false);
+            mfma_x_level<VT>(a, tiles[out ^ 1], tiles[out], twl[(j - 1) & 1], j,
+                             a.has_tail && j == a.k, tacc);
+            __syncthreads();
+            out ^= 1;
+        }
+        if (!a.has_tail) {
+            store_tile(a, tiles[out ^ 1], ap_grp * a.Gk, bg, chunk);
+            __syncthreads();
+        }
     }
     if (!a.has_tail) return;
     // final coefficients of the Gk boxes A to LDS as [a_loc][t][VT], then
     // g_v(x) = sum_k a_k(x) lambda_k(x) (eq. (eqn:tg))
+    float2* fin = tiles[0];
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int nwaves = blockDim.x >> 6;
@@ -402,7 +383,7 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
                 for (int jj = 0; jj < 4; ++jj) {
                     const int t = 4 * g + jj;
                     if (t < r_out)
-                        tile[(aloc * a.tail_r + t) * VT + col] =
+                        fin[(aloc * a.tail_r + t) * VT + col] =
                             make_float2(tacc[4 * m + 2 * i][jj],
                                         tacc[4 * m + 2 * i + 1][jj]);
                 }
@@ -410,7 +391,6 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
         }
     }
     __syncthreads();
-    const float2* acc = tile;
     const int tv = VT / a.r_amp;
     const int total = a.Gk * a.tail_r * tv;
     const int v0 = chunk * tv;
@@ -424,7 +404,7 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
         const long long x = (ap_grp * a.Gk + aloc) * (long long)a.tail_side + t;
         float2 sum = make_float2(0.f, 0.f);
         for (int kk = 0; kk < a.r_amp; ++kk) {
-            const float2 v = acc[(aloc * a.tail_r + t) * VT + vl * a.r_amp + kk];
+            const float2 v = fin[(aloc * a.tail_r + t) * VT + vl * a.r_amp + kk];
             if (a.amp_a) {
                 const float2 z = cmul(a.amp_a[(size_t)kk * a.N + x], v);
                 sum.x += z.x;
@@ -436,6 +416,13 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
         }
         a.g[(size_t)(v0 + vl) * a.N + x] = sum;
     }
+}
+
+size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
+    const size_t tsz = (size_t)a.Gk * a.rmax * a.Vt, wsz = (size_t)2 * a.Gk * a.rmax;
+    size_t e = 2 * tsz + 2 * wsz;
+    if (is_xi && a.has_head) e += (size_t)a.Gk * a.head_r * a.Vt;
+    return e * sizeof(float2);
 }
 
 template <int VT>

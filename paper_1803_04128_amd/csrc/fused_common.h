@@ -160,12 +160,14 @@ __device__ __forceinline__ void store_tile(const PassArgs& a,
     const int per_pair = a.r_state_out * a.Vt;
     const int lds_pair = a.rmax * a.Vt;
     const int total = a.Gk * per_pair;
-    float2* base = a.out + (size_t)chunk * a.N * per_pair;
+    // pair offsets within one column chunk stay below N * per_pair < 2^31
+    float2* base = a.out + (size_t)chunk * a.N * per_pair +
+                   (size_t)((a0 << shiftB) + bfix) * per_pair;
     Walk2 w(threadIdx.x, per_pair);      // (slot, t * Vt + col)
     for (int e = threadIdx.x; e < total; e += blockDim.x, w.next()) {
-        const long long A = a0 + digit_rev(w.hi, a.k, a.dim);
-        const long long P = (A << shiftB) + bfix;
-        base[(size_t)P * per_pair + w.lo] = tile[w.hi * lds_pair + w.lo];
+        const unsigned dA = (unsigned)digit_rev(w.hi, a.k, a.dim);
+        base[(dA << shiftB) * (unsigned)per_pair + (unsigned)w.lo] =
+            tile[w.hi * lds_pair + w.lo];
     }
 }
 
@@ -241,5 +243,7 @@ __device__ __forceinline__ void tile_switch(const PassArgs& a, float2* tile,
 // MFMA passes (apply_mfma.hip): launch one pass; "" on success.
 std::string launch_mfma_pass(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st);
+// Dynamic LDS bytes of an MFMA pass with these arguments.
+size_t mfma_pass_lds(const PassArgs& a, bool is_xi);
 
 }  // namespace bfi
