@@ -81,6 +81,9 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
         precision != BF_FP16X3)
         return fail(BF_EINVAL, "bf_plan: unknown precision");
     if (max_nvec < 1) return fail(BF_EINVAL, "bf_plan: max_nvec < 1");
+    if (precision != BF_FP32 && dim != 1)
+        return fail(BF_EUNSUPPORTED,
+                    "bf_plan: split precisions are implemented for 1D grids");
     int need = -1;
     switch (phase->kind) {
         case BF_PHASE_DFT: need = 0; break;

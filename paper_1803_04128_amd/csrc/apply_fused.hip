@@ -529,6 +529,8 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             if (s.kind == STEP_SWITCH) continue;
             a.lv[k].tw = s.tw;
             a.lv[k].mats = s.mats;
+            a.lv[k].mats_hi = s.mats_hi;
+            a.lv[k].mats_lo = s.mats_lo;
             a.lv[k].r_in = s.r_in;
             a.lv[k].r_out = s.r_out;
             a.lv[k].level = s.level;
@@ -542,6 +544,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
                          ((double)p.R * s.r_out * s.r_in * 4.0 + p.R * s.r_out * 8.0);
         }
         a.k = k;
+        a.prec = p.precision;
         a.Gk = 1 << (p.dim * k);
         a.L = p.L;
         a.n = p.n;
@@ -639,6 +642,11 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         const bool use_mfma =
             mfma_mode(p, Vt) && (is_xi || (k > 0 && !a.has_head)) &&
             (long long)a.Gk * Vt <= (long long)kMfmaTileCap * 8;
+        // the split precisions exist only on the MFMA passes; never compute
+        // a requested BF16/FP16 apply in FP32 silently
+        if (p.precision != BF_FP32 && !use_mfma)
+            return "split precision needs the 1D MFMA passes (power-of-two "
+                   "tile width, r in {1, 2, 4, 8}, a level in every pass)";
         if (use_mfma) {
             lds = mfma_pass_lds(a, is_xi);
             if (lds > 160 * 1024) return "MFMA pass does not fit in LDS";

@@ -41,6 +41,73 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// ---- split precision: x = hi + lo in bfloat16 or half, products
+// hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo term is dropped).
+// 16x16x32 layout: A lane l holds A[l%16][8(l/16)+e], B lane l holds
+// B[8(l/16)+e][l%16], e < 8; 16x16x16: 4(l/16)+e, e < 4 (checked by an
+// in-bounds probe).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct Split;
+
+template <> struct Split<BF_BF16X3> {
+    typedef bf16x8 v8;
+    typedef shortx4 v4;
+    static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
+        const __bf16 hv = (__bf16)v;
+        h[e] = hv;
+        l[e] = (__bf16)(v - (float)hv);
+    }
+    static __device__ __forceinline__ void put4(v4& h, v4& l, int e, float v) {
+        const __bf16 hv = (__bf16)v;
+        const __bf16 lv = (__bf16)(v - (float)hv);
+        h[e] = __builtin_bit_cast(short, hv);
+        l[e] = __builtin_bit_cast(short, lv);
+    }
+    static __device__ __forceinline__ void bits8(v8& h, int e, uint16_t b) {
+        h[e] = __builtin_bit_cast(__bf16, b);
+    }
+    static __device__ __forceinline__ void bits4(v4& h, int e, uint16_t b) {
+        h[e] = (short)b;
+    }
+    static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ floatx4 mma16(v4 a, v4 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+
+template <> struct Split<BF_FP16X3> {
+    typedef f16x8 v8;
+    typedef f16x4 v4;
+    static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
+        const _Float16 hv = (_Float16)v;
+        h[e] = hv;
+        l[e] = (_Float16)(v - (float)hv);
+    }
+    static __device__ __forceinline__ void put4(v4& h, v4& l, int e, float v) {
+        const _Float16 hv = (_Float16)v;
+        h[e] = hv;
+        l[e] = (_Float16)(v - (float)hv);
+    }
+    static __device__ __forceinline__ void bits8(v8& h, int e, uint16_t b) {
+        h[e] = __builtin_bit_cast(_Float16, b);
+    }
+    static __device__ __forceinline__ void bits4(v4& h, int e, uint16_t b) {
+        h[e] = __builtin_bit_cast(_Float16, b);
+    }
+    static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ floatx4 mma16(v4 a, v4 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+
 // Twiddles of local level j for the group's units into LDS:
 // twl[unit_loc][i][c][r], unit_loc = apl 2^(k-j) + bl, contiguous per apl.
 __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
@@ -65,7 +132,7 @@ __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
 }
 
 // One xi level: src (stride src_r coefficients per slot) -> dst.
-template <int VT>
+template <int VT, int PREC>
 __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
                                               const float2* src, int src_r,
                                               float2* dst, const float2* twl,
@@ -84,6 +151,60 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
     // the two children's slots differ by 2^(j-1) slots whatever the unit,
     // so x offsets fold the child in: xo = c 2^(j-1) RS + s VT + col
     const int cstride = (1 << (j - 1)) * RS;
+    if constexpr (PREC != BF_FP32) {
+        // K = 2 r_in <= 32: one 16x16x32 product per (chain, split term)
+        using SP = Split<PREC>;
+        typename SP::v8 ahi, alo;
+        int xo8[8], wo8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            const bool v = k < K;
+            const int c = (v && k >= r_in) ? 1 : 0;
+            const int s = v ? k - c * r_in : 0;
+            xo8[e] = c * cstride + s * VT + col;
+            wo8[e] = c * r_in + s;
+            const bool av = v && tA < r_out;
+            const int mi = (c * r_out + (av ? tA : 0)) * r_in + s;
+            SP::bits8(ahi, e, av ? lv.mats_hi[mi] : (uint16_t)0);
+            SP::bits8(alo, e, av ? lv.mats_lo[mi] : (uint16_t)0);
+        }
+        const int ntiles = (a.Gk + CPT - 1) / CPT;
+        const int DS = a.rmax * VT;
+        for (int tau = wave; tau < ntiles; tau += nwaves) {
+            int ui = tau * CPT + sub;
+            const bool ok = ui < a.Gk;
+            if (!ok) ui = 0;
+            const int unit = ui >> 1, i = ui & 1;
+            const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
+            const int rv = digit_rev(apl, j - 1, 1);
+            const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS;
+            const float2* wp = twl + (unit * 4 + i * 2) * r_in;
+            typename SP::v8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float2 x = xp[xo8[e]], w = wp[wo8[e]];
+                SP::put8(rh, rl, e, w.x * x.x - w.y * x.y);
+                SP::put8(ih, il, e, w.x * x.y + w.y * x.x);
+            }
+            floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+            accr = SP::mma32(ahi, rh, accr);
+            acci = SP::mma32(ahi, ih, acci);
+            accr = SP::mma32(ahi, rl, accr);
+            acci = SP::mma32(ahi, il, acci);
+            accr = SP::mma32(alo, rh, accr);
+            acci = SP::mma32(alo, ih, acci);
+            if (ok) {
+                float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int t = 4 * g + jj;
+                    if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
+                }
+            }
+        }
+        return;
+    }
     float aM[8];
     int xo[8], wo[8];
 #pragma unroll
@@ -135,7 +256,7 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
 
 // One x level: src -> dst, or (last level of a tail pass) added into tacc,
 // whose lane mapping is the same on every sub-iteration.
-template <int VT>
+template <int VT, int PREC>
 __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                                              const float2* src, float2* dst,
                                              const float2* twl, int j,
@@ -151,6 +272,85 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     constexpr int UPT = 16 / VT;             // units per tile
     const int sub = n / VT, col = n & (VT - 1);
     const int RS = a.rmax * VT;
+    if constexpr (PREC != BF_FP32) {
+        // K = r_in <= 16: one 16x16x16 product per (child i, chain, term)
+        using SP = Split<PREC>;
+        typename SP::v4 ahi[2], alo[2];
+        int xo4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int s = 4 * g + e;
+            const bool v = s < r_in;
+            xo4[e] = (v ? s : 0) * VT + col;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bool av = v && tA < r_out;
+                const int mi = (i * r_out + (av ? tA : 0)) * r_in + (v ? s : 0);
+                SP::bits4(ahi[i], e, av ? lv.mats_hi[mi] : (uint16_t)0);
+                SP::bits4(alo[i], e, av ? lv.mats_lo[mi] : (uint16_t)0);
+            }
+        }
+        const int nunits = a.Gk >> 1;
+        const int ntiles = (nunits + UPT - 1) / UPT;
+#pragma unroll
+        for (int m = 0; m < kWaveTiles / 2; ++m) {
+            const int tau = wave + m * nwaves;
+            if (tau >= ntiles) break;
+            int unit = tau * UPT + sub;
+            const bool ok = unit < nunits;
+            if (!ok) unit = 0;
+            const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
+            const int rv = digit_rev(apl, j - 1, 1);
+            const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS;
+            const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
+            typename SP::v4 r0h, r0l, i0h, i0l, r1h, r1l, i1h, i1l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float2 x0 = xp0[xo4[e]], x1 = xp1[xo4[e]];
+                SP::put4(r0h, r0l, e, x0.x);
+                SP::put4(i0h, i0l, e, x0.y);
+                SP::put4(r1h, r1l, e, x1.x);
+                SP::put4(i1h, i1l, e, x1.y);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                floatx4 y0r = SP::mma16(ahi[i], r0h, z), y0i = SP::mma16(ahi[i], i0h, z);
+                floatx4 y1r = SP::mma16(ahi[i], r1h, z), y1i = SP::mma16(ahi[i], i1h, z);
+                y0r = SP::mma16(ahi[i], r0l, y0r);
+                y0i = SP::mma16(ahi[i], i0l, y0i);
+                y1r = SP::mma16(ahi[i], r1l, y1r);
+                y1i = SP::mma16(ahi[i], i1l, y1i);
+                y0r = SP::mma16(alo[i], r0h, y0r);
+                y0i = SP::mma16(alo[i], i0h, y0i);
+                y1r = SP::mma16(alo[i], r1h, y1r);
+                y1i = SP::mma16(alo[i], i1h, y1i);
+                const float2* tp = twl + (unit * 4 + i * 2) * r_out;
+                floatx4 orr, oii;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    int t = 4 * g + jj;
+                    if (t >= r_out) t = 0;
+                    const float2 T0 = tp[t];
+                    const float2 T1 = tp[r_out + t];
+                    orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
+                    oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
+                }
+                if (to_tail) {
+                    tacc[4 * m + 2 * i] += orr;
+                    tacc[4 * m + 2 * i + 1] += oii;
+                } else if (ok) {
+                    float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int t = 4 * g + jj;
+                        if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
+                    }
+                }
+            }
+        }
+        return;
+    }
     float aM[2][4];
     int xo[4];
 #pragma unroll
@@ -248,17 +448,35 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
         so[kk] = ((s < r_in ? s : 0) * VT + colc) * 2 + reim;
     }
     const float2* S0 = a.S + (size_t)((a0 << shiftB) + bfix) * r_out * r_in;
-    for (int slot = wave; slot < a.Gk; slot += nwaves) {
+    // issue every S load of this wave's pairs first (one memory latency
+    // for the whole switch instead of one per pair)
+    constexpr int kPairs = kMfmaTileCap / (kMfmaThreads / 64);
+    for (int r0 = 0; r0 < a.Gk; r0 += kPairs * nwaves) {   // rounds of pairs
+    float2 svall[kPairs][4];
+#pragma unroll
+    for (int m = 0; m < kPairs; ++m) {
+        const int slot = r0 + wave + m * nwaves;
+        if (slot >= a.Gk) break;
         const unsigned dA = (unsigned)digit_rev(slot, a.k, 1);
         const float2* S = S0 + (dA << shiftB) * (unsigned)(r_out * r_in);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            if (kk >= nks) break;
+            const int s = 4 * kk + g;
+            svall[m][kk] = sv_ok[kk] ? S[tA * r_in + s] : make_float2(0.f, 0.f);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kPairs; ++m) {
+        const int slot = r0 + wave + m * nwaves;
+        if (slot >= a.Gk) break;
         const int base = slot * a.rmax * VT * 2;
         float2 sv[4];
         float bv[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             if (kk >= nks) break;
-            const int s = 4 * kk + g;
-            sv[kk] = sv_ok[kk] ? S[tA * r_in + s] : make_float2(0.f, 0.f);
+            sv[kk] = svall[m][kk];
             bv[kk] = tf[base + so[kk]];
         }
         floatx4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
@@ -276,18 +494,24 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
             if (col < VT && t < r_out) tf[base + (t * VT + col) * 2 + reim] = v;
         }
     }
+    }   // rounds
     __syncthreads();
 }
 
 // LDS of an MFMA pass: tiles[2] (Gk x rmax x VT), twiddles[2] (2 Gk rmax),
 // then the f tile (Gk x head_r x VT) when the pass starts from f.
-template <int VT>
+template <int VT, int PREC>
 __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
-    const size_t tsz = (size_t)a.Gk * a.rmax * VT, wsz = (size_t)2 * a.Gk * a.rmax;
-    float2* tiles[2] = {lds, lds + tsz};
-    float2* twl[2] = {lds + 2 * tsz, lds + 2 * tsz + wsz};
-    float2* ftile = lds + 2 * tsz + 2 * wsz;
+    // every LDS pointer below is lds + offset, selected with ternaries (not
+    // an array of pointers) so the compiler keeps them in the LDS address
+    // space and emits ds_read / ds_write
+    const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
+    float2* const T0 = lds;
+    float2* const T1 = lds + tsz;
+    float2* const W0 = lds + 2 * tsz;
+    float2* const W1 = lds + 2 * tsz + wsz;
+    float2* const ftile = lds + 2 * tsz + 2 * wsz;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
@@ -301,34 +525,36 @@ __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-            load_tile(a, tiles[0], p0, a.lv[0].r_in, chunk);
+            load_tile(a, T0, p0, a.lv[0].r_in, chunk);
         }
-        stage_twiddles(a, 1, twl[0], ap_grp, bg, true);
+        stage_twiddles(a, 1, W0, ap_grp, bg, true);
         __syncthreads();
-        const float2* src = a.has_head ? ftile : tiles[0];
-        int src_r = a.has_head ? a.head_r : a.rmax;
-        int out = a.has_head ? 0 : 1;
+        // level j reads the f tile (j = 1 with the head) or the tile the
+        // previous level wrote, and writes the other tile
+        const int flip = a.has_head ? 0 : 1;
         for (int j = 1; j <= a.k; ++j) {
-            if (j < a.k) stage_twiddles(a, j + 1, twl[j & 1], ap_grp, bg, true);
-            mfma_xi_level<VT>(a, src, src_r, tiles[out], twl[(j - 1) & 1], j);
+            if (j < a.k) stage_twiddles(a, j + 1, (j & 1) ? W1 : W0, ap_grp, bg, true);
+            const bool dst1 = ((j - 1 + flip) & 1) != 0;
+            const float2* src = (j == 1) ? (a.has_head ? ftile : T0) : (dst1 ? T0 : T1);
+            const int src_r = (j == 1 && a.has_head) ? a.head_r : a.rmax;
+            mfma_xi_level<VT, PREC>(a, src, src_r, dst1 ? T1 : T0, (j & 1) ? W0 : W1, j);
             __syncthreads();
-            src = tiles[out];
-            src_r = a.rmax;
-            out ^= 1;
         }
-        float2* cur = tiles[out ^ 1];
+        float2* cur = (((a.k - 1 + flip) & 1) != 0) ? T1 : T0;
         if (a.has_switch) mfma_switch<VT>(a, cur, ap_grp * a.Gk, bg);
         store_tile(a, cur, ap_grp * a.Gk, bg, chunk);
         __syncthreads();
     }
 }
 
-template <int VT>
+template <int VT, int PREC>
 __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
-    const size_t tsz = (size_t)a.Gk * a.rmax * VT, wsz = (size_t)2 * a.Gk * a.rmax;
-    float2* tiles[2] = {lds, lds + tsz};
-    float2* twl[2] = {lds + 2 * tsz, lds + 2 * tsz + wsz};
+    const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
+    float2* const T0 = lds;
+    float2* const T1 = lds + tsz;
+    float2* const W0 = lds + 2 * tsz;
+    float2* const W1 = lds + 2 * tsz + wsz;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
@@ -341,26 +567,26 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-        load_tile(a, tiles[0], p0, a.lv[0].r_in, chunk);
-        stage_twiddles(a, 1, twl[0], ap_grp, bg, false);
+        load_tile(a, T0, p0, a.lv[0].r_in, chunk);
+        stage_twiddles(a, 1, W0, ap_grp, bg, false);
         __syncthreads();
-        int out = 1;
+        // level j reads T0 (j odd) or T1 and writes the other
         for (int j = 1; j <= a.k; ++j) {
-            if (j < a.k) stage_twiddles(a, j + 1, twl[j & 1], ap_grp, bg, false);
-            mfma_x_level<VT>(a, tiles[out ^ 1], tiles[out], twl[(j - 1) & 1], j,
+            if (j < a.k) stage_twiddles(a, j + 1, (j & 1) ? W1 : W0, ap_grp, bg, false);
+            const bool odd = (j & 1) != 0;
+            mfma_x_level<VT, PREC>(a, odd ? T0 : T1, odd ? T1 : T0, odd ? W0 : W1, j,
                              a.has_tail && j == a.k, tacc);
             __syncthreads();
-            out ^= 1;
         }
         if (!a.has_tail) {
-            store_tile(a, tiles[out ^ 1], ap_grp * a.Gk, bg, chunk);
+            store_tile(a, (a.k & 1) ? T1 : T0, ap_grp * a.Gk, bg, chunk);
             __syncthreads();
         }
     }
     if (!a.has_tail) return;
     // final coefficients of the Gk boxes A to LDS as [a_loc][t][VT], then
     // g_v(x) = sum_k a_k(x) lambda_k(x) (eq. (eqn:tg))
-    float2* fin = tiles[0];
+    float2* fin = T0;
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int nwaves = blockDim.x >> 6;
@@ -425,25 +651,25 @@ size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     return e * sizeof(float2);
 }
 
-template <int VT>
+template <int VT, int PREC>
 static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st) {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT>,
+        (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
-        (void)hipFuncSetAttribute((const void*)x_pass_mfma<VT>,
+        (void)hipFuncSetAttribute((const void*)x_pass_mfma<VT, PREC>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
         attr = true;
     }
     const long long nblocks = a.nspatial * a.nchunk;
     if (is_xi)
-        hipLaunchKernelGGL(xi_pass_mfma<VT>, dim3((unsigned)nblocks),
+        hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
                            dim3(kMfmaThreads), lds, st, a);
     else
-        hipLaunchKernelGGL(x_pass_mfma<VT>, dim3((unsigned)nblocks),
+        hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
                            dim3(kMfmaThreads), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -451,14 +677,25 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
     return "";
 }
 
+template <int PREC>
+static std::string launch_prec(const PassArgs& a, bool is_xi, size_t lds,
+                               hipStream_t st) {
+    switch (a.Vt) {
+        case 1: return launch_vt<1, PREC>(a, is_xi, lds, st);
+        case 2: return launch_vt<2, PREC>(a, is_xi, lds, st);
+        case 4: return launch_vt<4, PREC>(a, is_xi, lds, st);
+        case 8: return launch_vt<8, PREC>(a, is_xi, lds, st);
+        default: return "MFMA pass: tile width must be 1, 2, 4 or 8";
+    }
+}
+
 std::string launch_mfma_pass(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st) {
-    switch (a.Vt) {
-        case 1: return launch_vt<1>(a, is_xi, lds, st);
-        case 2: return launch_vt<2>(a, is_xi, lds, st);
-        case 4: return launch_vt<4>(a, is_xi, lds, st);
-        case 8: return launch_vt<8>(a, is_xi, lds, st);
-        default: return "MFMA pass: tile width must be 1, 2, 4 or 8";
+    switch (a.prec) {
+        case BF_FP32: return launch_prec<BF_FP32>(a, is_xi, lds, st);
+        case BF_BF16X3: return launch_prec<BF_BF16X3>(a, is_xi, lds, st);
+        case BF_FP16X3: return launch_prec<BF_FP16X3>(a, is_xi, lds, st);
+        default: return "MFMA pass: unknown precision";
     }
 }
 

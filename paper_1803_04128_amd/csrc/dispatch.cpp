@@ -42,6 +42,8 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     while (chunk > 1 && 2 * state_bytes(p, chunk) > ws_bytes) --chunk;
     if (2 * state_bytes(p, chunk) > ws_bytes)
         return "workspace too small for one vector";
+    if (!p.fused && p.precision != BF_FP32)
+        return "split precision needs the fused passes (BF_FUSED=0 given)";
     const float2* f = (const float2*)fv;
     float2* g = (float2*)gv;
     for (int v0 = 0; v0 < nvec; v0 += chunk) {

@@ -27,12 +27,15 @@ constexpr int kMfmaTileCap = 64;
 struct PassLevel {
     const float2* tw;
     const float* mats;
+    const uint16_t* mats_hi;   // 16-bit hi/lo parts (split precisions)
+    const uint16_t* mats_lo;
     int r_in, r_out, level;
 };
 
 struct PassArgs {
     PassLevel lv[kMaxPassLevels];
     int k, Gk, la, L, n, dim;
+    int prec;                 // BF_FP32, BF_BF16X3 or BF_FP16X3
     long long N;
     int Vs, Vt, nchunk, r_amp;
     int rmax;                 // coefficient slots per pair in the tile

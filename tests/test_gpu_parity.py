@@ -184,3 +184,38 @@ def test_apply_rejects_overlap_and_bad_nvec():
         with pytest.raises(bfm.BfError):
             pl.apply(torch.zeros((3, 1024), dtype=torch.complex64,
                                  device="cuda"))
+
+
+# split precisions: hi + lo parts represent each operand to 2^-18 (bfloat16)
+# or 2^-22 (half) relative; over the ~13 contraction steps of these plans the
+# errors add to a few 1e-5 (BF16) or 1e-6 (FP16).  The bars are stated
+# against the FP64 oracle butterfly on the same points.
+SPLIT_TOL = {"bf16x3": 1e-4, "fp16x3": 1e-5}
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("n,q,r,nvec", [(4096, 10, 4, 3), (1 << 14, 8, 1, 2),
+                                        (1 << 13, 10, 2, 5)])
+def test_split_precision_accuracy(apply_path, precision, n, q, r, nvec):
+    if apply_path != "fused":
+        pytest.skip("split precisions run on the fused MFMA passes only")
+    log(f"case split {precision} n={n} q={q} r={r} nvec={nvec}")
+    amp = "sincos" if r > 1 else "one"
+    f32, f, ab = inputs(1, n, nvec, 950 + r, amp=amp, r=r)
+    with _plan(1, n, "fio1d", q, ab=ab, nvec=nvec, precision=precision) as pl:
+        g, _ = gpu_apply(pl, f32)
+    if ab is None:
+        ref = butterfly_apply(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, f)
+    else:
+        ref = butterfly_matvec(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, ab[0],
+                               ab[1], f)
+    err = np.max(rel(g, ref))
+    log(f"  {precision} rel err vs FP64 butterfly = {err:.3e}")
+    assert err < SPLIT_TOL[precision]
+
+
+def test_split_precision_rejected_where_not_built(apply_path):
+    import paper_1803_04128_amd as bfm
+    with pytest.raises(bfm.BfError):
+        bfm.Plan(2, 64, "radon2d", PHASE_PARAMS["radon2d"], q=7,
+                 precision="bf16x3")

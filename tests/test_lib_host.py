@@ -102,3 +102,10 @@ def test_no_device_is_an_error_not_a_crash():
     rc, h = _plan_rc()
     assert rc in (_lib.BF_EHIP, _lib.BF_ENOMEM)
     assert not h.value
+
+
+def test_split_precision_2d_unsupported_before_device_use():
+    rc, h = _plan_rc(dim=2, n=16, kind=2, params=(2, 1, 16, 2, 1, 16), q=7,
+                     prec=1)
+    assert rc == _lib.BF_EUNSUPPORTED
+    assert not h.value
