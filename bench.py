@@ -97,7 +97,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fio1d_n262144_batched",
-                    choices=sorted(WORKLOADS))
+                    choices=sorted(WORKLOADS) + ["serving"],
+                    help="'serving': the continuous-batching server on the "
+                         "mixed request stream (its own JSON line)")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="serving: requests per load level")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the execution forms first and keep the "
+                         "fastest (bf_autotune)")
     ap.add_argument("--precision", default=None,
                     choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--nvec", type=int, default=None,
@@ -113,6 +120,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU "
               "path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
@@ -147,6 +158,9 @@ def main():
     plan_s = time.perf_counter() - t0
     info = plan.info()
 
+    tune = None
+    if args.autotune:
+        tune = plan.autotune(f, out=g, reps=2)
     for _ in range(args.warmup):
         plan.apply(f, out=g)
     torch.cuda.synchronize()
@@ -183,7 +197,7 @@ def main():
     traffic = traffic_from_profiles(args.workload, precision, name)
     if ai >= ridge:
         achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu" if precision == "fp32" else "mfma",
+        roof = {"bound": "mfma" if "mfma" in name else "alu",
                 "achieved": achieved, "peak": peak_c, "unit": unit_c,
                 "frac": achieved / peak_c, "traffic": traffic}
     else:
@@ -219,7 +233,10 @@ def main():
                         "ms_per_launch": v["total_ms"] / v["launches"]}
                     for k, v in kstats.items()},
         "roofline": roof,
+        "exec": plan.config(),
     }
+    if tune is not None:
+        out["autotune"] = tune
     if not args.no_cpu_baseline:
         g_host = g[:1].cpu().numpy().astype(np.complex128)
         rep, err = cpu_baseline(w, f64.astype(np.complex64).astype(
@@ -227,6 +244,87 @@ def main():
         out["cpu_baseline"] = rep
         out["rel_err_vs_oracle"] = err
     plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving: 13 resident plans (1D FIO N = 2^12..2^20 with r = 1, 2 or
+    4; 2D Radon n = 64..256), a seeded request mix with 1..32 vectors per
+    request.  First every request arrives at once (saturation throughput),
+    then Poisson arrivals at 0.5x, 0.8x and 1.2x that request rate; each
+    level reports p50/p99 latency from arrival to completion on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_1803_04128_amd.serving import (PlanSpec, Request, Server,
+                                              summarize)
+    from synthetic import (PHASE_PARAMS, SERVING_SHAPES, amplitude_factors,
+                           gaussian_vectors, serving_requests)
+
+    max_batch = 32
+    srv = Server(hbm_budget_bytes=96 << 30, max_batch=max_batch)
+    pools, Ns = [], {}
+    for i, ((dim, n, phase, amp, r, q), _) in enumerate(SERVING_SHAPES):
+        ab = None
+        if amp != "one":
+            ab = amplitude_factors(amp, dim, n, r, 11)
+        name = f"s{i}"
+        srv.register(name, PlanSpec(dim, n, phase, PHASE_PARAMS[phase], q=q,
+                                    amplitude=ab))
+        Ns[name] = n ** dim
+        f = torch.from_numpy(gaussian_vectors(n ** dim, max_batch, 40 + i)
+                             .astype(np.complex64)).to("cuda")
+        pools.append((f, torch.empty_like(f)))
+    # plans are resident before the clock starts (built once, reused)
+    t0 = time.perf_counter()
+    for i in range(len(SERVING_SHAPES)):
+        rp = srv.cache.get(f"s{i}")
+        rp.plan.apply(pools[i][0], out=pools[i][1])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+
+    def stream(rate, seed):
+        out = []
+        for k, (t, i, nv) in enumerate(serving_requests(args.requests, seed,
+                                                        rate)):
+            f, g = pools[i]
+            out.append(Request(k, f"s{i}", f[:nv], t, out=g[:nv]))
+        return out
+
+    levels = {}
+    sat = summarize(srv.run(stream(None, 4)), Ns.get)
+    rate_sat = sat["served"] / sat["span_s"]
+    levels["saturation"] = dict(sat, rate_rps=rate_sat)
+    print(json.dumps({"level": "saturation", **levels["saturation"]}),
+          file=sys.stderr, flush=True)
+    for frac in (0.5, 0.8, 1.2):
+        st = summarize(srv.run(stream(frac * rate_sat, 4)), Ns.get)
+        levels[f"{frac}x"] = dict(st, rate_rps=frac * rate_sat)
+        print(json.dumps({"level": frac, **st}), file=sys.stderr, flush=True)
+    sizes = [nv for _, nv in srv.batches]
+    out = {
+        "metric": "serving: N·nvec/s at saturation",
+        "value": sat["throughput"],
+        "unit": "N·nvec/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": sat["span_s"] * 1e3 / max(1, sat["served"]),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving_mix", "plans": len(SERVING_SHAPES),
+                   "requests_per_level": args.requests,
+                   "max_batch": max_batch},
+        "levels": levels,
+        "batches": len(sizes),
+        "mean_batch_vectors": float(np.mean(sizes)) if sizes else 0.0,
+        "resident_plan_bytes": srv.cache.resident_bytes,
+        "plan_build_s": build_s,
+    }
+    srv.close()
     print(json.dumps(out), flush=True)
 
 

@@ -156,10 +156,85 @@ typedef struct bf_plan_info {
 
 int bf_query(bf_plan_t plan, bf_plan_info* info);
 
+/* ---- execution form ------------------------------------------------------
+ * How an apply is issued; every form computes the same Algorithm 4.1 and
+ * agrees to FP32 rounding (the split precisions exist on BF_PATH_FUSED only).
+ * BF_PATH_FUSED:      level-fused passes, one kernel per group of levels:
+ *                     the state of a radix-2^k group of pairs stays in LDS
+ *                     across k levels (and the switch), so HBM sees it once
+ *                     per pass; 1D plans with r in {1, 2, 4, 8} contract on
+ *                     MFMA, the others on the vector ALU.
+ * BF_PATH_FUSED_VALU: the same passes on the vector ALU only.
+ * BF_PATH_PER_STEP:   one kernel per computed level (state through HBM).
+ * The initial form is BF_PATH_FUSED with the default tile width, unless the
+ * environment variables BF_FUSED=0, BF_MFMA=0 or BF_TILE_COLS=<w> are set
+ * when the plan is built; a plan whose fused passes do not fit starts with
+ * BF_PATH_PER_STEP.                                                        */
+#define BF_PATH_FUSED       0
+#define BF_PATH_FUSED_VALU  1
+#define BF_PATH_PER_STEP    2
+
+typedef struct bf_config {
+    int path;            /* BF_PATH_* */
+    int tile_cols;       /* columns per fused tile: 0 = default (about 8),
+                            else a multiple of r, <= 64; the MFMA passes
+                            round it down to a power of two that fits   */
+    int tile_cols_used;  /* out (bf_get_config, bf_autotune): the width
+                            the passes use for a full chunk; 0 per step */
+} bf_config;
+
+/* Current execution form of the plan. */
+int bf_get_config(bf_plan_t plan, bf_config* cfg);
+
+/* Makes cfg the plan's execution form (synchronous; tile_cols_used is
+ * ignored).  Grows the plan's default workspace when the form needs more
+ * (bf_workspace_bytes reports the new size).  Returns BF_EINVAL for an
+ * unknown path or a bad width, BF_EUNSUPPORTED when the form cannot run
+ * this plan (a pass does not fit the LDS, or a split precision off the
+ * MFMA passes; the plan is then unchanged), BF_EBUSY while graphs captured
+ * from the plan exist.                                                    */
+int bf_set_config(bf_plan_t plan, const bf_config* cfg);
+
+/* Autotuner: times every candidate execution form on the caller's buffers
+ * (f, g as for bf_apply, nvec vectors, on stream): one warm-up apply, then
+ * reps timed applies (hipEvents), and makes the fastest the plan's form.
+ * Candidates: BF_PATH_FUSED and BF_PATH_FUSED_VALU at tile widths r * 2^j
+ * <= 16, and BF_PATH_PER_STEP; out (capacity cap) receives one entry per
+ * candidate with its mean milliseconds per apply, -1 when the form cannot
+ * run the plan, -2 when it resolves to kernels already timed; *count
+ * receives the number of candidates.  Synchronous; allocates a temporary
+ * workspace; g holds the result of the last timed form.  BF_EBUSY while
+ * graphs captured from the plan exist.                                     */
+typedef struct bf_tune_entry {
+    bf_config config;
+    double ms;
+} bf_tune_entry;
+
+int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
+                void* stream, bf_tune_entry* out, int cap, int* count);
+
+/* ---- captured applies (HIP graphs) --------------------------------------
+ * bf_graph_create records the kernels of bf_apply(plan, nvec, f, g) into an
+ * executable HIP graph (captured on a private stream; nothing runs), bound
+ * to f, g and the plan's default workspace.  bf_graph_launch replays it on
+ * stream: the same computation as bf_apply with one launch call, for small
+ * problems where launch overhead dominates.  Replays and bf_apply share the
+ * workspace, so they must not overlap.  The graph holds no memset node.
+ * While a graph exists the plan cannot be reconfigured or destroyed
+ * (BF_EBUSY).  bf_graph_destroy synchronises the device first; NULL is
+ * accepted.                                                                */
+typedef struct bf_graph_s* bf_graph_t;
+
+int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
+                    bf_graph_t* out);
+int bf_graph_launch(bf_graph_t graph, void* stream);
+int bf_graph_destroy(bf_graph_t graph);
+
 /* ---- kernel timing (diagnostics) ---------------------------------------
  * bf_profile(plan, 1): every later apply of this plan records a hipEvent
  * pair around each kernel launch it issues, on the apply stream (at most
- * 65536 launches are kept; later ones are not timed).  bf_profile(plan, 0)
+ * 4096 launches are kept until the next bf_profile_read; later ones are not
+ * timed, and launches inside a graph capture never are).  bf_profile(plan, 0)
  * stops recording.  bf_profile_read synchronises the recorded events and
  * returns one entry per kernel class: launches, total milliseconds, and the
  * algorithmic bytes (inputs, outputs and factors each counted once) and

@@ -13,9 +13,9 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BfError, PHASES, PRECISIONS  # noqa: F401
+from ._lib import BfError, PATHS, PHASES, PRECISIONS  # noqa: F401
 
-__all__ = ["Plan", "BfError", "points", "lagrange", "load"]
+__all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load"]
 
 
 def load():
@@ -98,19 +98,27 @@ class Plan:
         s = stream if stream is not None else torch.cuda.current_stream()
         return C.c_void_p(s.cuda_stream)
 
-    def apply(self, f, out=None, stream=None, workspace=None):
-        """g = K f for a complex64 CUDA tensor f [nvec][N] (or [N]).
-        Asynchronous on ``stream`` (default: torch's current stream)."""
+    def _args(self, f, out):
         import torch
         if not (f.is_cuda and f.dtype == torch.complex64):
             raise TypeError("f must be a complex64 CUDA tensor")
-        squeeze = f.dim() == 1
-        f2 = f.reshape(1, -1) if squeeze else f
+        f2 = f.reshape(1, -1) if f.dim() == 1 else f
         if f2.shape[-1] != self.N or not f2.is_contiguous():
             raise ValueError("f must be contiguous with N entries per vector")
         if out is None:
             out = torch.empty_like(f2)
-        nvec = f2.shape[0]
+        elif out.dim() == 1:
+            out = out.reshape(1, -1)
+        if out.shape != f2.shape or out.dtype != f2.dtype or \
+                not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 like f")
+        return f2, out, f2.shape[0]
+
+    def apply(self, f, out=None, stream=None, workspace=None):
+        """g = K f for a complex64 CUDA tensor f [nvec][N] (or [N]).
+        Asynchronous on ``stream`` (default: torch's current stream)."""
+        squeeze = f.dim() == 1
+        f2, out, nvec = self._args(f, out)
         st = self._stream(stream)
         if workspace is None:
             _lib.check(self._lib.bf_apply(self._h, nvec, C.c_void_p(
@@ -121,6 +129,38 @@ class Plan:
                 C.c_void_p(out.data_ptr()), C.c_void_p(workspace.data_ptr()),
                 workspace.numel() * workspace.element_size(), st))
         return out.reshape(-1) if squeeze else out
+
+    def config(self):
+        """Execution form: {"path", "tile_cols", "tile_cols_used"}."""
+        c = _lib.BfConfig()
+        _lib.check(self._lib.bf_get_config(self._h, C.byref(c)))
+        names = {v: k for k, v in PATHS.items()}
+        return dict(path=names[c.path], tile_cols=c.tile_cols,
+                    tile_cols_used=c.tile_cols_used)
+
+    def set_config(self, path="fused", tile_cols=0):
+        c = _lib.BfConfig(PATHS[path], int(tile_cols), 0)
+        _lib.check(self._lib.bf_set_config(self._h, C.byref(c)))
+
+    def autotune(self, f, out=None, reps=3, stream=None):
+        """Time the candidate execution forms on f (bf_autotune) and keep
+        the fastest; returns the candidates with their ms per apply."""
+        f2, out, nvec = self._args(f, out)
+        cap = 32
+        arr = (_lib.BfTuneEntry * cap)()
+        cnt = C.c_int()
+        _lib.check(self._lib.bf_autotune(
+            self._h, nvec, C.c_void_p(f2.data_ptr()),
+            C.c_void_p(out.data_ptr()), int(reps), self._stream(stream), arr,
+            cap, C.byref(cnt)))
+        names = {v: k for k, v in PATHS.items()}
+        return [dict(path=names[e.config.path], tile_cols=e.config.tile_cols,
+                     tile_cols_used=e.config.tile_cols_used, ms=e.ms)
+                for e in arr[:min(cnt.value, cap)]]
+
+    def graph(self, f, out=None):
+        """Capture the apply on f into a replayable HIP graph."""
+        return Graph(self, f, out)
 
     def profile(self, enable=True):
         """Start (or stop) per-launch event timing inside the library."""
@@ -143,6 +183,42 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(self._lib.bf_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Graph:
+    """A captured apply (bf_graph_create): replays K f for the tensors it was
+    built with, in one launch call.  Keep f and out alive while it exists."""
+
+    def __init__(self, plan, f, out=None):
+        self._lib = plan._lib
+        self.plan = plan
+        self.f, self.out, nvec = plan._args(f, out)
+        self._h = C.c_void_p()
+        _lib.check(self._lib.bf_graph_create(
+            plan._h, nvec, C.c_void_p(self.f.data_ptr()),
+            C.c_void_p(self.out.data_ptr()), C.byref(self._h)))
+
+    def launch(self, stream=None):
+        _lib.check(self._lib.bf_graph_launch(self._h,
+                                             Plan._stream(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(self._lib.bf_graph_destroy(self._h))
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -45,9 +45,23 @@ class BfKernelStat(C.Structure):
                 ("flops", C.c_double)]
 
 
+PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2}
+
+
+class BfConfig(C.Structure):
+    _fields_ = [("path", C.c_int), ("tile_cols", C.c_int),
+                ("tile_cols_used", C.c_int)]
+
+
+class BfTuneEntry(C.Structure):
+    _fields_ = [("config", BfConfig), ("ms", C.c_double)]
+
+
 EXPORTS = ["bf_plan", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
-           "bf_lagrange", "bf_profile", "bf_profile_read"]
+           "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
+           "bf_set_config", "bf_autotune", "bf_graph_create",
+           "bf_graph_launch", "bf_graph_destroy"]
 
 _lib = None
 
@@ -94,6 +108,15 @@ def load():
     lib.bf_profile.argtypes = [C.c_void_p, C.c_int]
     lib.bf_profile_read.argtypes = [C.c_void_p, P(BfKernelStat), C.c_int,
                                     P(C.c_int)]
+    lib.bf_get_config.argtypes = [C.c_void_p, P(BfConfig)]
+    lib.bf_set_config.argtypes = [C.c_void_p, P(BfConfig)]
+    lib.bf_autotune.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                C.c_int, C.c_void_p, P(BfTuneEntry), C.c_int,
+                                P(C.c_int)]
+    lib.bf_graph_create.argtypes = [C.c_void_p, C.c_int, C.c_void_p,
+                                    C.c_void_p, P(C.c_void_p)]
+    lib.bf_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+    lib.bf_graph_destroy.argtypes = [C.c_void_p]
     for name in EXPORTS:
         getattr(lib, name).restype = (C.c_char_p if name == "bf_last_error"
                                       else C.c_int)

@@ -37,6 +37,62 @@ struct bf_plan_s {
     unsigned magic = 0xbf00bf00u;
 };
 
+struct bf_graph_s {
+    bf_plan_s* plan = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned magic = 0xbf09bf09u;
+};
+
+namespace {
+
+int path_of(const bfi::Plan& p) {
+    if (!p.fused) return BF_PATH_PER_STEP;
+    return p.mfma ? BF_PATH_FUSED : BF_PATH_FUSED_VALU;
+}
+
+void put_path(bfi::Plan& p, int path, int tile_cols) {
+    p.fused = path != BF_PATH_PER_STEP;
+    p.mfma = path == BF_PATH_FUSED;
+    p.tile_cols = tile_cols;
+}
+
+// Validates cfg against the plan and makes it current; the default workspace
+// grows when the new form needs more.  On failure the plan is unchanged.
+int apply_config(bfi::Plan& p, const bf_config& cfg) {
+    if (cfg.path != BF_PATH_FUSED && cfg.path != BF_PATH_FUSED_VALU &&
+        cfg.path != BF_PATH_PER_STEP)
+        return fail(BF_EINVAL, "bf_set_config: unknown path");
+    if (cfg.tile_cols < 0 || cfg.tile_cols > 64 ||
+        (cfg.tile_cols > 0 && cfg.tile_cols % p.r_amp != 0))
+        return fail(BF_EINVAL,
+                    "bf_set_config: tile_cols must be 0 or a multiple of r "
+                    "up to 64");
+    const bool f0 = p.fused, m0 = p.mfma;
+    const int t0 = p.tile_cols;
+    put_path(p, cfg.path, cfg.tile_cols);
+    std::string err = bfi::check_config(p);
+    if (!err.empty()) {
+        p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+        return fail(BF_EUNSUPPORTED, "bf_set_config: " + err);
+    }
+    const size_t need = bfi::workspace_bytes(p, p.max_nvec);
+    if (need > p.ws_bytes) {
+        void* nw = nullptr;
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMalloc(&nw, need) != hipSuccess) {
+            (void)hipGetLastError();
+            p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+            return fail(BF_ENOMEM, "bf_set_config: workspace allocation");
+        }
+        (void)hipFree(p.ws);
+        p.ws = nw;
+        p.ws_bytes = need;
+    }
+    return BF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bf_last_error(void) { return g_last_error.c_str(); }
@@ -123,8 +179,13 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     p.phase.dim = dim;
     p.phase.n = n;
     for (int i = 0; i < need; ++i) p.phase.p[i] = phase->params[i];
+    // initial execution form (bf_set_config / bf_autotune change it later)
     const char* fenv = std::getenv("BF_FUSED");
     p.fused = fenv ? std::atoi(fenv) != 0 : true;
+    const char* menv = std::getenv("BF_MFMA");
+    p.mfma = menv ? std::atoi(menv) != 0 : true;
+    const char* tenv = std::getenv("BF_TILE_COLS");
+    p.tile_cols = tenv ? std::max(0, std::atoi(tenv)) : 0;
     if (hipGetDevice(&p.device) != hipSuccess) {
         delete h;
         return fail(BF_EHIP, "bf_plan: no HIP device");
@@ -147,6 +208,16 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
         delete h;
         return fail(BF_ENOMEM, "bf_plan: plan exceeds BF_MEM_CAP_BYTES");
     }
+    if (bfi::check_config(p) != "") {
+        // the configured fused passes do not fit this plan
+        if (precision != BF_FP32) {
+            std::string why = bfi::check_config(p);
+            delete h;
+            return fail(BF_EUNSUPPORTED, "bf_plan: " + why);
+        }
+        p.fused = false;
+    }
+    bfi::init_kernel_attrs();
     err = bfi::build_factors(p);
     if (err.empty() && p.has_amp) err = bfi::upload_amplitude(p, a, b);
     if (err.empty()) {
@@ -222,6 +293,8 @@ int bf_destroy(bf_plan_t plan) {
     if (!plan) return BF_OK;
     if (int e = check_plan(plan)) return e;
     bfi::Plan& p = plan->p;
+    if (p.graphs > 0)
+        return fail(BF_EBUSY, "bf_destroy: captured graphs still use the plan");
     int rc = BF_OK;
     if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
     if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
@@ -303,13 +376,199 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
     info->first_xi_level = p.l0;
     info->last_x_level = p.l1;
     info->n_steps = (int)p.steps.size();
-    info->n_passes = p.fused ? (int)p.passes.size() : (int)p.steps.size() + 1;
+    info->n_passes = p.fused ? bfi::fused_pass_count(p, p.chunk_nvec * p.r_amp)
+                             : (int)p.steps.size() + 1;
     info->max_rank = p.max_rank;
     info->chunk_nvec = p.chunk_nvec;
     info->factor_bytes = p.arena_bytes;
     info->workspace_bytes = p.ws_bytes;
     info->flops_per_column = p.flops_per_column;
     info->factor_stream_bytes = p.factor_stream_bytes;
+    return BF_OK;
+}
+
+int bf_get_config(bf_plan_t plan, bf_config* cfg) {
+    if (int e = check_plan(plan)) return e;
+    if (!cfg) return fail(BF_EINVAL, "bf_get_config: NULL cfg");
+    const bfi::Plan& p = plan->p;
+    cfg->path = path_of(p);
+    cfg->tile_cols = p.tile_cols;
+    cfg->tile_cols_used =
+        p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
+    return BF_OK;
+}
+
+int bf_set_config(bf_plan_t plan, const bf_config* cfg) {
+    if (int e = check_plan(plan)) return e;
+    if (!cfg) return fail(BF_EINVAL, "bf_set_config: NULL cfg");
+    if (plan->p.graphs > 0)
+        return fail(BF_EBUSY, "bf_set_config: captured graphs use the plan");
+    return apply_config(plan->p, *cfg);
+}
+
+int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
+                void* stream, bf_tune_entry* out, int cap, int* count) {
+    if (int e = check_apply(plan, nvec, f, g)) return e;
+    if (reps < 1 || !count || (cap > 0 && !out))
+        return fail(BF_EINVAL, "bf_autotune: bad argument");
+    bfi::Plan& p = plan->p;
+    if (p.graphs > 0)
+        return fail(BF_EBUSY, "bf_autotune: captured graphs use the plan");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+        return fail(BF_EINVAL, "bf_autotune: plan belongs to another device");
+    hipStream_t st = (hipStream_t)stream;
+    // candidates: both fused forms at tile widths r * 2^j <= 16, and the
+    // per-step launches; forms that resolve to the same kernels are timed once
+    std::vector<bf_config> cand;
+    for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
+        for (int tc = p.r_amp; tc <= 16; tc *= 2) cand.push_back({path, tc, 0});
+    cand.push_back({BF_PATH_PER_STEP, 0, 0});
+    const bool f0 = p.fused, m0 = p.mfma;
+    const int t0 = p.tile_cols;
+    std::vector<bf_tune_entry> res;
+    std::vector<std::pair<int, int>> seen;   // (path, tile width) timed
+    size_t ws_need = 0;
+    for (auto& c : cand) {
+        put_path(p, c.path, c.tile_cols);
+        bf_tune_entry e{};
+        e.config = c;
+        e.ms = -1.0;
+        if (bfi::check_config(p).empty()) {
+            e.config.tile_cols_used =
+                p.fused ? bfi::fused_tile_cols(p, std::min(nvec, p.chunk_nvec) *
+                                                      p.r_amp)
+                        : 0;
+            // 2D plans (and r not a power of two) have no MFMA passes: the
+            // fused form is then the vector-ALU one
+            const bool mf = p.fused && p.mfma && p.dim == 1 &&
+                            (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
+            const int key = !p.fused ? 2 : (mf ? 0 : 1);
+            std::pair<int, int> k{key, e.config.tile_cols_used};
+            bool dup = false;
+            for (auto& s2 : seen) dup |= s2 == k;
+            if (!dup) {
+                seen.push_back(k);
+                e.ms = 0.0;   // to be timed
+                ws_need = std::max(ws_need, bfi::workspace_bytes(p, nvec));
+            } else {
+                e.ms = -2.0;
+            }
+        }
+        res.push_back(e);
+    }
+    void* ws = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::string err;
+    if (hipMalloc(&ws, std::max<size_t>(ws_need, 256)) != hipSuccess)
+        err = "workspace allocation";
+    if (err.empty() && (hipEventCreate(&e0) != hipSuccess ||
+                        hipEventCreate(&e1) != hipSuccess))
+        err = "event creation";
+    const bool prof0 = p.prof.on;
+    p.prof.on = false;
+    int best = -1;
+    for (size_t i = 0; i < res.size() && err.empty(); ++i) {
+        if (res[i].ms != 0.0) continue;
+        put_path(p, res[i].config.path, res[i].config.tile_cols);
+        err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);   // warm-up
+        if (!err.empty()) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { err = "event record"; break; }
+        for (int k = 0; k < reps && err.empty(); ++k)
+            err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);
+        float ms = 0.f;
+        if (err.empty() && (hipEventRecord(e1, st) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            err = "event timing";
+        if (!err.empty()) break;
+        res[i].ms = ms / reps;
+        if (best < 0 || res[i].ms < res[best].ms) best = (int)i;
+    }
+    p.prof.on = prof0;
+    if (ws) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(ws);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+    if (!err.empty()) {
+        (void)hipGetLastError();
+        return fail(BF_EHIP, "bf_autotune: " + err);
+    }
+    *count = (int)res.size();
+    for (int i = 0; i < (int)res.size() && i < cap; ++i) out[i] = res[i];
+    if (best < 0) return fail(BF_EUNSUPPORTED, "bf_autotune: no candidate ran");
+    bf_config chosen = res[best].config;
+    chosen.tile_cols_used = 0;
+    return apply_config(p, chosen);
+}
+
+int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
+                    bf_graph_t* out) {
+    if (!out) return fail(BF_EINVAL, "bf_graph_create: out is NULL");
+    *out = nullptr;
+    if (int e = check_apply(plan, nvec, f, g)) return e;
+    bfi::Plan& p = plan->p;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+        return fail(BF_EINVAL, "bf_graph_create: plan belongs to another device");
+    bf_graph_s* gr = new (std::nothrow) bf_graph_s();
+    if (!gr) return fail(BF_ENOMEM, "bf_graph_create: host allocation");
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    std::string err;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        err = "stream creation";
+    else if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) !=
+             hipSuccess)
+        err = "begin capture";
+    else {
+        p.capturing = true;
+        std::string aerr = bfi::launch_apply(p, nvec, f, g, p.ws, p.ws_bytes, cs);
+        p.capturing = false;
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (!aerr.empty()) err = aerr;
+        else if (ee != hipSuccess || !graph) err = "end capture";
+        else if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) !=
+                 hipSuccess)
+            err = "graph instantiation";
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!err.empty()) {
+        (void)hipGetLastError();
+        delete gr;
+        return fail(BF_EHIP, "bf_graph_create: " + err);
+    }
+    gr->plan = plan;
+    ++p.graphs;
+    *out = gr;
+    return BF_OK;
+}
+
+int bf_graph_launch(bf_graph_t graph, void* stream) {
+    if (!graph || graph->magic != 0xbf09bf09u)
+        return fail(BF_EINVAL, "invalid graph handle");
+    if (hipGraphLaunch(graph->exec, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BF_EHIP, "bf_graph_launch: hipGraphLaunch failed");
+    }
+    return BF_OK;
+}
+
+int bf_graph_destroy(bf_graph_t graph) {
+    if (!graph) return BF_OK;
+    if (graph->magic != 0xbf09bf09u)
+        return fail(BF_EINVAL, "invalid graph handle");
+    int rc = BF_OK;
+    if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
+    if (hipGraphExecDestroy(graph->exec) != hipSuccess) rc = BF_EHIP;
+    --graph->plan->p.graphs;
+    graph->magic = 0;
+    delete graph;
+    if (rc != BF_OK) return fail(rc, "bf_graph_destroy: HIP error");
     return BF_OK;
 }
 

@@ -362,11 +362,9 @@ static int count_kind(const Plan& p, int kind) {
 }
 
 // MFMA passes serve 1D plans whose tile width is a power of two <= 8
-// (BF_MFMA=0 forces the vector-ALU passes).
+// (a plan configured without MFMA uses the vector-ALU passes).
 static bool mfma_mode(const Plan& p, int Vt) {
-    static const char* env = std::getenv("BF_MFMA");
-    if (env && std::atoi(env) == 0) return false;
-    return p.dim == 1 && pow2_le8(Vt) && pow2_le8(p.r_amp);
+    return p.mfma && p.dim == 1 && pow2_le8(Vt) && pow2_le8(p.r_amp);
 }
 
 // Columns per tile: a multiple of the amplitude rank (the final sums
@@ -374,10 +372,9 @@ static bool mfma_mode(const Plan& p, int Vt) {
 // MFMA passes the width is a power of two, lowered (not below r) until the
 // larger half of the levels fits one pass (Gk * Vt <= 512).
 int fused_tile_cols(const Plan& p, int Vs) {
-    // BF_TILE_COLS overrides the width (a multiple of r; tuning experiments)
-    static const char* env = std::getenv("BF_TILE_COLS");
+    // a configured width (a multiple of r) replaces the default of about 8
     int tv = std::max(1, 8 / p.r_amp);
-    if (env && std::atoi(env) >= p.r_amp) tv = std::atoi(env) / p.r_amp;
+    if (p.tile_cols >= p.r_amp) tv = p.tile_cols / p.r_amp;
     int vt = std::min(tv * p.r_amp, Vs);
     if (p.dim == 1 && pow2_le8(p.r_amp)) {
         int v2 = 1;
@@ -479,11 +476,17 @@ std::vector<Pass> plan_passes(const Plan& p, int Vt) {
     return out;
 }
 
+int fused_pass_count(const Plan& p, int Vs) {
+    return (int)plan_passes(p, fused_tile_cols(p, Vs)).size();
+}
+
 size_t fused_state_bytes(const Plan& p, int Vs) {
     const int Vt = fused_tile_cols(p, Vs);
     const int nchunk = (Vs + Vt - 1) / Vt;
     return (size_t)p.N * p.max_rank * (size_t)nchunk * Vt * sizeof(float2);
 }
+
+void init_mfma_attrs();
 
 template <int R, int TB, int MAXIT>
 static void set_lds_limit() {
@@ -498,8 +501,18 @@ static void set_lds_limit() {
     done = true;
 }
 
+// Raise the dynamic LDS limit of every pass kernel once, before any launch
+// (so that a graph capture records launches only).
+void init_kernel_attrs() {
+    set_lds_limit<2, 16, 2>();
+    set_lds_limit<4, 32, 2>();
+    init_mfma_attrs();
+}
+
+// dry: check every pass of the configuration (LDS, tile caps, grid) and
+// launch nothing.
 std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
-                      float2* buf0, float2* buf1, hipStream_t st) {
+                      float2* buf0, float2* buf1, hipStream_t st, bool dry) {
     const int Vs = nv * p.r_amp;
     const int Vt = fused_tile_cols(p, Vs);
     const int nchunk = (Vs + Vt - 1) / Vt;
@@ -651,6 +664,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             lds = mfma_pass_lds(a, is_xi);
             if (lds > 160 * 1024) return "MFMA pass does not fit in LDS";
         }
+        if (dry) continue;
         ProfScope prof(p, st);
         const char* name;
         if (use_mfma) {

@@ -652,18 +652,36 @@ size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
 }
 
 template <int VT, int PREC>
+static void set_attrs() {
+    static bool attr = false;
+    if (attr) return;
+    (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)x_pass_mfma<VT, PREC>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+}
+
+template <int PREC>
+static void set_attrs_prec() {
+    set_attrs<1, PREC>();
+    set_attrs<2, PREC>();
+    set_attrs<4, PREC>();
+    set_attrs<8, PREC>();
+}
+
+void init_mfma_attrs() {
+    set_attrs_prec<BF_FP32>();
+    set_attrs_prec<BF_BF16X3>();
+    set_attrs_prec<BF_FP16X3>();
+}
+
+template <int VT, int PREC>
 static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        (void)hipFuncSetAttribute((const void*)x_pass_mfma<VT, PREC>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr = true;
-    }
+    set_attrs<VT, PREC>();
     const long long nblocks = a.nspatial * a.nchunk;
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),

@@ -116,7 +116,6 @@ struct Plan {
     int head_step_side = 1;   // side of the boxes the first step reads f over
     int tail_side = 1;        // side of the T_X boxes summed in the tail
     std::vector<Step> steps;
-    std::vector<Pass> passes;
     int max_rank = 1;
     // device memory
     void* arena = nullptr;
@@ -129,6 +128,10 @@ struct Plan {
     int chunk_nvec = 1;
     int device = 0;
     bool fused = true;        // level-fused passes (else one launch per step)
+    bool mfma = true;         // fused passes may use the MFMA kernels
+    int tile_cols = 0;        // fused tile width override (0: heuristic)
+    int graphs = 0;           // live captured graphs bound to ws
+    bool capturing = false;   // inside a graph capture (no event records)
     double flops_per_column = 0;
     double factor_stream_bytes = 0;
     Profiler prof;
@@ -156,6 +159,11 @@ std::string upload_amplitude(Plan& p, const double* a, const double* b);
 std::string launch_apply(Plan& p, int nvec, const void* f, void* g, void* ws,
                          size_t ws_bytes, hipStream_t stream);
 size_t workspace_bytes(const Plan& p, int nvec);
+std::string check_config(Plan& p);   // "" when every pass fits
+// apply_fused.hip
+int fused_tile_cols(const Plan& p, int Vs);
+int fused_pass_count(const Plan& p, int Vs);
+void init_kernel_attrs();
 
 // tiny helpers
 inline int ilog2(long long v) {

@@ -7,7 +7,9 @@
 namespace bfi {
 
 ProfScope::ProfScope(Plan& pl, hipStream_t s) : p(pl), st(s) {
-    if (!p.prof.on || p.prof.used + 2 > (int)p.prof.pool.size()) return;
+    if (!p.prof.on || p.capturing ||
+        p.prof.used + 2 > (int)p.prof.pool.size())
+        return;
     ev0 = p.prof.used++;
     if (hipEventRecord(p.prof.pool[ev0], st) != hipSuccess) ev0 = -1;
 }
@@ -20,7 +22,7 @@ void ProfScope::end(const std::string& name, double bytes, double flops) {
 }
 
 std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
-                      float2* buf0, float2* buf1, hipStream_t st);
+                      float2* buf0, float2* buf1, hipStream_t st, bool dry);
 size_t fused_state_bytes(const Plan& p, int Vs);
 
 // Two ping-pong state buffers of N * max_rank * (nv * r) complex64 each
@@ -43,7 +45,7 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     if (2 * state_bytes(p, chunk) > ws_bytes)
         return "workspace too small for one vector";
     if (!p.fused && p.precision != BF_FP32)
-        return "split precision needs the fused passes (BF_FUSED=0 given)";
+        return "split precision needs the fused passes";
     const float2* f = (const float2*)fv;
     float2* g = (float2*)gv;
     for (int v0 = 0; v0 < nvec; v0 += chunk) {
@@ -52,9 +54,23 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
         float2* b1 = (float2*)((char*)ws + state_bytes(p, nv));
         std::string err =
             p.fused ? run_fused(p, nv, f + (size_t)v0 * p.N,
-                                g + (size_t)v0 * p.N, b0, b1, st)
+                                g + (size_t)v0 * p.N, b0, b1, st, false)
                     : run_basic(p, nv, f + (size_t)v0 * p.N,
                                 g + (size_t)v0 * p.N, b0, b1, st);
+        if (!err.empty()) return err;
+    }
+    return "";
+}
+
+std::string check_config(Plan& p) {
+    if (p.precision != BF_FP32 && !p.fused)
+        return "split precision needs the fused passes";
+    if (!p.fused) return "";
+    // every chunk width the applies can take: the full chunk and a tail
+    const int widths[2] = {p.chunk_nvec, 1};
+    for (int nv : widths) {
+        std::string err = run_fused(p, nv, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, true);
         if (!err.empty()) return err;
     }
     return "";

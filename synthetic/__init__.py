@@ -13,4 +13,10 @@ from .inputs import (  # noqa: F401
     amplitude_factors,
     orthogonal_mix,
 )
-from .configs import CONFIGS, PHASE_PARAMS, Workload  # noqa: F401
+from .configs import (  # noqa: F401
+    CONFIGS,
+    PHASE_PARAMS,
+    Workload,
+    SERVING_SHAPES,
+    serving_requests,
+)

@@ -73,3 +73,41 @@ CONFIGS = {
                                      "fio1d", "sincos", 4, 10, 256, seed=3,
                                      rows=1024, row_seed=103),
 }
+
+
+# Serving mix: plan shapes (dim, n, phase, amplitude, r, q) and their weights
+# in the request stream; smaller transforms are requested more often.
+SERVING_SHAPES = (
+    ((1, 1 << 12, "fio1d", "one", 1, 8), 6),
+    ((1, 1 << 12, "fio1d", "sincos", 4, 8), 4),
+    ((1, 1 << 14, "fio1d", "one", 1, 8), 5),
+    ((1, 1 << 14, "fio1d", "sincos", 2, 8), 4),
+    ((1, 1 << 16, "fio1d", "one", 1, 8), 4),
+    ((1, 1 << 16, "fio1d", "sincos", 4, 8), 3),
+    ((1, 1 << 18, "fio1d", "one", 1, 8), 2),
+    ((1, 1 << 18, "fio1d", "sincos", 2, 8), 2),
+    ((1, 1 << 20, "fio1d", "one", 1, 8), 1),
+    ((1, 1 << 20, "fio1d", "sincos", 2, 8), 1),
+    ((2, 64, "radon2d", "one", 1, 7), 3),
+    ((2, 128, "radon2d", "one", 1, 7), 2),
+    ((2, 256, "radon2d", "one", 1, 7), 1),
+)
+SERVING_NVEC = (1, 2, 4, 8, 16, 32)
+SERVING_NVEC_WEIGHTS = (8, 6, 4, 3, 2, 1)
+
+
+def serving_requests(count, seed, rate=None, shapes=SERVING_SHAPES):
+    """Request stream: [(arrival_s, shape_index, nvec)], Poisson arrivals at
+    ``rate`` requests/s (all at t = 0 when rate is None), shapes and vector
+    counts drawn with the weights above (PCG64, ``seed``)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    w = np.array([s[1] for s in shapes], float)
+    kinds = rng.choice(len(shapes), size=count, p=w / w.sum())
+    wv = np.array(SERVING_NVEC_WEIGHTS, float)
+    nv = rng.choice(SERVING_NVEC, size=count, p=wv / wv.sum())
+    if rate is None:
+        t = np.zeros(count)
+    else:
+        t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    return [(float(t[i]), int(kinds[i]), int(nv[i])) for i in range(count)]

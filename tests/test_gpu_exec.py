@@ -1,0 +1,161 @@
+"""GPU tests of the execution forms: configuration (fused MFMA, fused vector
+ALU, one launch per step), the autotuner, and captured HIP graphs.  Every
+form must reproduce the oracle's butterfly to the FP32 bar; a graph replay
+must reproduce the eager apply of the same form bit for bit, replay after
+replay, with other device work between the replays."""
+
+import numpy as np
+import pytest
+
+from _util import inputs, rel, log
+from oracle.butterfly import butterfly_matvec, butterfly_apply
+from synthetic import PHASE_PARAMS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _bfm():
+    import paper_1803_04128_amd as bfm
+    return bfm
+
+
+def _to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def test_default_config_and_forms_agree_with_oracle():
+    bfm = _bfm()
+    n, q, nvec = 4096, 10, 2
+    log(f"case forms n={n} q={q}")
+    f32, f, ab = inputs(1, n, nvec, 31, amp="sincos", r=4)
+    ref = butterfly_matvec(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, ab[0],
+                           ab[1], f)
+    with bfm.Plan(1, n, "fio1d", PHASE_PARAMS["fio1d"], q=q, amplitude=ab,
+                  max_nvec=nvec) as pl:
+        c = pl.config()
+        assert c["path"] == "fused" and c["tile_cols"] == 0
+        assert c["tile_cols_used"] == 8
+        assert pl.info()["n_passes"] == 2
+        ft = _to_dev(f32)
+        for path, tc in [("fused", 4), ("fused", 8), ("fused_valu", 4),
+                         ("fused_valu", 8), ("per_step", 0)]:
+            pl.set_config(path, tc)
+            assert pl.config()["path"] == path
+            g = _host(pl.apply(ft))
+            err = np.max(rel(g, ref))
+            log(f"  {path} tile {tc}: rel {err:.2e}")
+            assert err < TOL, (path, tc)
+        assert pl.info()["n_passes"] == pl.info()["n_steps"] + 1
+
+
+def test_set_config_rejects_bad_forms():
+    bfm = _bfm()
+    with bfm.Plan(1, 1024, "fio1d", PHASE_PARAMS["fio1d"], q=8,
+                  amplitude=inputs(1, 1024, 1, 1, amp="sincos", r=4)[2],
+                  max_nvec=2) as pl:
+        for path, tc in [("fused", 3), ("fused", -4), ("fused", 68)]:
+            with pytest.raises(bfm.BfError) as ei:
+                pl.set_config(path, tc)
+            assert ei.value.code == bfm._lib.BF_EINVAL
+        assert pl.config()["path"] == "fused"
+    with bfm.Plan(1, 1024, "fio1d", PHASE_PARAMS["fio1d"], q=8,
+                  precision="bf16x3") as pl:
+        for path in ["per_step", "fused_valu"]:
+            with pytest.raises(bfm.BfError) as ei:
+                pl.set_config(path)
+            assert ei.value.code == bfm._lib.BF_EUNSUPPORTED
+        assert pl.config()["path"] == "fused"
+
+
+@pytest.mark.parametrize("dim,n,kind,q,nvec,amp,r", [
+    (1, 16384, "fio1d", 10, 4, "sincos", 4),
+    (1, 8192, "dft", 8, 3, "one", 1),
+    (2, 64, "radon2d", 5, 2, "one", 1),
+])
+def test_autotune_picks_a_timed_form(dim, n, kind, q, nvec, amp, r):
+    bfm = _bfm()
+    log(f"case autotune dim={dim} n={n} kind={kind}")
+    f32, f, ab = inputs(dim, n, nvec, 41, amp=amp, r=r)
+    with bfm.Plan(dim, n, kind, PHASE_PARAMS[kind], q=q, amplitude=ab,
+                  max_nvec=nvec) as pl:
+        ft = _to_dev(f32)
+        g0 = _host(pl.apply(ft))
+        res = pl.autotune(ft, reps=2)
+        for e in res:
+            log("  ", e)
+        timed = [e for e in res if e["ms"] > 0]
+        assert timed and any(e["path"] == "per_step" for e in timed)
+        best = min(timed, key=lambda e: e["ms"])
+        c = pl.config()
+        assert c["path"] == best["path"]
+        assert c["tile_cols"] == best["tile_cols"]
+        g1 = _host(pl.apply(ft))
+        assert np.max(rel(g1, g0)) < 2 * TOL
+    if dim == 1 and n <= 8192:
+        ref = butterfly_apply(dim, n, kind, PHASE_PARAMS[kind], q, f)
+        assert np.max(rel(g1, ref)) < TOL
+
+
+@pytest.mark.parametrize("dim,n,kind,q,nvec,path", [
+    (1, 1024, "fio1d", 8, 1, "fused"),
+    (1, 1024, "fio1d", 8, 3, "per_step"),
+    (1, 65536, "fio1d", 10, 2, "fused"),
+    (2, 64, "radon2d", 7, 2, "fused"),
+])
+def test_graph_replays_match_eager(dim, n, kind, q, nvec, path):
+    import torch
+    bfm = _bfm()
+    log(f"case graph dim={dim} n={n} nvec={nvec} path={path}")
+    rng = np.random.default_rng(7)
+    with bfm.Plan(dim, n, kind, PHASE_PARAMS[kind], q=q,
+                  max_nvec=nvec) as pl:
+        pl.set_config(path)
+        f32, f, _ = inputs(dim, n, nvec, 51)
+        fin = _to_dev(f32)
+        gout = torch.zeros_like(fin)
+        gr = pl.graph(fin, gout)
+        try:
+            for rep in range(4):
+                # new data in the bound input buffer, then other device
+                # work, an eager apply, and a synchronisation
+                x = (rng.standard_normal(fin.shape) +
+                     1j * rng.standard_normal(fin.shape)).astype(np.complex64)
+                fin.copy_(_to_dev(x))
+                eager = pl.apply(fin)
+                junk = torch.randn(1 << 20, device="cuda").sum()
+                torch.cuda.synchronize()
+                gr.launch()
+                torch.cuda.synchronize()
+                assert torch.equal(gout, eager), rep
+                assert float(junk) == float(junk)
+                if rep == 0:
+                    ref = butterfly_apply(dim, n, kind, PHASE_PARAMS[kind], q,
+                                          x.astype(np.complex128))
+                    assert np.max(rel(_host(gout), ref)) < TOL
+            # the plan cannot change under a live graph
+            with pytest.raises(bfm.BfError) as ei:
+                pl.set_config("per_step")
+            assert ei.value.code == bfm._lib.BF_EBUSY
+        finally:
+            gr.close()
+        pl.set_config("per_step")
+
+
+def test_plan_destroy_waits_for_graphs():
+    bfm = _bfm()
+    import torch
+    pl = bfm.Plan(1, 256, "dft", (), q=4)
+    fin = torch.zeros(256, dtype=torch.complex64, device="cuda")
+    gr = pl.graph(fin)
+    with pytest.raises(bfm.BfError) as ei:
+        pl.close()
+    assert ei.value.code == bfm._lib.BF_EBUSY
+    gr.close()
+    pl.close()

@@ -1,0 +1,128 @@
+"""GPU serving loop: every request's result in the mixed, batched stream is
+bit-identical to applying it alone with the same plan, also when a tight HBM
+budget forces plans out of the cache and back; one result is checked
+against the oracle."""
+
+import numpy as np
+import pytest
+
+from _util import inputs, rel, log
+from oracle.butterfly import butterfly_matvec
+from synthetic import PHASE_PARAMS, amplitude_factors
+
+pytestmark = pytest.mark.gpu
+
+SPECS = {
+    "fio4096": (1, 4096, "fio1d", 8, None),
+    "fio2048_r4": (1, 2048, "fio1d", 8, ("sincos", 4)),
+    "radon32": (2, 32, "radon2d", 7, None),
+}
+MAX_BATCH = 8
+
+
+def _spec(name):
+    from paper_1803_04128_amd.serving import PlanSpec
+    dim, n, kind, q, amp = SPECS[name]
+    ab = None
+    if amp:
+        ab = amplitude_factors(amp[0], dim, n, amp[1], 11)
+        ab = tuple(x.astype(np.complex64).astype(np.complex128) for x in ab)
+    return PlanSpec(dim, n, kind, PHASE_PARAMS[kind], q=q, amplitude=ab)
+
+
+def _requests(count, seed, rate):
+    import torch
+    from paper_1803_04128_amd.serving import Request
+    rng = np.random.default_rng(seed)
+    names = list(SPECS)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    out = []
+    for i in range(count):
+        name = names[rng.integers(len(names))]
+        N = SPECS[name][1] ** SPECS[name][0]
+        nv = int(rng.integers(1, 5))
+        f32, _, _ = inputs(1, N, nv, 1000 + i)
+        out.append(Request(i, name, torch.from_numpy(f32).to("cuda"),
+                           float(t[i])))
+    return out
+
+
+def _alone(reqs):
+    """Each request applied on its own through a fresh plan."""
+    import paper_1803_04128_amd as bfm
+    ref = {}
+    for name in SPECS:
+        s = _spec(name)
+        with bfm.Plan(s.dim, s.n, s.phase, s.params, q=s.q,
+                      amplitude=s.amplitude, max_nvec=MAX_BATCH) as pl:
+            for r in reqs:
+                if r.plan == name:
+                    ref[r.rid] = pl.apply(r.f).cpu().numpy()
+    return ref
+
+
+@pytest.mark.parametrize("budget_plans", [3, 1])
+def test_batched_stream_matches_single_applies(budget_plans):
+    import torch
+    from paper_1803_04128_amd.serving import Server, summarize
+    log(f"case serving budget_plans={budget_plans}")
+    reqs = _requests(80, 5, rate=4000.0)
+    ref = _alone(reqs)
+    srv = Server(hbm_budget_bytes=1 << 40, max_batch=MAX_BATCH)
+    for name in SPECS:
+        srv.register(name, _spec(name))
+    if budget_plans == 1:
+        # room for the largest plan alone: every change of plan evicts
+        sizes = []
+        for name in SPECS:
+            rp = srv._build(name)
+            sizes.append(rp.footprint)
+            rp.close()
+        srv.cache.budget = max(sizes) + 1
+    try:
+        done = srv.run(reqs)
+        torch.cuda.synchronize()
+        for r in done:
+            assert r.error is None, r.error
+            assert r.done is not None and r.done >= r.arrival - 1e-3
+            assert np.array_equal(r.out.cpu().numpy(), ref[r.rid]), r.rid
+        sizes = [n for _, n in srv.batches]
+        assert max(sizes) > 4 and len(sizes) < len(reqs)
+        if budget_plans == 1:
+            assert srv.cache.evictions > 0
+        st = summarize(done, lambda n: SPECS[n][1] ** SPECS[n][0])
+        log(f"  {st} batches={len(sizes)} evictions={srv.cache.evictions}")
+        assert st["served"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+    finally:
+        srv.close()
+    # one request against the oracle's butterfly
+    r = next(x for x in done if x.plan == "fio2048_r4")
+    s = _spec("fio2048_r4")
+    f = r.f.cpu().numpy().astype(np.complex128)
+    g = butterfly_matvec(1, 2048, "fio1d", PHASE_PARAMS["fio1d"], 8,
+                         s.amplitude[0], s.amplitude[1], f)
+    assert np.max(rel(r.out.cpu().numpy().astype(np.complex128), g)) < 1e-5
+
+
+def test_plan_over_budget_fails_its_requests_only():
+    from paper_1803_04128_amd.serving import Server
+    reqs = _requests(30, 6, rate=2000.0)
+    srv = Server(hbm_budget_bytes=1 << 40, max_batch=MAX_BATCH)
+    for name in SPECS:
+        srv.register(name, _spec(name))
+    sizes = {}
+    for name in SPECS:
+        x = srv._build(name)
+        sizes[name] = x.footprint
+        x.close()
+    srv.cache.budget = min(sizes.values()) + 1   # the smallest plan only
+    try:
+        done = srv.run(reqs)
+        for r in done:
+            if sizes[r.plan] > srv.cache.budget:
+                assert r.error is not None and r.out is not None
+            else:
+                assert r.error is None and r.done is not None
+        assert any(r.error for r in done) and any(not r.error for r in done)
+    finally:
+        srv.close()

@@ -1,0 +1,116 @@
+"""Host logic of the serving loop (no GPU): batch formation, fairness and
+ordering, HBM-budget admission and LRU eviction, latency statistics."""
+
+import pytest
+import torch
+
+from paper_1803_04128_amd.serving import (AdmissionError, PlanCache, Request,
+                                          Scheduler, summarize)
+from synthetic import serving_requests, SERVING_SHAPES
+
+
+def _req(rid, plan, nvec, t=0.0):
+    return Request(rid, plan, torch.zeros(nvec, 4), t)
+
+
+def test_batches_take_the_oldest_plan_in_order_up_to_capacity():
+    s = Scheduler(max_batch=8)
+    for rid, (plan, nv) in enumerate([("a", 3), ("b", 2), ("a", 4), ("a", 2),
+                                      ("b", 8), ("a", 1)]):
+        s.add(_req(rid, plan, nv, t=rid))
+    name, b = s.next_batch()
+    # a: 3 + 4 fit, 2 does not: the batch ends there (order kept)
+    assert name == "a" and [r.rid for r in b] == [0, 2]
+    name, b = s.next_batch()
+    assert name == "b" and [r.rid for r in b] == [1]
+    name, b = s.next_batch()
+    assert name == "a" and [r.rid for r in b] == [3, 5]
+    name, b = s.next_batch()
+    assert name == "b" and [r.rid for r in b] == [4]
+    assert s.next_batch() is None
+
+
+def test_every_request_is_batched_once_and_per_plan_order_holds():
+    s = Scheduler(max_batch=32)
+    reqs = [_req(i, f"p{k}", nv, t)
+            for i, (t, k, nv) in enumerate(serving_requests(500, 4))]
+    for r in reqs:
+        s.add(r)
+    seen, last = [], {}
+    while True:
+        nb = s.next_batch()
+        if nb is None:
+            break
+        name, batch = nb
+        assert batch and sum(r.nvec for r in batch) <= 32
+        assert all(r.plan == name for r in batch)
+        for r in batch:
+            assert last.get(name, -1) < r.rid
+            last[name] = r.rid
+        seen += [r.rid for r in batch]
+    assert sorted(seen) == list(range(500))
+
+
+def test_oversized_request_is_rejected():
+    s = Scheduler(max_batch=4)
+    with pytest.raises(ValueError):
+        s.add(_req(0, "a", 5))
+
+
+class _Fake:
+    def __init__(self, name, size, log):
+        self.name, self.footprint, self.log = name, size, log
+
+    def close(self):
+        self.log.append(self.name)
+
+
+def test_cache_evicts_least_recently_used_and_refuses_oversized():
+    closed = []
+    sizes = {"a": 40, "b": 30, "c": 50, "huge": 101}
+    cache = PlanCache(100, lambda n: _Fake(n, sizes[n], closed))
+    cache.get("a")
+    cache.get("b")
+    cache.get("a")                        # a is now the most recent
+    cache.get("c")                        # 120 > 100: evict b (LRU)
+    assert closed == ["b"] and cache.names() == ["a", "c"]
+    assert cache.resident_bytes == 90
+    with pytest.raises(AdmissionError):
+        cache.get("huge")
+    assert closed[-1] == "huge" and cache.names() == ["a", "c"]
+    # pinned plans are never evicted
+    with pytest.raises(AdmissionError):
+        cache.get("b", pinned={"a", "c"})
+    assert cache.names() == ["a", "c"]
+    cache.get("b", pinned={"c"})          # evicts a only
+    assert cache.names() == ["c", "b"] and cache.evictions == 2
+    cache.clear()
+    assert cache.resident_bytes == 0
+
+
+def test_summary_statistics():
+    reqs = []
+    for i in range(100):
+        r = _req(i, "a", 2, t=i * 0.01)
+        r.done = r.arrival + (i + 1) * 1e-3
+        reqs.append(r)
+    bad = _req(100, "a", 1)
+    bad.error = "refused"
+    s = summarize(reqs + [bad], lambda name: 1000)
+    assert s["served"] == 100 and s["failed"] == 1
+    assert abs(s["p50_ms"] - 50.5) < 1e-9
+    assert abs(s["p99_ms"] - 99.01) < 1e-9
+    span = 0.99 + 0.1
+    assert abs(s["throughput"] - 100 * 2 * 1000 / span) < 1e-6
+
+
+def test_request_stream_is_seeded_and_weighted():
+    a = serving_requests(2000, 4, rate=100.0)
+    b = serving_requests(2000, 4, rate=100.0)
+    assert a == b
+    t = [x[0] for x in a]
+    assert all(t[i] < t[i + 1] for i in range(len(t) - 1))
+    assert 15 < t[-1] < 25                 # about 2000 / 100 s
+    kinds = [x[1] for x in a]
+    assert set(kinds) == set(range(len(SERVING_SHAPES)))
+    assert kinds.count(0) > kinds.count(8)  # weights 6 vs 1
