@@ -165,14 +165,19 @@ int bf_query(bf_plan_t plan, bf_plan_info* info);
  *                     per pass; 1D plans with r in {1, 2, 4, 8} contract on
  *                     MFMA, the others on the vector ALU.
  * BF_PATH_FUSED_VALU: the same passes on the vector ALU only.
- * BF_PATH_PER_STEP:   one kernel per computed level (state through HBM).
- * The initial form is BF_PATH_FUSED with the default tile width, unless the
- * environment variables BF_FUSED=0, BF_MFMA=0 or BF_TILE_COLS=<w> are set
- * when the plan is built; a plan whose fused passes do not fit starts with
- * BF_PATH_PER_STEP.                                                        */
-#define BF_PATH_FUSED       0
-#define BF_PATH_FUSED_VALU  1
-#define BF_PATH_PER_STEP    2
+ * BF_PATH_PER_STEP:   one kernel per computed level (state through HBM),
+ *                     vector ALU.
+ * BF_PATH_PER_STEP_MFMA: one kernel per computed level with the level's
+ *                     shared-matrix and switch contractions on MFMA (ranks
+ *                     up to 64: the 2D form).
+ * The initial form is BF_PATH_FUSED (1D) or BF_PATH_PER_STEP_MFMA (2D) with
+ * the default tile width; the environment variables BF_FUSED=0|1, BF_MFMA=0
+ * and BF_TILE_COLS=<w>, read when the plan is built, override it.  A plan
+ * whose fused passes do not fit starts with one launch per step.           */
+#define BF_PATH_FUSED          0
+#define BF_PATH_FUSED_VALU     1
+#define BF_PATH_PER_STEP       2
+#define BF_PATH_PER_STEP_MFMA  3
 
 typedef struct bf_config {
     int path;            /* BF_PATH_* */
@@ -199,7 +204,7 @@ int bf_set_config(bf_plan_t plan, const bf_config* cfg);
  * (f, g as for bf_apply, nvec vectors, on stream): one warm-up apply, then
  * reps timed applies (hipEvents), and makes the fastest the plan's form.
  * Candidates: BF_PATH_FUSED and BF_PATH_FUSED_VALU at tile widths r * 2^j
- * <= 16, and BF_PATH_PER_STEP; out (capacity cap) receives one entry per
+ * <= 16, BF_PATH_PER_STEP and BF_PATH_PER_STEP_MFMA; out (capacity cap) receives one entry per
  * candidate with its mean milliseconds per apply, -1 when the form cannot
  * run the plan, -2 when it resolves to kernels already timed; *count
  * receives the number of candidates.  Synchronous; allocates a temporary

@@ -45,7 +45,7 @@ class BfKernelStat(C.Structure):
                 ("flops", C.c_double)]
 
 
-PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2}
+PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2, "per_step_mfma": 3}
 
 
 class BfConfig(C.Structure):

@@ -17,7 +17,8 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbf.so")
 
 SOURCES = ["geometry.cpp", "factors.hip", "apply_basic.hip",
-           "apply_fused.hip", "apply_mfma.hip", "dispatch.cpp", "api.cpp"]
+           "apply_fused.hip", "apply_mfma.hip", "apply_step_mfma.hip",
+           "dispatch.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

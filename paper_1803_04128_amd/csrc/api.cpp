@@ -46,13 +46,13 @@ struct bf_graph_s {
 namespace {
 
 int path_of(const bfi::Plan& p) {
-    if (!p.fused) return BF_PATH_PER_STEP;
+    if (!p.fused) return p.mfma ? BF_PATH_PER_STEP_MFMA : BF_PATH_PER_STEP;
     return p.mfma ? BF_PATH_FUSED : BF_PATH_FUSED_VALU;
 }
 
 void put_path(bfi::Plan& p, int path, int tile_cols) {
-    p.fused = path != BF_PATH_PER_STEP;
-    p.mfma = path == BF_PATH_FUSED;
+    p.fused = path == BF_PATH_FUSED || path == BF_PATH_FUSED_VALU;
+    p.mfma = path == BF_PATH_FUSED || path == BF_PATH_PER_STEP_MFMA;
     p.tile_cols = tile_cols;
 }
 
@@ -60,7 +60,7 @@ void put_path(bfi::Plan& p, int path, int tile_cols) {
 // grows when the new form needs more.  On failure the plan is unchanged.
 int apply_config(bfi::Plan& p, const bf_config& cfg) {
     if (cfg.path != BF_PATH_FUSED && cfg.path != BF_PATH_FUSED_VALU &&
-        cfg.path != BF_PATH_PER_STEP)
+        cfg.path != BF_PATH_PER_STEP && cfg.path != BF_PATH_PER_STEP_MFMA)
         return fail(BF_EINVAL, "bf_set_config: unknown path");
     if (cfg.tile_cols < 0 || cfg.tile_cols > 64 ||
         (cfg.tile_cols > 0 && cfg.tile_cols % p.r_amp != 0))
@@ -180,8 +180,11 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     p.phase.n = n;
     for (int i = 0; i < need; ++i) p.phase.p[i] = phase->params[i];
     // initial execution form (bf_set_config / bf_autotune change it later)
+    // default: fused passes in 1D, per-step MFMA launches in 2D (whose
+    // 49- and 64-coefficient blocks the fused passes hold only on the
+    // vector ALU)
     const char* fenv = std::getenv("BF_FUSED");
-    p.fused = fenv ? std::atoi(fenv) != 0 : true;
+    p.fused = fenv ? std::atoi(fenv) != 0 : dim == 1;
     const char* menv = std::getenv("BF_MFMA");
     p.mfma = menv ? std::atoi(menv) != 0 : true;
     const char* tenv = std::getenv("BF_TILE_COLS");
@@ -424,6 +427,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
     for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
         for (int tc = p.r_amp; tc <= 16; tc *= 2) cand.push_back({path, tc, 0});
     cand.push_back({BF_PATH_PER_STEP, 0, 0});
+    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0});
     const bool f0 = p.fused, m0 = p.mfma;
     const int t0 = p.tile_cols;
     std::vector<bf_tune_entry> res;
@@ -443,7 +447,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
             // fused form is then the vector-ALU one
             const bool mf = p.fused && p.mfma && p.dim == 1 &&
                             (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
-            const int key = !p.fused ? 2 : (mf ? 0 : 1);
+            const int key = !p.fused ? (p.mfma ? 3 : 2) : (mf ? 0 : 1);
             std::pair<int, int> k{key, e.config.tile_cols_used};
             bool dup = false;
             for (auto& s2 : seen) dup |= s2 == k;

@@ -193,6 +193,9 @@ static void launch_step_basic(const Step& s, const StepArgs& a,
                            dim3(256), 0, st, a);
 }
 
+std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
+                             hipStream_t st);
+
 std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
                       float2* buf0, float2* buf1, hipStream_t st) {
     const int Vc = nv * p.r_amp;
@@ -221,7 +224,14 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
             name = "switch_basic";
         }
         ProfScope ps(p, st);
-        if (p.dim == 1) {
+        if (p.mfma) {
+            // contractions on MFMA (one launch per step)
+            std::string err = launch_step_mfma(p, s, a, st);
+            if (!err.empty()) return err;
+            name = s.kind == STEP_XI ? "xi_step_mfma"
+                                     : (s.kind == STEP_X ? "x_step_mfma"
+                                                         : "switch_step_mfma");
+        } else if (p.dim == 1) {
             if (p.max_rank <= 16) launch_step_basic<2, 16>(s, a, st);
             else return "1D rank above 16";
         } else {

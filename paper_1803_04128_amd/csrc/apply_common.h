@@ -10,6 +10,7 @@ struct StepArgs {
     float2* out;
     const float2* tw;
     const float* mats;
+    const float* amat;     // mats in MFMA A-operand order (Step::amat)
     const float2* S;
     const float2* f;       // vector chunk [nv][N] (when reads_f)
     const float2* bamp;    // b_k [r][N] or nullptr (alpha = 1)
@@ -58,6 +59,7 @@ inline StepArgs make_step_args(const Plan& p, const Step& s, int Vc,
     a.out = out;
     a.tw = s.tw;
     a.mats = s.mats;
+    a.amat = s.amat;
     a.S = s.S;
     a.f = f;
     a.bamp = p.has_amp ? p.b_dev : nullptr;

@@ -1,0 +1,309 @@
+// One launch per computed step with the contractions on MFMA: the per-level
+// form for plans whose ranks are too large for the fused passes (2D boxes of
+// up to 8 x 8 points, 64 coefficients per pair).
+//
+// Each kernel multiplies real (or complex) r_out x r_in blocks into panels of
+// 16 columns with v_mfma_f32_16x16x4f32.  Operand layout (checked by an
+// in-bounds probe): A lane l = A[l % 16][l / 16], B lane l = B[l / 16][l % 16],
+// D lane l holds D[4 (l / 16) + j][l % 16], j < 4.  The shared Lagrange
+// matrices come pre-arranged in the A order (Step::amat), so every A load is
+// one coalesced 256-byte read; the input panel of a unit is staged in LDS.
+// The state layout and the unit / pair index math are those of the vector
+// ALU per-step kernels.
+#include "apply_common.h"
+
+namespace bfi {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mma(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kCols = 16;      // panel columns per block
+constexpr int kMaxMT = 4;      // row tiles: r_out <= 64
+
+__device__ __forceinline__ floatx4 zero4() {
+    floatx4 z = {0.f, 0.f, 0.f, 0.f};
+    return z;
+}
+
+}  // namespace
+
+// xi step (eq. (eqn:2) regrouped), block = (unit, 16-column tile), wave i =
+// output child i: D_i = sum_c M_c (W_{i,c} . X_c).
+template <int R>
+__global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
+    extern __shared__ float2 lds_step[];
+    float2* xs = lds_step;                              // [R][r_in][16]
+    float2* ws = xs + (size_t)R * a.r_in * kCols;       // [R][R][r_in]
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    const long long u = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const int shiftB = a.dim * (a.L - a.level);
+    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    const int nin = R * a.r_in * kCols;
+    for (int e = threadIdx.x; e < nin; e += R * 64) {
+        const int n = e % kCols, cs = e / kCols;
+        const int c = cs / a.r_in, s = cs - c * a.r_in;
+        const int col = col0 + n;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < a.Vc) {
+            if (a.reads_f) {
+                v = head_value(a, b * R + c, s, col);
+            } else {
+                const long long pin = (ap << (shiftB + a.dim)) + (b << a.dim) + c;
+                v = a.in[(pin * a.r_in + s) * a.Vc + col];
+            }
+        }
+        xs[e] = v;
+    }
+    const int ntw = R * R * a.r_in;
+    for (int e = threadIdx.x; e < ntw; e += R * 64)
+        ws[e] = a.tw[u * ntw + e];
+    __syncthreads();
+    const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, n = lane & 15;
+    const int MT = (a.r_out + 15) >> 4, KS = (a.r_in + 3) >> 2;
+    floatx4 accr[kMaxMT], acci[kMaxMT];
+#pragma unroll
+    for (int m = 0; m < kMaxMT; ++m) accr[m] = acci[m] = zero4();
+    for (int c = 0; c < R; ++c) {
+        const float* am = a.amat + (size_t)c * MT * KS * 64 + lane;
+        const float2* w = ws + (i * R + c) * a.r_in;
+        const float2* x = xs + (size_t)c * a.r_in * kCols + n;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int s = 4 * ks + kq;
+            float2 z = make_float2(0.f, 0.f);
+            if (s < a.r_in) z = cmul(w[s], x[s * kCols]);
+#pragma unroll
+            for (int m = 0; m < kMaxMT; ++m) {
+                if (m < MT) {
+                    const float av = am[(m * KS + ks) * 64];
+                    accr[m] = mma(av, z.x, accr[m]);
+                    acci[m] = mma(av, z.y, acci[m]);
+                }
+            }
+        }
+    }
+    const int col = col0 + n;
+    if (col >= a.Vc) return;
+    const long long pout = ((ap * R + i) << shiftB) + b;
+    float2* o = a.out + pout * a.r_out * a.Vc + col;
+#pragma unroll
+    for (int m = 0; m < kMaxMT; ++m) {
+        if (m < MT) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = 16 * m + 4 * kq + j;
+                if (t < a.r_out)
+                    o[(size_t)t * a.Vc] = make_float2(accr[m][j], acci[m][j]);
+            }
+        }
+    }
+}
+
+// x step (eq. (eqn:3) regrouped), block = (unit, 16-column tile), wave i =
+// output child i: D_i = sum_c T_{i,c} . (M_i X_c).
+template <int R>
+__global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
+    extern __shared__ float2 lds_step[];
+    float2* xs = lds_step;                              // [R][r_in][16]
+    float2* ts = xs + (size_t)R * a.r_in * kCols;       // [R][R][r_out]
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    const long long u = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const int shiftB = a.dim * (a.L - a.level);
+    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    const int nin = R * a.r_in * kCols;
+    for (int e = threadIdx.x; e < nin; e += R * 64) {
+        const int n = e % kCols, cs = e / kCols;
+        const int c = cs / a.r_in, s = cs - c * a.r_in;
+        const int col = col0 + n;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < a.Vc) {
+            const long long pin = (ap << (shiftB + a.dim)) + (b << a.dim) + c;
+            v = a.in[(pin * a.r_in + s) * a.Vc + col];
+        }
+        xs[e] = v;
+    }
+    const int ntw = R * R * a.r_out;
+    for (int e = threadIdx.x; e < ntw; e += R * 64)
+        ts[e] = a.tw[u * ntw + e];
+    __syncthreads();
+    const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, n = lane & 15;
+    const int MT = (a.r_out + 15) >> 4, KS = (a.r_in + 3) >> 2;
+    const float* am = a.amat + (size_t)i * MT * KS * 64 + lane;
+    floatx4 accr[kMaxMT], acci[kMaxMT];
+#pragma unroll
+    for (int m = 0; m < kMaxMT; ++m) accr[m] = acci[m] = zero4();
+    for (int c = 0; c < R; ++c) {
+        floatx4 yr[kMaxMT], yi[kMaxMT];
+#pragma unroll
+        for (int m = 0; m < kMaxMT; ++m) yr[m] = yi[m] = zero4();
+        const float2* x = xs + (size_t)c * a.r_in * kCols + n;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int s = 4 * ks + kq;
+            const float2 xv = s < a.r_in ? x[s * kCols] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int m = 0; m < kMaxMT; ++m) {
+                if (m < MT) {
+                    const float av = am[(m * KS + ks) * 64];
+                    yr[m] = mma(av, xv.x, yr[m]);
+                    yi[m] = mma(av, xv.y, yi[m]);
+                }
+            }
+        }
+        const float2* tw = ts + (i * R + c) * a.r_out;
+#pragma unroll
+        for (int m = 0; m < kMaxMT; ++m) {
+            if (m < MT) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t = 16 * m + 4 * kq + j;
+                    const float2 T = t < a.r_out ? tw[t] : make_float2(0.f, 0.f);
+                    accr[m][j] += T.x * yr[m][j] - T.y * yi[m][j];
+                    acci[m][j] += T.x * yi[m][j] + T.y * yr[m][j];
+                }
+            }
+        }
+    }
+    const int col = col0 + n;
+    if (col >= a.Vc) return;
+    const long long pout = ((ap * R + i) << shiftB) + b;
+    float2* o = a.out + pout * a.r_out * a.Vc + col;
+#pragma unroll
+    for (int m = 0; m < kMaxMT; ++m) {
+        if (m < MT) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = 16 * m + 4 * kq + j;
+                if (t < a.r_out)
+                    o[(size_t)t * a.Vc] = make_float2(accr[m][j], acci[m][j]);
+            }
+        }
+    }
+}
+
+// Switch (Algorithm 4.1 step 4 regrouped), block = (pair, 16-column tile),
+// wave m = row tile m of nu = S mu; the complex block S is staged in LDS and
+// enters as two real A operands (Re S, Im S).
+__global__ void __launch_bounds__(kMaxMT * 64) switch_step_mfma(StepArgs a) {
+    extern __shared__ float2 lds_step[];
+    const int ldS = a.r_in + 1;                         // padded row
+    float2* xs = lds_step;                              // [r_in][16]
+    float2* Ss = xs + (size_t)a.r_in * kCols;           // [r_out][r_in + 1]
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    const long long p = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - p * nct) * kCols;
+    const int shiftB = a.dim * (a.L - a.level);
+    const long long bm = p & ((1LL << shiftB) - 1);
+    const int nthr = blockDim.x;
+    for (int e = threadIdx.x; e < a.r_in * kCols; e += nthr) {
+        const int n = e % kCols, s = e / kCols;
+        const int col = col0 + n;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < a.Vc)
+            v = a.reads_f ? head_value(a, bm, s, col)
+                          : a.in[(p * a.r_in + s) * a.Vc + col];
+        xs[e] = v;
+    }
+    const int nS = a.r_out * a.r_in;
+    const float2* S = a.S + p * nS;
+    for (int e = threadIdx.x; e < nS; e += nthr) {
+        const int t = e / a.r_in, s = e - t * a.r_in;
+        Ss[t * ldS + s] = S[e];
+    }
+    __syncthreads();
+    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, n = lane & 15;
+    const int KS = (a.r_in + 3) >> 2;
+    const int row = 16 * m + n;
+    floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
+    for (int ks = 0; ks < KS; ++ks) {
+        const int s = 4 * ks + kq;
+        float2 sv = make_float2(0.f, 0.f), xv = make_float2(0.f, 0.f);
+        if (s < a.r_in) {
+            xv = xs[s * kCols + n];
+            if (row < a.r_out) sv = Ss[row * ldS + s];
+        }
+        p1 = mma(sv.x, xv.x, p1);
+        p2 = mma(sv.y, xv.y, p2);
+        p3 = mma(sv.x, xv.y, p3);
+        p4 = mma(sv.y, xv.x, p4);
+    }
+    const int col = col0 + n;
+    if (col >= a.Vc) return;
+    float2* o = a.out + p * a.r_out * a.Vc + col;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int t = 16 * m + 4 * kq + j;
+        if (t < a.r_out)
+            o[(size_t)t * a.Vc] = make_float2(p1[j] - p2[j], p3[j] + p4[j]);
+    }
+}
+
+// LDS bytes of one block of the step's kernel.
+size_t step_mfma_lds(const Plan& p, const Step& s) {
+    if (s.kind == STEP_SWITCH)
+        return ((size_t)s.r_in * kCols + (size_t)s.r_out * (s.r_in + 1)) *
+               sizeof(float2);
+    const int rt = s.kind == STEP_XI ? s.r_in : s.r_out;
+    return ((size_t)p.R * s.r_in * kCols + (size_t)p.R * p.R * rt) *
+           sizeof(float2);
+}
+
+void init_step_mfma_attrs() {
+    static bool done = false;
+    if (done) return;
+    const void* fns[] = {(const void*)xi_step_mfma<2>, (const void*)xi_step_mfma<4>,
+                         (const void*)x_step_mfma<2>, (const void*)x_step_mfma<4>,
+                         (const void*)switch_step_mfma};
+    for (const void* fn : fns)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+    done = true;
+}
+
+// Launches one step; "" on success.
+std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
+                             hipStream_t st) {
+    if (s.r_out > kMaxMT * 16) return "step rank above 64";
+    const long long nct = (a.Vc + kCols - 1) / kCols;
+    const size_t lds = step_mfma_lds(p, s);
+    if (lds > 160 * 1024) return "step does not fit in LDS";
+    init_step_mfma_attrs();
+    if (s.kind == STEP_SWITCH) {
+        const long long nb = s.units * nct;
+        if (nb > 0x7fffffffLL) return "switch grid too large";
+        const int MT = (s.r_out + 15) / 16;
+        hipLaunchKernelGGL(switch_step_mfma, dim3((unsigned)nb), dim3(64 * MT),
+                           lds, st, a);
+    } else {
+        const long long nb = s.units * nct;
+        if (nb > 0x7fffffffLL) return "step grid too large";
+        if (p.R == 2) {
+            if (s.kind == STEP_XI)
+                hipLaunchKernelGGL((xi_step_mfma<2>), dim3((unsigned)nb),
+                                   dim3(128), lds, st, a);
+            else
+                hipLaunchKernelGGL((x_step_mfma<2>), dim3((unsigned)nb),
+                                   dim3(128), lds, st, a);
+        } else {
+            if (s.kind == STEP_XI)
+                hipLaunchKernelGGL((xi_step_mfma<4>), dim3((unsigned)nb),
+                                   dim3(256), lds, st, a);
+            else
+                hipLaunchKernelGGL((x_step_mfma<4>), dim3((unsigned)nb),
+                                   dim3(256), lds, st, a);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
+    return "";
+}
+
+}  // namespace bfi

@@ -67,7 +67,11 @@ struct Step {
     // split-precision copies of mats: hi and lo parts, 16-bit each
     uint16_t* mats_hi = nullptr;
     uint16_t* mats_lo = nullptr;
-    size_t tw_elems = 0, mat_elems = 0, S_elems = 0;
+    // mats in the A-operand order of a 16x16x4 FP32 MFMA, zero padded:
+    // [R][ceil(r_out/16)][ceil(r_in/4)][lane], lane l holding
+    // M[16 mt + l % 16][4 ks + l / 16]
+    float* amat = nullptr;
+    size_t tw_elems = 0, mat_elems = 0, S_elems = 0, amat_elems = 0;
     std::vector<double> mats_host;  // FP64 Lagrange matrices
 };
 

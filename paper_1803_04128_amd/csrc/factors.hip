@@ -161,8 +161,10 @@ std::string build_factors(Plan& p) {
     // arena layout
     size_t bytes = 0;
     const bool split = p.precision != BF_FP32;
-    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo;
+    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am;
     for (auto& s : p.steps) {
+        off_am.push_back(bytes);
+        bytes = align_up(bytes + s.amat_elems * sizeof(float));
         off_tw.push_back(bytes);
         bytes = align_up(bytes + s.tw_elems * sizeof(float2));
         off_S.push_back(bytes);
@@ -191,6 +193,7 @@ std::string build_factors(Plan& p) {
         s.tw = s.tw_elems ? (float2*)(base + off_tw[k]) : nullptr;
         s.S = s.S_elems ? (float2*)(base + off_S[k]) : nullptr;
         s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
+        s.amat = s.amat_elems ? (float*)(base + off_am[k]) : nullptr;
         if (split && s.mat_elems) {
             s.mats_hi = (uint16_t*)(base + off_hi[k]);
             s.mats_lo = (uint16_t*)(base + off_lo[k]);
@@ -222,6 +225,20 @@ std::string build_factors(Plan& p) {
             for (size_t e = 0; e < s.mat_elems; ++e)
                 mf[e] = (float)s.mats_host[e];
             HIPCHK(hipMemcpy(s.mats, mf.data(), s.mat_elems * sizeof(float),
+                             hipMemcpyHostToDevice));
+            // the same matrices in MFMA A-operand order
+            const int MT = (s.r_out + 15) / 16, KS = (s.r_in + 3) / 4;
+            std::vector<float> am(s.amat_elems, 0.f);
+            for (int c = 0; c < p.R; ++c)
+                for (int mt = 0; mt < MT; ++mt)
+                    for (int ks = 0; ks < KS; ++ks)
+                        for (int l = 0; l < 64; ++l) {
+                            const int t = 16 * mt + l % 16, sx = 4 * ks + l / 16;
+                            if (t < s.r_out && sx < s.r_in)
+                                am[(((size_t)c * MT + mt) * KS + ks) * 64 + l] =
+                                    mf[((size_t)c * s.r_out + t) * s.r_in + sx];
+                        }
+            HIPCHK(hipMemcpy(s.amat, am.data(), s.amat_elems * sizeof(float),
                              hipMemcpyHostToDevice));
             if (split) {
                 hipLaunchKernelGGL(split_matrices,

@@ -152,6 +152,7 @@ std::string build_schedule(Plan& p) {
         s.units = p.N / R;
         s.tw_elems = (size_t)s.units * R * R * s.r_in;
         s.mat_elems = (size_t)R * s.r_out * s.r_in;
+        s.amat_elems = (size_t)R * ((s.r_out + 15) / 16) * ((s.r_in + 3) / 4) * 64;
         xi_matrices(s, d, R);
         p.steps.push_back(s);
     }
@@ -181,6 +182,7 @@ std::string build_schedule(Plan& p) {
         s.units = p.N / R;
         s.tw_elems = (size_t)s.units * R * R * s.r_out;
         s.mat_elems = (size_t)R * s.r_out * s.r_in;
+        s.amat_elems = (size_t)R * ((s.r_out + 15) / 16) * ((s.r_in + 3) / 4) * 64;
         x_matrices(s, d, R);
         p.steps.push_back(s);
     }

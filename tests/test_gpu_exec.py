@@ -45,7 +45,8 @@ def test_default_config_and_forms_agree_with_oracle():
         assert pl.info()["n_passes"] == 2
         ft = _to_dev(f32)
         for path, tc in [("fused", 4), ("fused", 8), ("fused_valu", 4),
-                         ("fused_valu", 8), ("per_step", 0)]:
+                         ("fused_valu", 8), ("per_step", 0),
+                         ("per_step_mfma", 0)]:
             pl.set_config(path, tc)
             assert pl.config()["path"] == path
             g = _host(pl.apply(ft))
@@ -67,7 +68,7 @@ def test_set_config_rejects_bad_forms():
         assert pl.config()["path"] == "fused"
     with bfm.Plan(1, 1024, "fio1d", PHASE_PARAMS["fio1d"], q=8,
                   precision="bf16x3") as pl:
-        for path in ["per_step", "fused_valu"]:
+        for path in ["per_step", "per_step_mfma", "fused_valu"]:
             with pytest.raises(bfm.BfError) as ei:
                 pl.set_config(path)
             assert ei.value.code == bfm._lib.BF_EUNSUPPORTED
@@ -92,6 +93,7 @@ def test_autotune_picks_a_timed_form(dim, n, kind, q, nvec, amp, r):
             log("  ", e)
         timed = [e for e in res if e["ms"] > 0]
         assert timed and any(e["path"] == "per_step" for e in timed)
+        assert any(e["path"] == "per_step_mfma" for e in timed)
         best = min(timed, key=lambda e: e["ms"])
         c = pl.config()
         assert c["path"] == best["path"]
@@ -108,6 +110,7 @@ def test_autotune_picks_a_timed_form(dim, n, kind, q, nvec, amp, r):
     (1, 1024, "fio1d", 8, 3, "per_step"),
     (1, 65536, "fio1d", 10, 2, "fused"),
     (2, 64, "radon2d", 7, 2, "fused"),
+    (2, 64, "radon2d", 7, 2, "per_step_mfma"),
 ])
 def test_graph_replays_match_eager(dim, n, kind, q, nvec, path):
     import torch
@@ -159,3 +162,9 @@ def test_plan_destroy_waits_for_graphs():
     assert ei.value.code == bfm._lib.BF_EBUSY
     gr.close()
     pl.close()
+
+
+def test_2d_default_is_per_step_mfma():
+    bfm = _bfm()
+    with bfm.Plan(2, 32, "radon2d", PHASE_PARAMS["radon2d"], q=7) as pl:
+        assert pl.config()["path"] == "per_step_mfma"

@@ -20,11 +20,13 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-@pytest.fixture(autouse=True, params=["fused", "per_step"])
+@pytest.fixture(autouse=True, params=["fused", "per_step", "per_step_mfma"])
 def apply_path(request, monkeypatch):
-    """Run every parity case through the level-fused passes and through the
-    one-launch-per-level path (BF_FUSED is read when a plan is built)."""
+    """Run every parity case through the level-fused passes, the
+    one-launch-per-level vector-ALU kernels and the one-launch-per-level MFMA
+    kernels (BF_FUSED and BF_MFMA are read when a plan is built)."""
     monkeypatch.setenv("BF_FUSED", "1" if request.param == "fused" else "0")
+    monkeypatch.setenv("BF_MFMA", "0" if request.param == "per_step" else "1")
     return request.param
 
 
