@@ -408,7 +408,7 @@ static bool pass_fits(const Plan& p, int s0, int s1, int Vt, bool head,
         const int hr1 = p.head_step_side;
         // two tiles, two twiddle buffers, and the f tile of the head pass
         const size_t lds = 2 * ((size_t)Gk * rmax * Vt * 8 + (size_t)2 * Gk * rmax * 8) +
-                           (head ? (size_t)Gk * hr1 * Vt * 8 : 0);
+                           (head ? (size_t)Gk * hr1 * Vt * 8 : 0) + kMfmaLdsPad * 8;
         return lds <= kMfmaLdsBudget && Gk * Vt <= (long long)kMfmaTileCap * 8;
     }
     size_t lds = (size_t)Gk * rmax * Vt * 8;
@@ -542,6 +542,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             if (s.kind == STEP_SWITCH) continue;
             a.lv[k].tw = s.tw;
             a.lv[k].mats = s.mats;
+            a.lv[k].amat = s.kind == STEP_XI ? s.amat_xi : s.amat;
             a.lv[k].mats_hi = s.mats_hi;
             a.lv[k].mats_lo = s.mats_lo;
             a.lv[k].r_in = s.r_in;

@@ -27,9 +27,14 @@ namespace bfi {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// 8 waves per workgroup share one LDS tile (two waves per SIMD)
-constexpr int kMfmaThreads = 512;
-constexpr int kWaveTiles = kMfmaTileCap / (2 * (kMfmaThreads / 64));
+// Waves per workgroup: the FP32 passes run 16 waves (four per SIMD, 128
+// VGPRs each) on one LDS tile; the split-precision passes, which hold more
+// operands per lane, run 8.
+template <int PREC>
+constexpr int mfma_threads() { return PREC == BF_FP32 ? 1024 : 512; }
+// x-level MFMA tiles per wave at the largest tile (Gk * VT = 512)
+template <int PREC>
+constexpr int wave_tiles() { return kMfmaTileCap / (2 * (mfma_threads<PREC>() / 64)); }
 
 __device__ __forceinline__ float lane_swap1(float v) {
     // quad_perm [1, 0, 3, 2]: exchange with the neighbouring lane
@@ -205,18 +210,20 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
         }
         return;
     }
+    // FP32: K = 2 r_in ordered with the child fastest, k = 4 kk + g ->
+    // child c = g % 2, coefficient s = 2 kk + g / 2.  Every lane then reads
+    // x and w at a fixed base plus a compile-time step per kk, and A comes
+    // pre-arranged in this order (lv.amat, zero past r_in and r_out).  Steps
+    // past r_in read finite data: the pass zeroes its LDS before use.
+    (void)K;
+    const int nks2 = (r_in + 1) >> 1;
     float aM[8];
-    int xo[8], wo[8];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-        const int k = 4 * kk + g;
-        const bool v = kk < nks && k < K;
-        const int c = (v && k >= r_in) ? 1 : 0;
-        const int s = v ? k - c * r_in : 0;
-        xo[kk] = c * cstride + s * VT + col;
-        wo[kk] = c * r_in + s;
-        aM[kk] = (v && tA < r_out) ? lv.mats[(c * r_out + tA) * r_in + s] : 0.f;
-    }
+    for (int kk = 0; kk < 8; ++kk)
+        aM[kk] = kk < nks2 ? lv.amat[kk * 64 + lane] : 0.f;
+    const int cg = g & 1, sg = g >> 1;
+    const int xoff = cg * cstride + sg * VT + col;
+    const int woff = cg * r_in + sg;
     const int ntiles = (a.Gk + CPT - 1) / CPT;
     const int DS = a.rmax * VT;
     for (int tau = wave; tau < ntiles; tau += nwaves) {
@@ -226,19 +233,19 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
         const int unit = ui >> 1, i = ui & 1;
         const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
         const int rv = digit_rev(apl, j - 1, 1);
-        const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS;
-        const float2* wp = twl + (unit * 4 + i * 2) * r_in;
+        const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
+        const float2* wp = twl + (unit * 4 + i * 2) * r_in + woff;
         float2 xs[8], ws[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-            if (kk >= nks) break;
-            xs[kk] = xp[xo[kk]];
-            ws[kk] = wp[wo[kk]];
+            if (kk >= nks2) break;
+            xs[kk] = xp[kk * 2 * VT];
+            ws[kk] = wp[2 * kk];
         }
         floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-            if (kk >= nks) break;
+            if (kk >= nks2) break;
             const float2 x = xs[kk], w = ws[kk];
             accr = mfma4(aM[kk], w.x * x.x - w.y * x.y, accr);
             acci = mfma4(aM[kk], w.x * x.y + w.y * x.x, acci);
@@ -293,7 +300,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
         const int nunits = a.Gk >> 1;
         const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-        for (int m = 0; m < kWaveTiles / 2; ++m) {
+        for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             int unit = tau * UPT + sub;
@@ -351,22 +358,20 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
         }
         return;
     }
+    // FP32: coefficient s = 4 kk + g, so each lane reads x at a fixed base
+    // plus a compile-time step per kk; A comes pre-arranged (lv.amat, zero
+    // past r_in and r_out) and steps past r_in read finite (zeroed) LDS
     float aM[2][4];
-    int xo[4];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        const int s = 4 * kk + g;
-        const bool v = kk < nks && s < r_in;
-        xo[kk] = (v ? s : 0) * VT + col;
+    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-            aM[i][kk] = (v && tA < r_out) ? lv.mats[(i * r_out + tA) * r_in + s]
-                                          : 0.f;
-    }
+            aM[i][kk] = kk < nks ? lv.amat[(i * nks + kk) * 64 + lane] : 0.f;
+    const int xoff = g * VT + col;
     const int nunits = a.Gk >> 1;
     const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-    for (int m = 0; m < kWaveTiles / 2; ++m) {
+    for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
         const int tau = wave + m * nwaves;
         if (tau >= ntiles) break;
         int unit = tau * UPT + sub;
@@ -374,14 +379,14 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
         if (!ok) unit = 0;
         const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
         const int rv = digit_rev(apl, j - 1, 1);
-        const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS;
+        const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
         const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
         float2 x0[4], x1[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             if (kk >= nks) break;
-            x0[kk] = xp0[xo[kk]];
-            x1[kk] = xp1[xo[kk]];
+            x0[kk] = xp0[kk * 4 * VT];
+            x1[kk] = xp1[kk * 4 * VT];
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -395,14 +400,14 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                 y1r = mfma4(am, x1[kk].x, y1r);
                 y1i = mfma4(am, x1[kk].y, y1i);
             }
-            const float2* tp = twl + (unit * 4 + i * 2) * r_out;
+            // rows t >= r_out read finite (zeroed or stale) twiddles and are
+            // never stored
+            const float2* tp = twl + (unit * 4 + i * 2) * r_out + 4 * g;
             floatx4 orr, oii;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                int t = 4 * g + jj;
-                if (t >= r_out) t = 0;
-                const float2 T0 = tp[t];
-                const float2 T1 = tp[r_out + t];
+                const float2 T0 = tp[jj];
+                const float2 T1 = tp[r_out + jj];
                 orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
                 oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
             }
@@ -450,7 +455,7 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
     const float2* S0 = a.S + (size_t)((a0 << shiftB) + bfix) * r_out * r_in;
     // issue every S load of this wave's pairs first (one memory latency
     // for the whole switch instead of one per pair)
-    constexpr int kPairs = kMfmaTileCap / (kMfmaThreads / 64);
+    constexpr int kPairs = 2;
     for (int r0 = 0; r0 < a.Gk; r0 += kPairs * nwaves) {   // rounds of pairs
     float2 svall[kPairs][4];
 #pragma unroll
@@ -498,10 +503,23 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
     __syncthreads();
 }
 
+// Zero the tiles, the twiddle buffers and the trailing pad of a pass (the
+// f tile is written whole before use), so that K steps past a level's rank
+// and rows past r_out read finite values, which then meet zero A entries or
+// are never stored.
+__device__ __forceinline__ void zero_pass_lds(float2* lds, int n_front,
+                                              float2* pad) {
+    for (int e = threadIdx.x; e < n_front; e += blockDim.x)
+        lds[e] = make_float2(0.f, 0.f);
+    if (threadIdx.x < kMfmaLdsPad) pad[threadIdx.x] = make_float2(0.f, 0.f);
+    __syncthreads();
+}
+
 // LDS of an MFMA pass: tiles[2] (Gk x rmax x VT), twiddles[2] (2 Gk rmax),
-// then the f tile (Gk x head_r x VT) when the pass starts from f.
+// then the f tile (Gk x head_r x VT) when the pass starts from f, then a
+// zeroed pad of kMfmaLdsPad entries.
 template <int VT, int PREC>
-__global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
+__global__ void __launch_bounds__(mfma_threads<PREC>()) xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
     // every LDS pointer below is lds + offset, selected with ternaries (not
     // an array of pointers) so the compiler keeps them in the LDS address
@@ -516,6 +534,8 @@ __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
+    zero_pass_lds(lds, 2 * tsz + 2 * wsz,
+                  a.has_head ? ftile + a.Gk * a.head_r * VT : ftile);
     const long long bg = spatial % a.nbg;
     const long long ap_base = spatial / a.nbg;
     // the f tile is shared by every sub-iteration (the T_X boxes at level
@@ -548,7 +568,7 @@ __global__ void __launch_bounds__(kMfmaThreads) xi_pass_mfma(PassArgs a) {
 }
 
 template <int VT, int PREC>
-__global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
+__global__ void __launch_bounds__(mfma_threads<PREC>()) x_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
     const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
     float2* const T0 = lds;
@@ -559,11 +579,12 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
+    zero_pass_lds(lds, 2 * tsz + 2 * wsz, lds + 2 * tsz + 2 * wsz);
     const long long ap_grp = a.has_tail ? spatial : spatial / a.nbg;
     const long long bg0 = a.has_tail ? 0 : spatial % a.nbg;
-    floatx4 tacc[2 * kWaveTiles];
+    floatx4 tacc[2 * wave_tiles<PREC>()];
 #pragma unroll
-    for (int m = 0; m < 2 * kWaveTiles; ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 2 * wave_tiles<PREC>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
@@ -597,7 +618,7 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
         const int n = lane & 15, g = lane >> 4;
         const int sub = n / VT, col = n & (VT - 1);
 #pragma unroll
-        for (int m = 0; m < kWaveTiles / 2; ++m) {
+        for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             const int unit = tau * UPT + sub;
@@ -646,7 +667,7 @@ __global__ void __launch_bounds__(kMfmaThreads) x_pass_mfma(PassArgs a) {
 
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     const size_t tsz = (size_t)a.Gk * a.rmax * a.Vt, wsz = (size_t)2 * a.Gk * a.rmax;
-    size_t e = 2 * tsz + 2 * wsz;
+    size_t e = 2 * tsz + 2 * wsz + kMfmaLdsPad;
     if (is_xi && a.has_head) e += (size_t)a.Gk * a.head_r * a.Vt;
     return e * sizeof(float2);
 }
@@ -685,10 +706,10 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
     const long long nblocks = a.nspatial * a.nchunk;
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(kMfmaThreads), lds, st, a);
+                           dim3(mfma_threads<PREC>()), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(kMfmaThreads), lds, st, a);
+                           dim3(mfma_threads<PREC>()), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("MFMA pass launch: ") + hipGetErrorString(e);

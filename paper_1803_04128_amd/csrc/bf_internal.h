@@ -71,7 +71,12 @@ struct Step {
     // [R][ceil(r_out/16)][ceil(r_in/4)][lane], lane l holding
     // M[16 mt + l % 16][4 ks + l / 16]
     float* amat = nullptr;
+    // 1D xi steps (r_out <= 16): [M_0 | M_1] as the A operand of a K = 2 r_in
+    // product with the children interleaved, [ceil(r_in/2)][lane], lane l
+    // holding M_{c}[l % 16][2 kk + (l / 16) / 2], c = (l / 16) % 2
+    float* amat_xi = nullptr;
     size_t tw_elems = 0, mat_elems = 0, S_elems = 0, amat_elems = 0;
+    size_t amat_xi_elems = 0;
     std::vector<double> mats_host;  // FP64 Lagrange matrices
 };
 

@@ -161,10 +161,12 @@ std::string build_factors(Plan& p) {
     // arena layout
     size_t bytes = 0;
     const bool split = p.precision != BF_FP32;
-    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am;
+    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am, off_ax;
     for (auto& s : p.steps) {
         off_am.push_back(bytes);
         bytes = align_up(bytes + s.amat_elems * sizeof(float));
+        off_ax.push_back(bytes);
+        bytes = align_up(bytes + s.amat_xi_elems * sizeof(float));
         off_tw.push_back(bytes);
         bytes = align_up(bytes + s.tw_elems * sizeof(float2));
         off_S.push_back(bytes);
@@ -194,6 +196,7 @@ std::string build_factors(Plan& p) {
         s.S = s.S_elems ? (float2*)(base + off_S[k]) : nullptr;
         s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
         s.amat = s.amat_elems ? (float*)(base + off_am[k]) : nullptr;
+        s.amat_xi = s.amat_xi_elems ? (float*)(base + off_ax[k]) : nullptr;
         if (split && s.mat_elems) {
             s.mats_hi = (uint16_t*)(base + off_hi[k]);
             s.mats_lo = (uint16_t*)(base + off_lo[k]);
@@ -240,6 +243,23 @@ std::string build_factors(Plan& p) {
                         }
             HIPCHK(hipMemcpy(s.amat, am.data(), s.amat_elems * sizeof(float),
                              hipMemcpyHostToDevice));
+            if (s.amat_xi_elems) {
+                // xi order of the fused 1D passes: k = 4 kk + g, child
+                // c = g % 2, coefficient 2 kk + g / 2
+                std::vector<float> ax(s.amat_xi_elems, 0.f);
+                const int nk = (s.r_in + 1) / 2;
+                for (int kk = 0; kk < nk; ++kk)
+                    for (int l = 0; l < 64; ++l) {
+                        const int t = l % 16, g = l / 16;
+                        const int c = g % 2, sx = 2 * kk + g / 2;
+                        if (t < s.r_out && sx < s.r_in)
+                            ax[(size_t)kk * 64 + l] =
+                                mf[((size_t)c * s.r_out + t) * s.r_in + sx];
+                    }
+                HIPCHK(hipMemcpy(s.amat_xi, ax.data(),
+                                 s.amat_xi_elems * sizeof(float),
+                                 hipMemcpyHostToDevice));
+            }
             if (split) {
                 hipLaunchKernelGGL(split_matrices,
                                    dim3(grid_for((long long)s.mat_elems)),

@@ -153,6 +153,8 @@ std::string build_schedule(Plan& p) {
         s.tw_elems = (size_t)s.units * R * R * s.r_in;
         s.mat_elems = (size_t)R * s.r_out * s.r_in;
         s.amat_elems = (size_t)R * ((s.r_out + 15) / 16) * ((s.r_in + 3) / 4) * 64;
+        if (p.dim == 1 && s.r_out <= 16)
+            s.amat_xi_elems = (size_t)((s.r_in + 1) / 2) * 64;
         xi_matrices(s, d, R);
         p.steps.push_back(s);
     }
