@@ -102,6 +102,9 @@ def main():
                          "mixed request stream (its own JSON line)")
     ap.add_argument("--requests", type=int, default=2000,
                     help="serving: requests per load level")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the apply captured in a HIP graph "
+                         "(bf_graph_create / bf_graph_launch)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the execution forms first and keep the "
                          "fastest (bf_autotune)")
@@ -161,8 +164,16 @@ def main():
     tune = None
     if args.autotune:
         tune = plan.autotune(f, out=g, reps=2)
+    graph = plan.graph(f, g) if args.graph else None
+
+    def step(stream):
+        if graph is not None:
+            graph.launch(stream=stream)
+        else:
+            plan.apply(f, out=g, stream=stream)
+
     for _ in range(args.warmup):
-        plan.apply(f, out=g)
+        step(None)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
@@ -173,12 +184,20 @@ def main():
     t0 = time.perf_counter()
     evs[0].record(stream)
     for k in range(args.steps):
-        plan.apply(f, out=g, stream=stream)
+        step(stream)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     plan.profile(False)
     kstats = plan.profile_read()
+    if graph is not None:
+        # graph replays carry no library events: per-kernel times (for the
+        # roofline) come from eager applies after the timed region
+        plan.profile(True)
+        for _ in range(max(3, min(args.steps, 20))):
+            plan.apply(f, out=g, stream=stream)
+        plan.profile(False)
+        kstats = plan.profile_read()
     lat = np.array([evs[k].elapsed_time(evs[k + 1])
                     for k in range(args.steps)])
 
@@ -233,7 +252,7 @@ def main():
                         "ms_per_launch": v["total_ms"] / v["launches"]}
                     for k, v in kstats.items()},
         "roofline": roof,
-        "exec": plan.config(),
+        "exec": dict(plan.config(), graph=graph is not None),
     }
     if tune is not None:
         out["autotune"] = tune
@@ -243,6 +262,8 @@ def main():
             np.complex128), ab, g_host)
         out["cpu_baseline"] = rep
         out["rel_err_vs_oracle"] = err
+    if graph is not None:
+        graph.close()
     plan.close()
     print(json.dumps(out), flush=True)
 
@@ -257,7 +278,7 @@ def serve_bench(args):
     import torch
 
     from paper_1803_04128_amd.serving import (PlanSpec, Request, Server,
-                                              summarize)
+                                              overlap_fraction, summarize)
     from synthetic import (PHASE_PARAMS, SERVING_SHAPES, amplitude_factors,
                            gaussian_vectors, serving_requests)
 
@@ -320,6 +341,7 @@ def serve_bench(args):
                    "max_batch": max_batch},
         "levels": levels,
         "batches": len(sizes),
+        "device_overlap": overlap_fraction(srv.intervals),
         "mean_batch_vectors": float(np.mean(sizes)) if sizes else 0.0,
         "resident_plan_bytes": srv.cache.resident_bytes,
         "plan_build_s": build_s,

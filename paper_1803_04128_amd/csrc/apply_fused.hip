@@ -193,13 +193,16 @@ __global__ void __launch_bounds__(kPassThreads) xi_pass(PassArgs a) {
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
+    const int part = (int)(spatial % a.sub_split);
+    spatial /= a.sub_split;
     const long long bg = spatial % a.nbg;
     const long long ap_base = spatial / a.nbg;
     if (a.has_head) {
         load_head(a, ftile, bg * a.Gk, chunk);
         __syncthreads();
     }
-    for (int sub = 0; sub < a.n_sub; ++sub) {
+    for (int si = 0; si < a.n_sub; ++si) {
+        const int sub = part * a.n_sub + si;
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.dim * (a.L - a.la + 1))) +
@@ -637,6 +640,15 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
                 flops += N * Vs * (double)(1LL << (p.dim * (p.L - p.lend))) * 2.0 +
                          N * nv * p.r_amp * 8.0;
         }
+        // a head pass with few workgroups spreads its sub-iterations over
+        // more of them (each reloads the f tile) to fill the chip
+        a.sub_split = 1;
+        if (is_xi && a.has_head)
+            while (a.sub_split < a.n_sub &&
+                   a.nspatial * nchunk * a.sub_split < 512)
+                a.sub_split *= 2;
+        a.n_sub /= a.sub_split;
+        a.nspatial *= a.sub_split;
         a.xcd_map = (a.nspatial % 8 == 0) ? 1 : 0;
         if (lds > 160 * 1024) return "fused pass does not fit in LDS";
         {

@@ -536,12 +536,15 @@ __global__ void __launch_bounds__(mfma_threads<PREC>()) xi_pass_mfma(PassArgs a)
     if (spatial >= a.nspatial) return;
     zero_pass_lds(lds, 2 * tsz + 2 * wsz,
                   a.has_head ? ftile + a.Gk * a.head_r * VT : ftile);
+    const int part = (int)(spatial % a.sub_split);
+    spatial /= a.sub_split;
     const long long bg = spatial % a.nbg;
     const long long ap_base = spatial / a.nbg;
-    // the f tile is shared by every sub-iteration (the T_X boxes at level
-    // l0 - 1 all see the same input)
+    // the f tile is shared by the sub-iterations of the workgroup (the T_X
+    // boxes at level l0 - 1 all see the same input)
     if (a.has_head) load_head(a, ftile, bg * a.Gk, chunk);
-    for (int sub = 0; sub < a.n_sub; ++sub) {
+    for (int si = 0; si < a.n_sub; ++si) {
+        const int sub = part * a.n_sub + si;
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;

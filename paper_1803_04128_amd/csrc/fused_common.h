@@ -52,6 +52,9 @@ struct PassArgs {
     const float2* bamp;
     int head_side, head_r;
     int n_sub;                // sub-iterations per workgroup
+    int sub_split;            // xi head passes: workgroups sharing the
+                              // sub-iterations of one spatial group (the
+                              // block index carries the part)
     long long nbg;            // groups along T_Omega at the output level
     long long nspatial;
     int xcd_map;              // 1: XCD-aware block -> (spatial, chunk)

@@ -14,9 +14,10 @@ vector and far more efficient in large batches.  The server therefore
   ``max_batch`` vectors (continuous batching: requests that arrive while a
   batch runs join the next batch of their plan; the plan of the oldest
   queued request goes next, so no plan starves);
-* keeps up to ``max_inflight`` batches queued on the stream ahead of the
-  device and timestamps every batch with a device event, so a request's
-  latency runs from its arrival to the completion of its batch on the GPU.
+* runs up to ``max_inflight`` batches at once, each on its own HIP stream,
+  so batches of different plans overlap on the device, and timestamps every
+  batch with a device event: a request's latency runs from its arrival to
+  the completion of its batch on the GPU.
 
 Scheduling and admission are host logic (``Scheduler``, ``PlanCache``) and
 work with any plan object that has ``footprint`` and ``close()``; the device
@@ -100,14 +101,15 @@ class Scheduler:
                              f"max_batch {self.max_batch}")
         self._q.append(req)
 
-    def next_batch(self):
-        """(plan name, requests) for the plan of the oldest request: its
-        queued requests in arrival order while the vectors fit max_batch
-        (the first that does not fit ends the batch, which keeps each plan's
-        requests in order).  None when the queue is empty."""
-        if not self._q:
+    def next_batch(self, busy=()):
+        """(plan name, requests) for the plan of the oldest request whose
+        plan is not in ``busy``: its queued requests in arrival order while
+        the vectors fit max_batch (the first that does not fit ends the
+        batch, which keeps each plan's requests in order).  None when no
+        such request is queued."""
+        name = next((r.plan for r in self._q if r.plan not in busy), None)
+        if name is None:
             return None
-        name = self._q[0].plan
         take, keep, total, full = [], collections.deque(), 0, False
         for r in self._q:
             if r.plan == name and not full:
@@ -198,16 +200,20 @@ class ResidentPlan:
                            is not None else 0))
 
     def run(self, reqs, stream):
-        """Stage the requests' vectors, apply once, copy results out."""
-        off = 0
-        for r in reqs:
-            self.fin[off:off + r.nvec].copy_(r.f.reshape(r.nvec, -1))
-            off += r.nvec
-        self.plan.apply(self.fin[:off], out=self.fout[:off], stream=stream)
-        off = 0
-        for r in reqs:
-            r.out.reshape(r.nvec, -1).copy_(self.fout[off:off + r.nvec])
-            off += r.nvec
+        """Stage the requests' vectors, apply once, copy results out, all on
+        ``stream``."""
+        import torch
+        with torch.cuda.stream(stream):
+            off = 0
+            for r in reqs:
+                self.fin[off:off + r.nvec].copy_(r.f.reshape(r.nvec, -1))
+                off += r.nvec
+            self.plan.apply(self.fin[:off], out=self.fout[:off],
+                            stream=stream)
+            off = 0
+            for r in reqs:
+                r.out.reshape(r.nvec, -1).copy_(self.fout[off:off + r.nvec])
+                off += r.nvec
 
     def close(self):
         self.plan.close()
@@ -225,6 +231,8 @@ class Server:
         self.poll_s = poll_s
         self.cache = PlanCache(hbm_budget_bytes, self._build)
         self.batches: List[Tuple[str, int]] = []
+        # device intervals of the batches: (start s, end s, plan, slot)
+        self.intervals: List[Tuple[float, float, str, int]] = []
 
     def register(self, name, spec: PlanSpec):
         self.specs[name] = spec
@@ -234,7 +242,12 @@ class Server:
 
     def run(self, requests: List[Request]):
         """Serve every request; fills done (seconds from the run's start),
-        batch and error.  Returns the requests in arrival order."""
+        batch and error.  Returns the requests in arrival order.
+
+        Each of the max_inflight slots owns a HIP stream (default priority);
+        batches of different plans run concurrently on the device, and a
+        plan is in flight on at most one slot at a time (its staging buffers
+        and workspace are its own)."""
         import torch
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
@@ -243,61 +256,74 @@ class Server:
             if r.out is None:
                 r.out = torch.empty_like(r.f)
         sched = Scheduler(self.max_batch)
-        stream = torch.cuda.current_stream()
+        main = torch.cuda.current_stream()
+        slots = [torch.cuda.Stream() for _ in range(self.max_inflight)]
+        for st in slots:
+            st.wait_stream(main)        # inputs written on the caller's stream
         torch.cuda.synchronize()
         base = torch.cuda.Event(enable_timing=True)
-        base.record(stream)
+        base.record(main)
         t0 = time.perf_counter()
-        inflight = collections.deque()
+        inflight = {}       # slot -> (start event, end event, batch, plan)
         i, nb = 0, 0
 
-        def retire(item):
-            ev, batch = item
+        def retire(slot):
+            ev0, ev, batch, name = inflight.pop(slot)
             t = base.elapsed_time(ev) / 1e3
+            self.intervals.append((base.elapsed_time(ev0) / 1e3, t, name,
+                                   slot))
             for r in batch:
                 r.done = t
+
+        def drain():
+            for slot in list(inflight):
+                inflight[slot][1].synchronize()
+                retire(slot)
 
         while i < len(reqs) or len(sched) or inflight:
             now = time.perf_counter() - t0
             while i < len(reqs) and reqs[i].arrival <= now:
                 sched.add(reqs[i])
                 i += 1
-            while inflight and inflight[0][0].query():
-                retire(inflight.popleft())
-            if len(sched) and len(inflight) < self.max_inflight:
-                name, batch = sched.next_batch()
+            for slot in list(inflight):
+                if inflight[slot][1].query():
+                    retire(slot)
+            free = [k for k in range(len(slots)) if k not in inflight]
+            busy = {v[3] for v in inflight.values()}
+            nxt = sched.next_batch(busy=busy) if (free and len(sched)) else None
+            if nxt is not None:
+                name, batch = nxt
                 try:
                     try:
-                        rp = self.cache.get(
-                            name, pinned={b[0].plan for _, b in inflight})
+                        rp = self.cache.get(name, pinned=busy)
                     except PinnedError:
-                        # wait for the batches in flight, then evict freely
-                        while inflight:
-                            inflight[0][0].synchronize()
-                            retire(inflight.popleft())
+                        # room only once the plans in flight are released
+                        drain()
+                        free = list(range(len(slots)))
                         rp = self.cache.get(name)
                 except AdmissionError as e:
                     for r in batch + sched.drop(name):
                         r.error = str(e)
                     continue
-                rp.run(batch, stream)
+                slot = free[0]
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(slots[slot])
+                rp.run(batch, slots[slot])
                 ev = torch.cuda.Event(enable_timing=True)
-                ev.record(stream)
+                ev.record(slots[slot])
                 for r in batch:
                     r.batch = nb
                 nb += 1
                 self.batches.append((name, sum(r.nvec for r in batch)))
-                inflight.append((ev, batch))
+                inflight[slot] = (ev0, ev, batch, name)
                 continue
-            if inflight and (i >= len(reqs) or
-                             len(inflight) >= self.max_inflight):
-                if i >= len(reqs):
-                    inflight[0][0].synchronize()
-                    continue
-            if i < len(reqs):
-                wait = reqs[i].arrival - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, self.poll_s if inflight else wait))
+            # nothing to launch now: wait for an arrival or a completion
+            wait = (reqs[i].arrival - (time.perf_counter() - t0)
+                    if i < len(reqs) else float("inf"))
+            if inflight:
+                wait = min(wait, self.poll_s)
+            if wait > 0 and wait != float("inf"):
+                time.sleep(wait)
         torch.cuda.synchronize()
         return reqs
 
@@ -320,3 +346,20 @@ def summarize(reqs, N_of):
                 mean_ms=float(lat.mean()),
                 throughput=work / span if span > 0 else float("nan"),
                 span_s=span)
+
+
+def overlap_fraction(intervals):
+    """Fraction of the busy device time during which at least two batches
+    were running (from the batches' start and end events)."""
+    ev = sorted([(a, 1) for a, _, _, _ in intervals] +
+                [(b, -1) for _, b, _, _ in intervals])
+    busy = multi = 0.0
+    depth, last = 0, None
+    for t, d in ev:
+        if last is not None and depth > 0:
+            busy += t - last
+            if depth > 1:
+                multi += t - last
+        depth += d
+        last = t
+    return multi / busy if busy > 0 else 0.0

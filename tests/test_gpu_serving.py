@@ -64,7 +64,8 @@ def _alone(reqs):
 @pytest.mark.parametrize("budget_plans", [3, 1])
 def test_batched_stream_matches_single_applies(budget_plans):
     import torch
-    from paper_1803_04128_amd.serving import Server, summarize
+    from paper_1803_04128_amd.serving import (Server, overlap_fraction,
+                                              summarize)
     log(f"case serving budget_plans={budget_plans}")
     reqs = _requests(80, 5, rate=4000.0)
     ref = _alone(reqs)
@@ -88,10 +89,14 @@ def test_batched_stream_matches_single_applies(budget_plans):
             assert np.array_equal(r.out.cpu().numpy(), ref[r.rid]), r.rid
         sizes = [n for _, n in srv.batches]
         assert max(sizes) > 4 and len(sizes) < len(reqs)
+        if budget_plans == 3:
+            # batches of different plans ran on both streams (slots)
+            assert {s for _, _, _, s in srv.intervals} == {0, 1}
         if budget_plans == 1:
             assert srv.cache.evictions > 0
         st = summarize(done, lambda n: SPECS[n][1] ** SPECS[n][0])
-        log(f"  {st} batches={len(sizes)} evictions={srv.cache.evictions}")
+        log(f"  {st} batches={len(sizes)} evictions={srv.cache.evictions} "
+            f"overlap={overlap_fraction(srv.intervals):.2f}")
         assert st["served"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
     finally:
         srv.close()

@@ -114,3 +114,24 @@ def test_request_stream_is_seeded_and_weighted():
     kinds = [x[1] for x in a]
     assert set(kinds) == set(range(len(SERVING_SHAPES)))
     assert kinds.count(0) > kinds.count(8)  # weights 6 vs 1
+
+
+def test_busy_plans_are_skipped_without_losing_order():
+    s = Scheduler(max_batch=8)
+    for rid, plan in enumerate(["a", "b", "a", "c", "b"]):
+        s.add(_req(rid, plan, 1, t=rid))
+    name, b = s.next_batch(busy={"a"})
+    assert name == "b" and [r.rid for r in b] == [1, 4]
+    assert s.next_batch(busy={"a", "c"}) is None
+    name, b = s.next_batch(busy={"c"})
+    assert name == "a" and [r.rid for r in b] == [0, 2]
+    name, b = s.next_batch()
+    assert name == "c" and [r.rid for r in b] == [3]
+
+
+def test_overlap_fraction():
+    from paper_1803_04128_amd.serving import overlap_fraction
+    assert overlap_fraction([]) == 0.0
+    assert overlap_fraction([(0, 1, "a", 0), (2, 3, "b", 1)]) == 0.0
+    # [0,2] and [1,3]: busy 3, two at once during [1,2]
+    assert abs(overlap_fraction([(0, 2, "a", 0), (1, 3, "b", 1)]) - 1 / 3) < 1e-12
