@@ -133,12 +133,13 @@ __global__ void __launch_bounds__(256) switch_basic(StepArgs a) {
 // Final sums (Algorithm 4.1 steps 5-6 at the exact levels) and the amplitude
 // (eq. (eqn:tg)): g_v(x) = sum_k a_k(x) sum_B lambda_k^{A(x), B}(x), the
 // inner sum over the R^(L-lend) boxes B at level L-lend.
-// Thread = (vector, output index x).
+// Thread = (output index x, vector), the vector fastest so that
+// neighbouring threads read neighbouring state columns.
 __global__ void __launch_bounds__(256) tail_basic(TailArgs a) {
     const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (gid >= a.N * a.nv) return;
-    const long long x = gid % a.N;
-    const int vl = (int)(gid / a.N);
+    const int vl = (int)(gid % a.nv);
+    const long long x = gid / a.nv;
     int g[2], Ac[2], tdig[2];
     if (a.dim == 1) {
         g[0] = (int)x;

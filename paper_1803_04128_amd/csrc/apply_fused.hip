@@ -409,8 +409,9 @@ static bool pass_fits(const Plan& p, int s0, int s1, int Vt, bool head,
     if (k > kMaxPassLevels) return false;
     if (mfma_mode(p, Vt) && p.steps[s0].kind != STEP_SWITCH) {
         const int hr1 = p.head_step_side;
-        // two tiles, two twiddle buffers, and the f tile of the head pass
-        const size_t lds = 2 * ((size_t)Gk * rmax * Vt * 8 + (size_t)2 * Gk * rmax * 8) +
+        // the tile (updated in place), two twiddle buffers, and the f tile
+        // of the head pass
+        const size_t lds = (size_t)Gk * rmax * Vt * 8 + (size_t)4 * Gk * rmax * 8 +
                            (head ? (size_t)Gk * hr1 * Vt * 8 : 0) + kMfmaLdsPad * 8;
         return lds <= kMfmaLdsBudget && Gk * Vt <= (long long)kMfmaTileCap * 8;
     }

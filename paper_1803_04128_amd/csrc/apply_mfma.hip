@@ -16,25 +16,28 @@
 //   switch (Algorithm 4.1 step 4 regrouped): per pair, A = Re S and A = Im S
 //     against 16 real columns (Re mu, Im mu of 8 columns); the other half of
 //     each product comes from the neighbouring lane.
-// Levels ping-pong between two LDS tiles (outputs go straight to the other
-// tile) and the next level's twiddles are staged into the second twiddle
-// buffer while a level computes, so a level needs one workgroup barrier.
-// K steps past the end use A = 0 and read valid (finite) data, so the loads
-// need no guards.  R = 2, r <= 16, VT (columns per tile) in {1, 2, 4, 8}.
+// Levels update one LDS tile in place (a unit reads its two slots and
+// writes the same two, and all of a unit's columns sit in one wave) and the
+// next level's twiddles are staged into the second twiddle buffer while a
+// level computes, so a level needs one workgroup barrier.  K steps past the
+// end use A = 0 and read valid (finite) data, so the loads need no guards.
+// R = 2, r <= 16, VT (columns per tile) in {1, 2, 4, 8}.
 #include "fused_common.h"
 
 namespace bfi {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Waves per workgroup: the FP32 passes run 16 waves (four per SIMD, 128
+// The FP32 passes run 16 waves per workgroup (four per SIMD, <= 128
 // VGPRs each) on one LDS tile; the split-precision passes, which hold more
 // operands per lane, run 8.
-template <int PREC>
+template <int VT, int PREC>
 constexpr int mfma_threads() { return PREC == BF_FP32 ? 1024 : 512; }
 // x-level MFMA tiles per wave at the largest tile (Gk * VT = 512)
-template <int PREC>
-constexpr int wave_tiles() { return kMfmaTileCap / (2 * (mfma_threads<PREC>() / 64)); }
+template <int VT, int PREC>
+constexpr int wave_tiles() {
+    return kMfmaTileCap / (2 * (mfma_threads<VT, PREC>() / 64));
+}
 
 __device__ __forceinline__ float lane_swap1(float v) {
     // quad_perm [1, 0, 3, 2]: exchange with the neighbouring lane
@@ -300,7 +303,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
         const int nunits = a.Gk >> 1;
         const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-        for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
+        for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             int unit = tau * UPT + sub;
@@ -371,7 +374,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     const int nunits = a.Gk >> 1;
     const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-    for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
+    for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
         const int tau = wave + m * nwaves;
         if (tau >= ntiles) break;
         int unit = tau * UPT + sub;
@@ -515,26 +518,29 @@ __device__ __forceinline__ void zero_pass_lds(float2* lds, int n_front,
     __syncthreads();
 }
 
-// LDS of an MFMA pass: tiles[2] (Gk x rmax x VT), twiddles[2] (2 Gk rmax),
-// then the f tile (Gk x head_r x VT) when the pass starts from f, then a
-// zeroed pad of kMfmaLdsPad entries.
+// LDS of an MFMA pass: the tile (Gk x rmax x VT), two twiddle buffers
+// (2 Gk rmax each), the f tile (Gk x head_r x VT) when the pass starts from
+// f, then a zeroed pad of kMfmaLdsPad entries.  Levels update the tile in
+// place: a unit reads its two slots and writes the same two slots, and all
+// of a unit's columns sit in one wave, so no other wave touches them within
+// the level.
 template <int VT, int PREC>
-__global__ void __launch_bounds__(mfma_threads<PREC>()) xi_pass_mfma(PassArgs a) {
+__global__ void __launch_bounds__((mfma_threads<VT, PREC>()))
+xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
-    // every LDS pointer below is lds + offset, selected with ternaries (not
-    // an array of pointers) so the compiler keeps them in the LDS address
-    // space and emits ds_read / ds_write
+    // every LDS pointer below is lds + offset (not read from an array of
+    // pointers) so the compiler keeps them in the LDS address space and
+    // emits ds_read / ds_write
     const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
-    float2* const T0 = lds;
-    float2* const T1 = lds + tsz;
-    float2* const W0 = lds + 2 * tsz;
-    float2* const W1 = lds + 2 * tsz + wsz;
-    float2* const ftile = lds + 2 * tsz + 2 * wsz;
+    float2* const T = lds;
+    float2* const W0 = lds + tsz;
+    float2* const W1 = lds + tsz + wsz;
+    float2* const ftile = lds + tsz + 2 * wsz;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
-    zero_pass_lds(lds, 2 * tsz + 2 * wsz,
+    zero_pass_lds(lds, tsz + 2 * wsz,
                   a.has_head ? ftile + a.Gk * a.head_r * VT : ftile);
     const int part = (int)(spatial % a.sub_split);
     spatial /= a.sub_split;
@@ -548,69 +554,67 @@ __global__ void __launch_bounds__(mfma_threads<PREC>()) xi_pass_mfma(PassArgs a)
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-            load_tile(a, T0, p0, a.lv[0].r_in, chunk);
+            load_tile(a, T, p0, a.lv[0].r_in, chunk);
         }
         stage_twiddles(a, 1, W0, ap_grp, bg, true);
         __syncthreads();
-        // level j reads the f tile (j = 1 with the head) or the tile the
-        // previous level wrote, and writes the other tile
-        const int flip = a.has_head ? 0 : 1;
+        // level j uses W0 (j odd) or W1 while the next level's twiddles go
+        // to the other buffer; level 1 of a head pass reads the f tile
         for (int j = 1; j <= a.k; ++j) {
-            if (j < a.k) stage_twiddles(a, j + 1, (j & 1) ? W1 : W0, ap_grp, bg, true);
-            const bool dst1 = ((j - 1 + flip) & 1) != 0;
-            const float2* src = (j == 1) ? (a.has_head ? ftile : T0) : (dst1 ? T0 : T1);
-            const int src_r = (j == 1 && a.has_head) ? a.head_r : a.rmax;
-            mfma_xi_level<VT, PREC>(a, src, src_r, dst1 ? T1 : T0, (j & 1) ? W0 : W1, j);
+            const bool odd = (j & 1) != 0;
+            if (j < a.k) stage_twiddles(a, j + 1, odd ? W1 : W0, ap_grp, bg, true);
+            const bool from_f = j == 1 && a.has_head;
+            mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
+                                    from_f ? a.head_r : a.rmax, T,
+                                    odd ? W0 : W1, j);
             __syncthreads();
         }
-        float2* cur = (((a.k - 1 + flip) & 1) != 0) ? T1 : T0;
-        if (a.has_switch) mfma_switch<VT>(a, cur, ap_grp * a.Gk, bg);
-        store_tile(a, cur, ap_grp * a.Gk, bg, chunk);
+        if (a.has_switch) mfma_switch<VT>(a, T, ap_grp * a.Gk, bg);
+        store_tile(a, T, ap_grp * a.Gk, bg, chunk);
         __syncthreads();
     }
 }
 
 template <int VT, int PREC>
-__global__ void __launch_bounds__(mfma_threads<PREC>()) x_pass_mfma(PassArgs a) {
+__global__ void __launch_bounds__((mfma_threads<VT, PREC>()))
+x_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
     const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
-    float2* const T0 = lds;
-    float2* const T1 = lds + tsz;
-    float2* const W0 = lds + 2 * tsz;
-    float2* const W1 = lds + 2 * tsz + wsz;
+    float2* const T = lds;
+    float2* const W0 = lds + tsz;
+    float2* const W1 = lds + tsz + wsz;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
-    zero_pass_lds(lds, 2 * tsz + 2 * wsz, lds + 2 * tsz + 2 * wsz);
+    zero_pass_lds(lds, tsz + 2 * wsz, lds + tsz + 2 * wsz);
     const long long ap_grp = a.has_tail ? spatial : spatial / a.nbg;
     const long long bg0 = a.has_tail ? 0 : spatial % a.nbg;
-    floatx4 tacc[2 * wave_tiles<PREC>()];
+    floatx4 tacc[2 * wave_tiles<VT, PREC>()];
 #pragma unroll
-    for (int m = 0; m < 2 * wave_tiles<PREC>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 2 * wave_tiles<VT, PREC>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-        load_tile(a, T0, p0, a.lv[0].r_in, chunk);
+        load_tile(a, T, p0, a.lv[0].r_in, chunk);
         stage_twiddles(a, 1, W0, ap_grp, bg, false);
         __syncthreads();
-        // level j reads T0 (j odd) or T1 and writes the other
         for (int j = 1; j <= a.k; ++j) {
-            if (j < a.k) stage_twiddles(a, j + 1, (j & 1) ? W1 : W0, ap_grp, bg, false);
             const bool odd = (j & 1) != 0;
-            mfma_x_level<VT, PREC>(a, odd ? T0 : T1, odd ? T1 : T0, odd ? W0 : W1, j,
-                             a.has_tail && j == a.k, tacc);
+            if (j < a.k) stage_twiddles(a, j + 1, odd ? W1 : W0, ap_grp, bg, false);
+            mfma_x_level<VT, PREC>(a, T, T, odd ? W0 : W1, j,
+                                   a.has_tail && j == a.k, tacc);
             __syncthreads();
         }
         if (!a.has_tail) {
-            store_tile(a, (a.k & 1) ? T1 : T0, ap_grp * a.Gk, bg, chunk);
+            store_tile(a, T, ap_grp * a.Gk, bg, chunk);
             __syncthreads();
         }
     }
     if (!a.has_tail) return;
     // final coefficients of the Gk boxes A to LDS as [a_loc][t][VT], then
     // g_v(x) = sum_k a_k(x) lambda_k(x) (eq. (eqn:tg))
-    float2* fin = T0;
+    float2* fin = T;
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int nwaves = blockDim.x >> 6;
@@ -621,7 +625,7 @@ __global__ void __launch_bounds__(mfma_threads<PREC>()) x_pass_mfma(PassArgs a) 
         const int n = lane & 15, g = lane >> 4;
         const int sub = n / VT, col = n & (VT - 1);
 #pragma unroll
-        for (int m = 0; m < wave_tiles<PREC>() / 2; ++m) {
+        for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             const int unit = tau * UPT + sub;
@@ -670,7 +674,7 @@ __global__ void __launch_bounds__(mfma_threads<PREC>()) x_pass_mfma(PassArgs a) 
 
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     const size_t tsz = (size_t)a.Gk * a.rmax * a.Vt, wsz = (size_t)2 * a.Gk * a.rmax;
-    size_t e = 2 * tsz + 2 * wsz + kMfmaLdsPad;
+    size_t e = tsz + 2 * wsz + kMfmaLdsPad;
     if (is_xi && a.has_head) e += (size_t)a.Gk * a.head_r * a.Vt;
     return e * sizeof(float2);
 }
@@ -709,10 +713,10 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
     const long long nblocks = a.nspatial * a.nchunk;
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(mfma_threads<PREC>()), lds, st, a);
+                           dim3(mfma_threads<VT, PREC>()), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(mfma_threads<PREC>()), lds, st, a);
+                           dim3(mfma_threads<VT, PREC>()), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("MFMA pass launch: ") + hipGetErrorString(e);
