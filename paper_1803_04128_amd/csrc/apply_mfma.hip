@@ -139,12 +139,98 @@ __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
     }
 }
 
+// The same staging split in two: load() issues the global reads into
+// registers (up to NT per thread), store() writes them to LDS, so that the
+// reads overlap whatever runs in between (a level's MFMA work); entries past
+// NT per thread are copied directly by store().
+template <int NT>
+struct TwStage {
+    float2 v[NT];
+    int total, per_unit, kj, shiftB;
+    unsigned apg0, bg0;
+    const float2* tw;
+
+    __device__ __forceinline__ unsigned src_index(int unit, int lo) const {
+        const unsigned apl = (unsigned)unit >> kj;
+        const unsigned bl = (unsigned)unit & ((1u << kj) - 1);
+        const unsigned u = ((apg0 + apl) << shiftB) + bg0 + bl;
+        return u * (unsigned)per_unit + (unsigned)lo;
+    }
+
+    __device__ __forceinline__ void load(const PassArgs& a, int j,
+                                         long long ap_grp, long long bg,
+                                         bool xi) {
+        const PassLevel& lv = a.lv[j - 1];
+        const int rr = xi ? lv.r_in : lv.r_out;
+        kj = a.k - j;
+        per_unit = 4 * rr;
+        total = (a.Gk >> 1) * per_unit;
+        shiftB = a.L - (a.la + j - 1);
+        apg0 = (unsigned)(ap_grp << (j - 1));
+        bg0 = (unsigned)(bg << kj);
+        tw = lv.tw;
+        Walk2 w(threadIdx.x, per_unit);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+            if (threadIdx.x + m * (int)blockDim.x < total)
+                v[m] = tw[src_index(w.hi, w.lo)];
+            w.next();
+        }
+    }
+
+    __device__ __forceinline__ void store(float2* twl) const {
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+            const int e = threadIdx.x + m * (int)blockDim.x;
+            if (e < total) twl[e] = v[m];
+        }
+        for (int e = threadIdx.x + NT * (int)blockDim.x; e < total;
+             e += blockDim.x) {
+            const int unit = e / per_unit;
+            twl[e] = tw[src_index(unit, e - unit * per_unit)];
+        }
+    }
+};
+
+// Register-staged twiddle entries per thread: what the largest tile
+// (Gk * VT = 512, r <= 16) needs, at most 4.
+template <int VT, int PREC>
+constexpr int tw_regs() {
+    return (kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>() > 4
+               ? 4
+               : ((kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>() < 1
+                      ? 1
+                      : (kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>());
+}
+
+// A operand of an FP32 level, one coalesced load per k step (lv.amat):
+// xi levels aM[kk], kk < ceil(r_in / 2); x levels aM[4 i + kk], kk <
+// ceil(r_in / 4); zero elsewhere.
+__device__ __forceinline__ void load_amat(const PassLevel& lv, bool xi,
+                                          float (&aM)[8]) {
+    const int lane = threadIdx.x & 63;
+    if (xi) {
+        const int nks2 = (lv.r_in + 1) >> 1;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+            aM[kk] = kk < nks2 ? lv.amat[kk * 64 + lane] : 0.f;
+    } else {
+        const int nks = (lv.r_in + 3) >> 2;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                aM[4 * i + kk] =
+                    kk < nks ? lv.amat[(i * nks + kk) * 64 + lane] : 0.f;
+    }
+}
+
 // One xi level: src (stride src_r coefficients per slot) -> dst.
 template <int VT, int PREC>
 __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
                                               const float2* src, int src_r,
                                               float2* dst, const float2* twl,
-                                              int j) {
+                                              int j, const float (&aMin)[8]) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int K = 2 * r_in, nks = (K + 3) / 4;
@@ -220,10 +306,7 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
     // past r_in read finite data: the pass zeroes its LDS before use.
     (void)K;
     const int nks2 = (r_in + 1) >> 1;
-    float aM[8];
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk)
-        aM[kk] = kk < nks2 ? lv.amat[kk * 64 + lane] : 0.f;
+    const float (&aM)[8] = aMin;            // loaded by the caller
     const int cg = g & 1, sg = g >> 1;
     const int xoff = cg * cstride + sg * VT + col;
     const int woff = cg * r_in + sg;
@@ -270,7 +353,8 @@ template <int VT, int PREC>
 __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                                              const float2* src, float2* dst,
                                              const float2* twl, int j,
-                                             bool to_tail, floatx4* tacc) {
+                                             bool to_tail, floatx4* tacc,
+                                             const float (&aMin)[8]) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int nks = (r_in + 3) / 4;
@@ -364,12 +448,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     // FP32: coefficient s = 4 kk + g, so each lane reads x at a fixed base
     // plus a compile-time step per kk; A comes pre-arranged (lv.amat, zero
     // past r_in and r_out) and steps past r_in read finite (zeroed) LDS
-    float aM[2][4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-            aM[i][kk] = kk < nks ? lv.amat[(i * nks + kk) * 64 + lane] : 0.f;
+    const float (&aM)[8] = aMin;            // loaded by the caller
     const int xoff = g * VT + col;
     const int nunits = a.Gk >> 1;
     const int ntiles = (nunits + UPT - 1) / UPT;
@@ -397,7 +476,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 if (kk >= nks) break;
-                const float am = aM[i][kk];
+                const float am = aM[4 * i + kk];
                 y0r = mfma4(am, x0[kk].x, y0r);
                 y0i = mfma4(am, x0[kk].y, y0i);
                 y1r = mfma4(am, x1[kk].x, y1r);
@@ -557,17 +636,29 @@ xi_pass_mfma(PassArgs a) {
             load_tile(a, T, p0, a.lv[0].r_in, chunk);
         }
         stage_twiddles(a, 1, W0, ap_grp, bg, true);
+        float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == BF_FP32) load_amat(a.lv[0], true, aM);
         __syncthreads();
-        // level j uses W0 (j odd) or W1 while the next level's twiddles go
-        // to the other buffer; level 1 of a head pass reads the f tile
+        // level j uses W0 (j odd) or W1; the next level's A operand and
+        // twiddles are read from global memory before the level's MFMA work
+        // and the twiddles written to the other buffer after it, so the
+        // reads overlap the work; level 1 of a head pass reads the f tile
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
-            if (j < a.k) stage_twiddles(a, j + 1, odd ? W1 : W0, ap_grp, bg, true);
+            float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            TwStage<tw_regs<VT, PREC>()> next;
+            if (j < a.k) {
+                if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
+                next.load(a, j + 1, ap_grp, bg, true);
+            }
             const bool from_f = j == 1 && a.has_head;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
-                                    odd ? W0 : W1, j);
+                                    odd ? W0 : W1, j, aM);
+            if (j < a.k) next.store(odd ? W1 : W0);
             __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
         }
         if (a.has_switch) mfma_switch<VT>(a, T, ap_grp * a.Gk, bg);
         store_tile(a, T, ap_grp * a.Gk, bg, chunk);
@@ -598,13 +689,23 @@ x_pass_mfma(PassArgs a) {
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
         load_tile(a, T, p0, a.lv[0].r_in, chunk);
         stage_twiddles(a, 1, W0, ap_grp, bg, false);
+        float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == BF_FP32) load_amat(a.lv[0], false, aM);
         __syncthreads();
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
-            if (j < a.k) stage_twiddles(a, j + 1, odd ? W1 : W0, ap_grp, bg, false);
+            float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            TwStage<tw_regs<VT, PREC>()> next;
+            if (j < a.k) {
+                if constexpr (PREC == BF_FP32) load_amat(a.lv[j], false, aMn);
+                next.load(a, j + 1, ap_grp, bg, false);
+            }
             mfma_x_level<VT, PREC>(a, T, T, odd ? W0 : W1, j,
-                                   a.has_tail && j == a.k, tacc);
+                                   a.has_tail && j == a.k, tacc, aM);
+            if (j < a.k) next.store(odd ? W1 : W0);
             __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
         }
         if (!a.has_tail) {
             store_tile(a, T, ap_grp * a.Gk, bg, chunk);
