@@ -547,8 +547,8 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             a.lv[k].tw = s.tw;
             a.lv[k].mats = s.mats;
             a.lv[k].amat = s.kind == STEP_XI ? s.amat_xi : s.amat;
-            a.lv[k].mats_hi = s.mats_hi;
-            a.lv[k].mats_lo = s.mats_lo;
+            a.lv[k].ahi = s.asplit_hi;
+            a.lv[k].alo = s.asplit_lo;
             a.lv[k].r_in = s.r_in;
             a.lv[k].r_out = s.r_out;
             a.lv[k].level = s.level;

@@ -75,12 +75,6 @@ template <> struct Split<BF_BF16X3> {
         h[e] = __builtin_bit_cast(short, hv);
         l[e] = __builtin_bit_cast(short, lv);
     }
-    static __device__ __forceinline__ void bits8(v8& h, int e, uint16_t b) {
-        h[e] = __builtin_bit_cast(__bf16, b);
-    }
-    static __device__ __forceinline__ void bits4(v4& h, int e, uint16_t b) {
-        h[e] = (short)b;
-    }
     static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
@@ -101,12 +95,6 @@ template <> struct Split<BF_FP16X3> {
         const _Float16 hv = (_Float16)v;
         h[e] = hv;
         l[e] = (_Float16)(v - (float)hv);
-    }
-    static __device__ __forceinline__ void bits8(v8& h, int e, uint16_t b) {
-        h[e] = __builtin_bit_cast(_Float16, b);
-    }
-    static __device__ __forceinline__ void bits4(v4& h, int e, uint16_t b) {
-        h[e] = __builtin_bit_cast(_Float16, b);
     }
     static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -246,23 +234,17 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
     // so x offsets fold the child in: xo = c 2^(j-1) RS + s VT + col
     const int cstride = (1 << (j - 1)) * RS;
     if constexpr (PREC != BF_FP32) {
-        // K = 2 r_in <= 32: one 16x16x32 product per (chain, split term)
+        // K = 2 r_in <= 32: one 16x16x32 product per (chain, split term).
+        // Lane l holds k = 8 g + e ordered with the child fastest: child
+        // c = e % 2, coefficient s = 4 g + e / 2, so x and w sit at a fixed
+        // lane base plus compile-time (and uniform child) offsets; the hi/lo
+        // A parts come pre-arranged, 8 per lane (lv.ahi, lv.alo).
         using SP = Split<PREC>;
-        typename SP::v8 ahi, alo;
-        int xo8[8], wo8[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = 8 * g + e;
-            const bool v = k < K;
-            const int c = (v && k >= r_in) ? 1 : 0;
-            const int s = v ? k - c * r_in : 0;
-            xo8[e] = c * cstride + s * VT + col;
-            wo8[e] = c * r_in + s;
-            const bool av = v && tA < r_out;
-            const int mi = (c * r_out + (av ? tA : 0)) * r_in + s;
-            SP::bits8(ahi, e, av ? lv.mats_hi[mi] : (uint16_t)0);
-            SP::bits8(alo, e, av ? lv.mats_lo[mi] : (uint16_t)0);
-        }
+        const typename SP::v8 ahi =
+            __builtin_bit_cast(typename SP::v8, ((const uint4*)lv.ahi)[lane]);
+        const typename SP::v8 alo =
+            __builtin_bit_cast(typename SP::v8, ((const uint4*)lv.alo)[lane]);
+        const int xbase = 4 * g * VT + col, wbase = 4 * g;
         const int ntiles = (a.Gk + CPT - 1) / CPT;
         const int DS = a.rmax * VT;
         for (int tau = wave; tau < ntiles; tau += nwaves) {
@@ -272,12 +254,13 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
             const int unit = ui >> 1, i = ui & 1;
             const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
             const int rv = digit_rev(apl, j - 1, 1);
-            const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS;
-            const float2* wp = twl + (unit * 4 + i * 2) * r_in;
+            const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xbase;
+            const float2* wp = twl + (unit * 4 + i * 2) * r_in + wbase;
             typename SP::v8 rh, rl, ih, il;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float2 x = xp[xo8[e]], w = wp[wo8[e]];
+                const float2 x = xp[(e & 1) * cstride + (e >> 1) * VT];
+                const float2 w = wp[(e & 1) * r_in + (e >> 1)];
                 SP::put8(rh, rl, e, w.x * x.x - w.y * x.y);
                 SP::put8(ih, il, e, w.x * x.y + w.y * x.x);
             }
@@ -367,23 +350,19 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     const int sub = n / VT, col = n & (VT - 1);
     const int RS = a.rmax * VT;
     if constexpr (PREC != BF_FP32) {
-        // K = r_in <= 16: one 16x16x16 product per (child i, chain, term)
+        // K = r_in <= 16: one 16x16x16 product per (child i, chain, term);
+        // lane l holds s = 4 g + e, and the hi/lo A parts of M_i come
+        // pre-arranged, 4 per lane (lv.ahi, lv.alo)
         using SP = Split<PREC>;
         typename SP::v4 ahi[2], alo[2];
-        int xo4[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int s = 4 * g + e;
-            const bool v = s < r_in;
-            xo4[e] = (v ? s : 0) * VT + col;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const bool av = v && tA < r_out;
-                const int mi = (i * r_out + (av ? tA : 0)) * r_in + (v ? s : 0);
-                SP::bits4(ahi[i], e, av ? lv.mats_hi[mi] : (uint16_t)0);
-                SP::bits4(alo[i], e, av ? lv.mats_lo[mi] : (uint16_t)0);
-            }
+        for (int i = 0; i < 2; ++i) {
+            ahi[i] = __builtin_bit_cast(typename SP::v4,
+                                        ((const uint2*)lv.ahi)[i * 64 + lane]);
+            alo[i] = __builtin_bit_cast(typename SP::v4,
+                                        ((const uint2*)lv.alo)[i * 64 + lane]);
         }
+        const int xbase = 4 * g * VT + col;
         const int nunits = a.Gk >> 1;
         const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
@@ -400,7 +379,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
             typename SP::v4 r0h, r0l, i0h, i0l, r1h, r1l, i1h, i1l;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float2 x0 = xp0[xo4[e]], x1 = xp1[xo4[e]];
+                const float2 x0 = xp0[xbase + e * VT], x1 = xp1[xbase + e * VT];
                 SP::put4(r0h, r0l, e, x0.x);
                 SP::put4(i0h, i0l, e, x0.y);
                 SP::put4(r1h, r1l, e, x1.x);
@@ -419,14 +398,13 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                 y0i = SP::mma16(alo[i], i0h, y0i);
                 y1r = SP::mma16(alo[i], r1h, y1r);
                 y1i = SP::mma16(alo[i], i1h, y1i);
-                const float2* tp = twl + (unit * 4 + i * 2) * r_out;
+                // rows t >= r_out read finite twiddles and are not stored
+                const float2* tp = twl + (unit * 4 + i * 2) * r_out + 4 * g;
                 floatx4 orr, oii;
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    int t = 4 * g + jj;
-                    if (t >= r_out) t = 0;
-                    const float2 T0 = tp[t];
-                    const float2 T1 = tp[r_out + t];
+                    const float2 T0 = tp[jj];
+                    const float2 T1 = tp[r_out + jj];
                     orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
                     oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
                 }

@@ -64,9 +64,12 @@ struct Step {
     float2* tw = nullptr;       // [units][R][R][r] (r = r_in for XI, r_out X)
     float* mats = nullptr;      // [R][r_out][r_in]
     float2* S = nullptr;        // [N][r_out][r_in]
-    // split-precision copies of mats: hi and lo parts, 16-bit each
-    uint16_t* mats_hi = nullptr;
-    uint16_t* mats_lo = nullptr;
+    // split precisions (1D): hi and lo 16-bit parts of mats in the A-operand
+    // order of the fused passes' 16x16x32 (xi: [lane][8], lane l holding
+    // M_{e % 2}[l % 16][4 (l / 16) + e / 2]) or 16x16x16 products (x:
+    // [child][lane][4], M_i[l % 16][4 (l / 16) + e]); zero past the ranks
+    uint16_t* asplit_hi = nullptr;
+    uint16_t* asplit_lo = nullptr;
     // mats in the A-operand order of a 16x16x4 FP32 MFMA, zero padded:
     // [R][ceil(r_out/16)][ceil(r_in/4)][lane], lane l holding
     // M[16 mt + l % 16][4 ks + l / 16]
@@ -77,6 +80,7 @@ struct Step {
     float* amat_xi = nullptr;
     size_t tw_elems = 0, mat_elems = 0, S_elems = 0, amat_elems = 0;
     size_t amat_xi_elems = 0;
+    size_t asplit_elems = 0;  // 512 per step with a matrix (split plans)
     std::vector<double> mats_host;  // FP64 Lagrange matrices
 };
 

@@ -161,7 +161,7 @@ std::string build_factors(Plan& p) {
     // arena layout
     size_t bytes = 0;
     const bool split = p.precision != BF_FP32;
-    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am, off_ax;
+    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am, off_ax, off_af;
     for (auto& s : p.steps) {
         off_am.push_back(bytes);
         bytes = align_up(bytes + s.amat_elems * sizeof(float));
@@ -173,10 +173,15 @@ std::string build_factors(Plan& p) {
         bytes = align_up(bytes + s.S_elems * sizeof(float2));
         off_m.push_back(bytes);
         bytes = align_up(bytes + s.mat_elems * sizeof(float));
+        // split precisions: the arranged FP32 table, then its hi and lo parts
+        if (split && s.mat_elems && p.dim == 1 && s.r_out <= 16)
+            s.asplit_elems = 512;
+        off_af.push_back(bytes);
+        bytes = align_up(bytes + s.asplit_elems * sizeof(float));
         off_hi.push_back(bytes);
-        if (split) bytes = align_up(bytes + s.mat_elems * 2);
+        bytes = align_up(bytes + s.asplit_elems * 2);
         off_lo.push_back(bytes);
-        if (split) bytes = align_up(bytes + s.mat_elems * 2);
+        bytes = align_up(bytes + s.asplit_elems * 2);
     }
     size_t off_a = bytes;
     const bool has_amp = p.has_amp;
@@ -197,9 +202,9 @@ std::string build_factors(Plan& p) {
         s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
         s.amat = s.amat_elems ? (float*)(base + off_am[k]) : nullptr;
         s.amat_xi = s.amat_xi_elems ? (float*)(base + off_ax[k]) : nullptr;
-        if (split && s.mat_elems) {
-            s.mats_hi = (uint16_t*)(base + off_hi[k]);
-            s.mats_lo = (uint16_t*)(base + off_lo[k]);
+        if (s.asplit_elems) {
+            s.asplit_hi = (uint16_t*)(base + off_hi[k]);
+            s.asplit_lo = (uint16_t*)(base + off_lo[k]);
         }
         t.ax_in = s.ax_in;
         t.ax_out = s.ax_out;
@@ -260,12 +265,38 @@ std::string build_factors(Plan& p) {
                                  s.amat_xi_elems * sizeof(float),
                                  hipMemcpyHostToDevice));
             }
-            if (split) {
+            if (s.asplit_elems) {
+                // A operands of the split products, arranged per lane, then
+                // split into hi and lo parts on the device
+                std::vector<float> af(s.asplit_elems, 0.f);
+                for (int l = 0; l < 64; ++l) {
+                    const int t = l % 16, g = l / 16;
+                    if (t >= s.r_out) continue;
+                    if (s.kind == STEP_XI) {
+                        for (int e = 0; e < 8; ++e) {
+                            const int c = e % 2, sx = 4 * g + e / 2;
+                            if (sx < s.r_in)
+                                af[(size_t)l * 8 + e] =
+                                    mf[((size_t)c * s.r_out + t) * s.r_in + sx];
+                        }
+                    } else {
+                        for (int i = 0; i < 2; ++i)
+                            for (int e = 0; e < 4; ++e) {
+                                const int sx = 4 * g + e;
+                                if (sx < s.r_in)
+                                    af[((size_t)i * 64 + l) * 4 + e] =
+                                        mf[((size_t)i * s.r_out + t) * s.r_in + sx];
+                            }
+                    }
+                }
+                float* dev = (float*)(base + off_af[k]);
+                HIPCHK(hipMemcpy(dev, af.data(), af.size() * sizeof(float),
+                                 hipMemcpyHostToDevice));
                 hipLaunchKernelGGL(split_matrices,
-                                   dim3(grid_for((long long)s.mat_elems)),
-                                   dim3(kFactorBlock), 0, 0, s.mats,
-                                   s.mats_hi, s.mats_lo,
-                                   (long long)s.mat_elems,
+                                   dim3(grid_for((long long)s.asplit_elems)),
+                                   dim3(kFactorBlock), 0, 0, dev,
+                                   s.asplit_hi, s.asplit_lo,
+                                   (long long)s.asplit_elems,
                                    p.precision == BF_FP16X3 ? 1 : 0);
                 HIPCHK(hipGetLastError());
             }

@@ -23,7 +23,7 @@ constexpr int kMaxPassLevels = 12;
 constexpr int kPassThreads = 256;
 // MFMA tiles (16 panel columns each) a workgroup holds per level
 constexpr int kMfmaTileCap = 64;
-constexpr int kMfmaLdsPad = 32;   // zeroed float2 entries after an MFMA pass's LDS
+constexpr int kMfmaLdsPad = 128;  // zeroed float2 entries after an MFMA pass's LDS
 
 struct PassLevel {
     const float2* tw;
@@ -31,8 +31,8 @@ struct PassLevel {
     const float* amat;         // mats in the MFMA A order of the level
                                // (Step::amat_xi for xi levels, Step::amat
                                // for x levels)
-    const uint16_t* mats_hi;   // 16-bit hi/lo parts (split precisions)
-    const uint16_t* mats_lo;
+    const uint16_t* ahi;       // 16-bit hi/lo A parts (split precisions,
+    const uint16_t* alo;       // Step::asplit_hi / asplit_lo)
     int r_in, r_out, level;
 };
 
