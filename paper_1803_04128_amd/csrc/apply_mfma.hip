@@ -28,15 +28,12 @@ namespace bfi {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// The FP32 passes run 16 waves per workgroup (four per SIMD, <= 128
-// VGPRs each) on one LDS tile; the split-precision passes, which hold more
-// operands per lane, run 8.
-template <int VT, int PREC>
-constexpr int mfma_threads() { return PREC == BF_FP32 ? 1024 : 512; }
+// Workgroups of 16 waves (four per SIMD, <= 128 VGPRs each) on one LDS tile.
+constexpr int kMfmaThreads = 1024;
 // x-level MFMA tiles per wave at the largest tile (Gk * VT = 512)
-template <int VT, int PREC>
+template <int VT>
 constexpr int wave_tiles() {
-    return kMfmaTileCap / (2 * (mfma_threads<VT, PREC>() / 64));
+    return kMfmaTileCap / (2 * (kMfmaThreads / 64));
 }
 
 __device__ __forceinline__ float lane_swap1(float v) {
@@ -182,13 +179,13 @@ struct TwStage {
 
 // Register-staged twiddle entries per thread: what the largest tile
 // (Gk * VT = 512, r <= 16) needs, at most 4.
-template <int VT, int PREC>
+template <int VT>
 constexpr int tw_regs() {
-    return (kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>() > 4
+    return (kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads > 4
                ? 4
-               : ((kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>() < 1
+               : ((kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads < 1
                       ? 1
-                      : (kMfmaTileCap * 8 / VT) * 32 / mfma_threads<VT, PREC>());
+                      : (kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads);
 }
 
 // A operand of an FP32 level, one coalesced load per k step (lv.amat):
@@ -366,7 +363,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
         const int nunits = a.Gk >> 1;
         const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-        for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
+        for (int m = 0; m < wave_tiles<VT>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             int unit = tau * UPT + sub;
@@ -431,7 +428,7 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     const int nunits = a.Gk >> 1;
     const int ntiles = (nunits + UPT - 1) / UPT;
 #pragma unroll
-    for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
+    for (int m = 0; m < wave_tiles<VT>() / 2; ++m) {
         const int tau = wave + m * nwaves;
         if (tau >= ntiles) break;
         int unit = tau * UPT + sub;
@@ -582,7 +579,7 @@ __device__ __forceinline__ void zero_pass_lds(float2* lds, int n_front,
 // of a unit's columns sit in one wave, so no other wave touches them within
 // the level.
 template <int VT, int PREC>
-__global__ void __launch_bounds__((mfma_threads<VT, PREC>()))
+__global__ void __launch_bounds__((kMfmaThreads))
 xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
     // every LDS pointer below is lds + offset (not read from an array of
@@ -624,7 +621,7 @@ xi_pass_mfma(PassArgs a) {
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
             float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            TwStage<tw_regs<VT, PREC>()> next;
+            TwStage<tw_regs<VT>()> next;
             if (j < a.k) {
                 if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
                 next.load(a, j + 1, ap_grp, bg, true);
@@ -645,7 +642,7 @@ xi_pass_mfma(PassArgs a) {
 }
 
 template <int VT, int PREC>
-__global__ void __launch_bounds__((mfma_threads<VT, PREC>()))
+__global__ void __launch_bounds__((kMfmaThreads))
 x_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
     const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
@@ -659,9 +656,9 @@ x_pass_mfma(PassArgs a) {
     zero_pass_lds(lds, tsz + 2 * wsz, lds + tsz + 2 * wsz);
     const long long ap_grp = a.has_tail ? spatial : spatial / a.nbg;
     const long long bg0 = a.has_tail ? 0 : spatial % a.nbg;
-    floatx4 tacc[2 * wave_tiles<VT, PREC>()];
+    floatx4 tacc[2 * wave_tiles<VT>()];
 #pragma unroll
-    for (int m = 0; m < 2 * wave_tiles<VT, PREC>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 2 * wave_tiles<VT>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int sub = 0; sub < a.n_sub; ++sub) {
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
@@ -673,7 +670,7 @@ x_pass_mfma(PassArgs a) {
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
             float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            TwStage<tw_regs<VT, PREC>()> next;
+            TwStage<tw_regs<VT>()> next;
             if (j < a.k) {
                 if constexpr (PREC == BF_FP32) load_amat(a.lv[j], false, aMn);
                 next.load(a, j + 1, ap_grp, bg, false);
@@ -704,7 +701,7 @@ x_pass_mfma(PassArgs a) {
         const int n = lane & 15, g = lane >> 4;
         const int sub = n / VT, col = n & (VT - 1);
 #pragma unroll
-        for (int m = 0; m < wave_tiles<VT, PREC>() / 2; ++m) {
+        for (int m = 0; m < wave_tiles<VT>() / 2; ++m) {
             const int tau = wave + m * nwaves;
             if (tau >= ntiles) break;
             const int unit = tau * UPT + sub;
@@ -792,10 +789,10 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
     const long long nblocks = a.nspatial * a.nchunk;
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(mfma_threads<VT, PREC>()), lds, st, a);
+                           dim3(kMfmaThreads), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(mfma_threads<VT, PREC>()), lds, st, a);
+                           dim3(kMfmaThreads), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("MFMA pass launch: ") + hipGetErrorString(e);
