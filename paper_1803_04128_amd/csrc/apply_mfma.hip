@@ -484,39 +484,38 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     }
 }
 
-// nu = S mu per pair, in place (pairs are independent, so each wave reads
-// its pair's slot and writes it back without a workgroup barrier between).
-// 16 real columns: n = (column, re|im), Re nu = Re S Re mu - Im S Im mu and
-// Im nu = Re S Im mu + Im S Re mu with the cross term from lane n ^ 1.
-template <int VT>
-__device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
-                                            long long a0, long long bfix) {
+// Switch blocks of one round of pairs (NP per wave) in registers, in the
+// A-operand layout of the switch's MFMAs: lane l holds S[l % 16][4 kk +
+// l / 16] of each of its wave's pairs (zero past the ranks).
+template <int NP>
+struct SwRound {
+    float2 v[NP][4];
+};
+
+// Rounds of the switch: the FP32 passes take two pairs per wave and round
+// and read each round's blocks at its start; the split-precision passes,
+// whose levels leave more registers free, take one pair per round and read
+// the next round's blocks ahead (the first round's during the last level).
+template <int PREC>
+constexpr int sw_pairs() { return PREC == BF_FP32 ? 2 : 1; }
+template <int PREC>
+constexpr bool sw_ahead() { return PREC != BF_FP32; }
+
+// Issue the reads of the round starting at slot r0 (group of the pass whose
+// switch pairs are (a0 + rev_k(slot), bfix)).
+template <int NP>
+__device__ __forceinline__ void sw_load(const PassArgs& a, long long a0,
+                                        long long bfix, int r0,
+                                        SwRound<NP>& R) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
     const int r_in = a.sw_r_in, r_out = a.sw_r_out;
     const int nks = (r_in + 3) / 4;
     const int shiftB = a.L - (a.la - 1 + a.k);
     const int g = lane >> 4, tA = lane & 15;
-    const int n = lane & 15;
-    const int col = n >> 1, reim = n & 1;
-    const int colc = col < VT ? col : 0;
-    float* tf = (float*)tile;
-    int so[4];
-    bool sv_ok[4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        const int s = 4 * kk + g;
-        sv_ok[kk] = kk < nks && s < r_in && tA < r_out;
-        so[kk] = ((s < r_in ? s : 0) * VT + colc) * 2 + reim;
-    }
     const float2* S0 = a.S + (size_t)((a0 << shiftB) + bfix) * r_out * r_in;
-    // issue every S load of this wave's pairs first (one memory latency
-    // for the whole switch instead of one per pair)
-    constexpr int kPairs = 2;
-    for (int r0 = 0; r0 < a.Gk; r0 += kPairs * nwaves) {   // rounds of pairs
-    float2 svall[kPairs][4];
 #pragma unroll
-    for (int m = 0; m < kPairs; ++m) {
+    for (int m = 0; m < NP; ++m) {
         const int slot = r0 + wave + m * nwaves;
         if (slot >= a.Gk) break;
         const unsigned dA = (unsigned)digit_rev(slot, a.k, 1);
@@ -525,38 +524,75 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
         for (int kk = 0; kk < 4; ++kk) {
             if (kk >= nks) break;
             const int s = 4 * kk + g;
-            svall[m][kk] = sv_ok[kk] ? S[tA * r_in + s] : make_float2(0.f, 0.f);
+            R.v[m][kk] = (s < r_in && tA < r_out) ? S[tA * r_in + s]
+                                                  : make_float2(0.f, 0.f);
         }
     }
+}
+
+// nu = S mu per pair, in place (pairs are independent, so each wave reads
+// its pair's slot and writes it back without a workgroup barrier between).
+// 16 real columns: n = (column, re|im), Re nu = Re S Re mu - Im S Im mu and
+// Im nu = Re S Im mu + Im S Re mu with the cross term from lane n ^ 1.
+// AHEAD: first holds the first round's blocks, read by the caller ahead of
+// time, and each round issues the next round's reads before its own MFMA
+// work; otherwise each round reads its blocks at its start.
+template <int VT, int NP, bool AHEAD>
+__device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
+                                            long long a0, long long bfix,
+                                            const SwRound<NP>& first) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int r_in = a.sw_r_in, r_out = a.sw_r_out;
+    const int nks = (r_in + 3) / 4;
+    const int g = lane >> 4;
+    const int n = lane & 15;
+    const int col = n >> 1, reim = n & 1;
+    const int colc = col < VT ? col : 0;
+    float* tf = (float*)tile;
+    int so[4];
 #pragma unroll
-    for (int m = 0; m < kPairs; ++m) {
-        const int slot = r0 + wave + m * nwaves;
-        if (slot >= a.Gk) break;
-        const int base = slot * a.rmax * VT * 2;
-        float2 sv[4];
-        float bv[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            if (kk >= nks) break;
-            sv[kk] = svall[m][kk];
-            bv[kk] = tf[base + so[kk]];
-        }
-        floatx4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            if (kk >= nks) break;
-            ar = mfma4(sv[kk].x, bv[kk], ar);
-            ai = mfma4(sv[kk].y, bv[kk], ai);
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const float p = lane_swap1(ai[jj]);
-            const float v = reim ? ar[jj] + p : ar[jj] - p;
-            const int t = 4 * g + jj;
-            if (col < VT && t < r_out) tf[base + (t * VT + col) * 2 + reim] = v;
-        }
+    for (int kk = 0; kk < 4; ++kk) {
+        const int s = 4 * kk + g;
+        so[kk] = ((s < r_in ? s : 0) * VT + colc) * 2 + reim;
     }
-    }   // rounds
+    const int step = NP * nwaves;
+    SwRound<NP> cur = first;
+    for (int r0 = 0; r0 < a.Gk; r0 += step) {   // rounds of pairs
+        SwRound<NP> nxt;
+        if constexpr (AHEAD) {
+            if (r0 + step < a.Gk) sw_load(a, a0, bfix, r0 + step, nxt);
+        } else {
+            sw_load(a, a0, bfix, r0, cur);
+        }
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            const int slot = r0 + wave + m * nwaves;
+            if (slot >= a.Gk) break;
+            const int base = slot * a.rmax * VT * 2;
+            float bv[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                if (kk >= nks) break;
+                bv[kk] = tf[base + so[kk]];
+            }
+            floatx4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                if (kk >= nks) break;
+                ar = mfma4(cur.v[m][kk].x, bv[kk], ar);
+                ai = mfma4(cur.v[m][kk].y, bv[kk], ai);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float p = lane_swap1(ai[jj]);
+                const float v = reim ? ar[jj] + p : ar[jj] - p;
+                const int t = 4 * g + jj;
+                if (col < VT && t < r_out) tf[base + (t * VT + col) * 2 + reim] = v;
+            }
+        }
+        if constexpr (AHEAD) cur = nxt;
+    }
     __syncthreads();
 }
 
@@ -618,24 +654,36 @@ xi_pass_mfma(PassArgs a) {
         // twiddles are read from global memory before the level's MFMA work
         // and the twiddles written to the other buffer after it, so the
         // reads overlap the work; level 1 of a head pass reads the f tile
-        for (int j = 1; j <= a.k; ++j) {
+        for (int j = 1; j < a.k; ++j) {
             const bool odd = (j & 1) != 0;
             float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             TwStage<tw_regs<VT>()> next;
-            if (j < a.k) {
-                if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
-                next.load(a, j + 1, ap_grp, bg, true);
-            }
+            if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
+            next.load(a, j + 1, ap_grp, bg, true);
             const bool from_f = j == 1 && a.has_head;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     odd ? W0 : W1, j, aM);
-            if (j < a.k) next.store(odd ? W1 : W0);
+            next.store(odd ? W1 : W0);
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
         }
-        if (a.has_switch) mfma_switch<VT>(a, T, ap_grp * a.Gk, bg);
+        {
+            // the last level reads the switch's first blocks ahead
+            const int j = a.k;
+            SwRound<sw_pairs<PREC>()> sw0;
+            if constexpr (sw_ahead<PREC>())
+                if (a.has_switch) sw_load(a, ap_grp * a.Gk, bg, 0, sw0);
+            const bool from_f = j == 1 && a.has_head;
+            mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
+                                    from_f ? a.head_r : a.rmax, T,
+                                    (j & 1) ? W0 : W1, j, aM);
+            __syncthreads();
+            if (a.has_switch)
+                mfma_switch<VT, sw_pairs<PREC>(), sw_ahead<PREC>()>(
+                    a, T, ap_grp * a.Gk, bg, sw0);
+        }
         store_tile(a, T, ap_grp * a.Gk, bg, chunk);
         __syncthreads();
     }
