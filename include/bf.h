@@ -65,7 +65,9 @@ extern "C" {
  *            bfloat16; the shared-matrix contraction runs on MFMA as
  *            hi*hi + hi*lo + lo*hi with FP32 accumulation; twiddles,
  *            switch blocks and the state stay FP32.
- * BF_FP16X3: as BF_BF16X3 with IEEE half hi/lo parts (scaled per tile).    */
+ * BF_FP16X3: as BF_BF16X3 with IEEE half hi/lo parts; each panel column
+ *            of a product is scaled by a power of two (exact) so that its
+ *            largest magnitude maps into [0.5, 1) before the split.        */
 #define BF_FP32    0
 #define BF_BF16X3  1
 #define BF_FP16X3  2

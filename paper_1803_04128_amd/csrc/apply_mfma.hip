@@ -61,6 +61,7 @@ template <int PREC> struct Split;
 template <> struct Split<BF_BF16X3> {
     typedef bf16x8 v8;
     typedef shortx4 v4;
+    static constexpr bool kScaled = false;   // bfloat16 has the FP32 range
     static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
         const __bf16 hv = (__bf16)v;
         h[e] = hv;
@@ -83,6 +84,7 @@ template <> struct Split<BF_BF16X3> {
 template <> struct Split<BF_FP16X3> {
     typedef f16x8 v8;
     typedef f16x4 v4;
+    static constexpr bool kScaled = true;    // half: scale each column
     static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
         const _Float16 hv = (_Float16)v;
         h[e] = hv;
@@ -100,6 +102,19 @@ template <> struct Split<BF_FP16X3> {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
     }
 };
+
+// Exponent e of a power-of-two column scale for the half-precision split:
+// m is this lane's largest magnitude; the lanes 16, 32 and 48 apart hold
+// the same B column (other K rows), so after the exchange every lane of the
+// column has the column maximum M = f 2^e, f in [0.5, 1), and the column
+// scaled by 2^-e lies in (-1, 1) (zero columns get e = 0).
+__device__ __forceinline__ int column_exponent(float m) {
+    m = fmaxf(m, __shfl_xor(m, 16));
+    m = fmaxf(m, __shfl_xor(m, 32));
+    int e = 0;
+    (void)frexpf(m, &e);
+    return e;
+}
 
 // Twiddles of local level j for the group's units into LDS:
 // twl[unit_loc][i][c][r], unit_loc = apl 2^(k-j) + bl, contiguous per apl.
@@ -253,13 +268,29 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
             const int rv = digit_rev(apl, j - 1, 1);
             const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xbase;
             const float2* wp = twl + (unit * 4 + i * 2) * r_in + wbase;
-            typename SP::v8 rh, rl, ih, il;
+            float zr[8], zi[8];
+            float zmax = 0.f;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float2 x = xp[(e & 1) * cstride + (e >> 1) * VT];
                 const float2 w = wp[(e & 1) * r_in + (e >> 1)];
-                SP::put8(rh, rl, e, w.x * x.x - w.y * x.y);
-                SP::put8(ih, il, e, w.x * x.y + w.y * x.x);
+                // K rows past r_in read other data and meet A = 0; with the
+                // half scaling they are zeroed so that they neither set the
+                // scale nor overflow
+                const bool kv = !SP::kScaled || wbase + (e >> 1) < r_in;
+                zr[e] = kv ? w.x * x.x - w.y * x.y : 0.f;
+                zi[e] = kv ? w.x * x.y + w.y * x.x : 0.f;
+                if constexpr (SP::kScaled)
+                    zmax = fmaxf(zmax, fmaxf(fabsf(zr[e]), fabsf(zi[e])));
+            }
+            // half: the column scaled into (-1, 1) by a power of two (exact)
+            int ex = 0;
+            if constexpr (SP::kScaled) ex = column_exponent(zmax);
+            typename SP::v8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                SP::put8(rh, rl, e, SP::kScaled ? ldexpf(zr[e], -ex) : zr[e]);
+                SP::put8(ih, il, e, SP::kScaled ? ldexpf(zi[e], -ex) : zi[e]);
             }
             floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
             accr = SP::mma32(ahi, rh, accr);
@@ -268,6 +299,13 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
             acci = SP::mma32(ahi, il, acci);
             accr = SP::mma32(alo, rh, accr);
             acci = SP::mma32(alo, ih, acci);
+            if constexpr (SP::kScaled) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    accr[jj] = ldexpf(accr[jj], ex);
+                    acci[jj] = ldexpf(acci[jj], ex);
+                }
+            }
             if (ok) {
                 float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
 #pragma unroll
@@ -373,14 +411,34 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
             const int rv = digit_rev(apl, j - 1, 1);
             const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS;
             const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
+            float2 x0[4], x1[4];
+            float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // rows past r_in meet A = 0; with the half scaling they are
+                // zeroed (no scale, no overflow)
+                const bool kv = !SP::kScaled || 4 * g + e < r_in;
+                const float2 z = make_float2(0.f, 0.f);
+                x0[e] = kv ? xp0[xbase + e * VT] : z;
+                x1[e] = kv ? xp1[xbase + e * VT] : z;
+                if constexpr (SP::kScaled) {
+                    m0 = fmaxf(m0, fmaxf(fabsf(x0[e].x), fabsf(x0[e].y)));
+                    m1 = fmaxf(m1, fmaxf(fabsf(x1[e].x), fabsf(x1[e].y)));
+                }
+            }
+            // half: each child's columns scaled into (-1, 1) by a power of 2
+            int e0 = 0, e1 = 0;
+            if constexpr (SP::kScaled) {
+                e0 = column_exponent(m0);
+                e1 = column_exponent(m1);
+            }
             typename SP::v4 r0h, r0l, i0h, i0l, r1h, r1l, i1h, i1l;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float2 x0 = xp0[xbase + e * VT], x1 = xp1[xbase + e * VT];
-                SP::put4(r0h, r0l, e, x0.x);
-                SP::put4(i0h, i0l, e, x0.y);
-                SP::put4(r1h, r1l, e, x1.x);
-                SP::put4(i1h, i1l, e, x1.y);
+                SP::put4(r0h, r0l, e, SP::kScaled ? ldexpf(x0[e].x, -e0) : x0[e].x);
+                SP::put4(i0h, i0l, e, SP::kScaled ? ldexpf(x0[e].y, -e0) : x0[e].y);
+                SP::put4(r1h, r1l, e, SP::kScaled ? ldexpf(x1[e].x, -e1) : x1[e].x);
+                SP::put4(i1h, i1l, e, SP::kScaled ? ldexpf(x1[e].y, -e1) : x1[e].y);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
@@ -395,6 +453,15 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                 y0i = SP::mma16(alo[i], i0h, y0i);
                 y1r = SP::mma16(alo[i], r1h, y1r);
                 y1i = SP::mma16(alo[i], i1h, y1i);
+                if constexpr (SP::kScaled) {
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        y0r[jj] = ldexpf(y0r[jj], e0);
+                        y0i[jj] = ldexpf(y0i[jj], e0);
+                        y1r[jj] = ldexpf(y1r[jj], e1);
+                        y1i[jj] = ldexpf(y1i[jj], e1);
+                    }
+                }
                 // rows t >= r_out read finite twiddles and are not stored
                 const float2* tp = twl + (unit * 4 + i * 2) * r_out + 4 * g;
                 floatx4 orr, oii;

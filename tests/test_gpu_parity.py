@@ -216,6 +216,28 @@ def test_split_precision_accuracy(apply_path, precision, n, q, r, nvec):
     assert err < SPLIT_TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("scale", [1e6, 1e-6])
+def test_split_precision_any_input_scale(apply_path, precision, scale):
+    # half parts have a narrow range: the panel columns are scaled by powers
+    # of two inside the products, so the relative error does not depend on
+    # the magnitude of f (1e6 * |f| overflows half without the scaling)
+    if apply_path != "fused":
+        pytest.skip("split precisions run on the fused MFMA passes only")
+    n, q = 4096, 10
+    log(f"case split scale {precision} {scale:g}")
+    f32, f, _ = inputs(1, n, 2, 960)
+    f32 = (f32 * np.float32(scale)).astype(np.complex64)
+    with _plan(1, n, "fio1d", q, nvec=2, precision=precision) as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_apply(1, n, "fio1d", PHASE_PARAMS["fio1d"], q,
+                          f32.astype(np.complex128))
+    assert np.all(np.isfinite(g))
+    err = np.max(rel(g, ref))
+    log(f"  rel err {err:.3e}")
+    assert err < SPLIT_TOL[precision]
+
+
 def test_split_precision_rejected_where_not_built(apply_path):
     import paper_1803_04128_amd as bfm
     with pytest.raises(bfm.BfError):
