@@ -168,3 +168,38 @@ def test_2d_default_is_per_step_mfma():
     bfm = _bfm()
     with bfm.Plan(2, 32, "radon2d", PHASE_PARAMS["radon2d"], q=7) as pl:
         assert pl.config()["path"] == "per_step_mfma"
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_split_precision_graph_and_autotune(precision):
+    # only the fused MFMA passes compute the split precisions: the autotuner
+    # must time those alone, and a captured split apply must replay exactly
+    import torch
+    bfm = _bfm()
+    n, q, nvec = 8192, 10, 2
+    log(f"case split exec {precision}")
+    f32, f, ab = inputs(1, n, nvec, 71, amp="sincos", r=2)
+    with bfm.Plan(1, n, "fio1d", PHASE_PARAMS["fio1d"], q=q, amplitude=ab,
+                  precision=precision, max_nvec=nvec) as pl:
+        ft = _to_dev(f32)
+        res = pl.autotune(ft, reps=2)
+        for e in res:
+            log("  ", e)
+            if e["path"] != "fused":
+                assert e["ms"] == -1.0
+        assert any(e["ms"] > 0 for e in res)
+        assert pl.config()["path"] == "fused"
+        eager = pl.apply(ft)
+        gout = torch.zeros_like(ft)
+        gr = pl.graph(ft, gout)
+        try:
+            for _ in range(3):
+                gr.launch()
+                torch.cuda.synchronize()
+                assert torch.equal(gout, eager)
+        finally:
+            gr.close()
+    ref = butterfly_matvec(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, ab[0],
+                           ab[1], f)
+    tol = {"bf16x3": 1e-4, "fp16x3": 1e-5}[precision]
+    assert np.max(rel(_host(eager), ref)) < tol
