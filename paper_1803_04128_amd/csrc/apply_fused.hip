@@ -650,6 +650,19 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
                 a.sub_split *= 2;
         a.n_sub /= a.sub_split;
         a.nspatial *= a.sub_split;
+        // a tail pass with few A groups splits its B groups over more
+        // workgroups; the split depends on the plan only (not on the batch
+        // size), so the summation order is the same for every batch, and
+        // the partial outputs fit the state buffer this pass does not use
+        a.x_split = 1;
+        a.gpart = bufs[which];
+        if (!is_xi && a.has_tail && mfma_mode(p, Vt) && k > 0 && !a.has_head &&
+            (long long)a.Gk * Vt <= (long long)kMfmaTileCap * 8)   // MFMA pass
+            while (a.x_split < a.n_sub && a.nspatial * a.x_split < 256 &&
+                   2 * a.x_split <= p.max_rank * p.r_amp)
+                a.x_split *= 2;
+        a.n_sub /= a.x_split;
+        a.nspatial *= a.x_split;
         a.xcd_map = (a.nspatial % 8 == 0) ? 1 : 0;
         if (lds > 160 * 1024) return "fused pass does not fit in LDS";
         {
@@ -708,6 +721,13 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         if (e != hipSuccess)
             return std::string("fused pass launch: ") + hipGetErrorString(e);
         prof.end(name, in_bytes + out_bytes + fbytes, flops);
+        if (a.x_split > 1) {
+            ProfScope ps2(p, st);
+            std::string err = launch_sum_parts(a, nv, st);
+            if (!err.empty()) return err;
+            ps2.end("sum_parts", (a.x_split + 1.0) * nv * N * 8.0,
+                    (double)(a.x_split - 1) * nv * N * 2.0);
+        }
         cur = bufs[which];
         which ^= 1;
     }

@@ -769,12 +769,16 @@ x_pass_mfma(PassArgs a) {
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
     zero_pass_lds(lds, tsz + 2 * wsz, lds + tsz + 2 * wsz);
+    // with x_split > 1 the workgroup takes part `part` of the B groups
+    const int part = (int)(spatial % a.x_split);
+    spatial /= a.x_split;
     const long long ap_grp = a.has_tail ? spatial : spatial / a.nbg;
     const long long bg0 = a.has_tail ? 0 : spatial % a.nbg;
     floatx4 tacc[2 * wave_tiles<VT>()];
 #pragma unroll
     for (int m = 0; m < 2 * wave_tiles<VT>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int sub = 0; sub < a.n_sub; ++sub) {
+    for (int si = 0; si < a.n_sub; ++si) {
+        const int sub = part * a.n_sub + si;
         const long long bg = a.has_tail ? sub : bg0;
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
         load_tile(a, T, p0, a.lv[0].r_in, chunk);
@@ -859,8 +863,36 @@ x_pass_mfma(PassArgs a) {
                 sum.y += v.y;
             }
         }
-        a.g[(size_t)(v0 + vl) * a.N + x] = sum;
+        if (a.x_split > 1)   // partial sum over this part's B groups
+            a.gpart[((size_t)part * nvs + v0 + vl) * a.N + x] = sum;
+        else
+            a.g[(size_t)(v0 + vl) * a.N + x] = sum;
     }
+}
+
+// g[v][x] = sum over the parts of a split tail pass, in part order (the
+// same order for every batch size, so results do not depend on it).
+__global__ void __launch_bounds__(256) sum_parts(const float2* part,
+                                                 float2* g, int parts,
+                                                 long long count) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float2 s = part[i];
+    for (int p = 1; p < parts; ++p) {
+        const float2 v = part[(size_t)p * count + i];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    g[i] = s;
+}
+
+std::string launch_sum_parts(const PassArgs& a, int nv, hipStream_t st) {
+    const long long count = (long long)nv * a.N;
+    hipLaunchKernelGGL(sum_parts, dim3((unsigned)((count + 255) / 256)),
+                       dim3(256), 0, st, a.gpart, a.g, a.x_split, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return std::string("sum_parts launch: ") + hipGetErrorString(e);
+    return "";
 }
 
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {

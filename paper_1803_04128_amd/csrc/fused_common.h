@@ -52,6 +52,10 @@ struct PassArgs {
     const float2* bamp;
     int head_side, head_r;
     int n_sub;                // sub-iterations per workgroup
+    int x_split;              // tail x passes: workgroups sharing the
+                              // sub-iterations (B groups) of one A group;
+                              // each writes its partial g to gpart
+    float2* gpart;            // [x_split][nv][N] partial outputs
     int sub_split;            // xi head passes: workgroups sharing the
                               // sub-iterations of one spatial group (the
                               // block index carries the part)
@@ -255,5 +259,6 @@ std::string launch_mfma_pass(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st);
 // Dynamic LDS bytes of an MFMA pass with these arguments.
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi);
+std::string launch_sum_parts(const PassArgs& a, int nv, hipStream_t st);
 
 }  // namespace bfi
