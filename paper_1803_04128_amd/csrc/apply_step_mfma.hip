@@ -189,51 +189,54 @@ __global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
 }
 
 // Switch (Algorithm 4.1 step 4 regrouped), block = (pair, 16-column tile),
-// wave m = row tile m of nu = S mu; the complex block S is staged in LDS and
-// enters as two real A operands (Re S, Im S).
+// wave m = row tile m of nu = S mu.  The complex block S enters as two real
+// A operands (Re S, Im S) read straight from HBM in the A layout (each lane
+// its row and four consecutive K columns), all K steps issued before the
+// input panel is staged in LDS, so that the reads overlap the staging and
+// the small LDS footprint lets many blocks stream S at once.
 __global__ void __launch_bounds__(kMaxMT * 64) switch_step_mfma(StepArgs a) {
     extern __shared__ float2 lds_step[];
-    const int ldS = a.r_in + 1;                         // padded row
     float2* xs = lds_step;                              // [r_in][16]
-    float2* Ss = xs + (size_t)a.r_in * kCols;           // [r_out][r_in + 1]
     const int nct = (a.Vc + kCols - 1) / kCols;
     const long long p = (long long)blockIdx.x / nct;
     const int col0 = (int)((long long)blockIdx.x - p * nct) * kCols;
     const int shiftB = a.dim * (a.L - a.level);
     const long long bm = p & ((1LL << shiftB) - 1);
+    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, n = lane & 15;
+    const int KS = (a.r_in + 3) >> 2;
+    const int row = 16 * m + n;
+    const float2* S = a.S + p * a.r_out * a.r_in + (size_t)row * a.r_in;
+    float2 sv[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        const int s = 4 * ks + kq;
+        sv[ks] = (ks < KS && row < a.r_out && s < a.r_in) ? S[s]
+                                                        : make_float2(0.f, 0.f);
+    }
     const int nthr = blockDim.x;
     for (int e = threadIdx.x; e < a.r_in * kCols; e += nthr) {
-        const int n = e % kCols, s = e / kCols;
-        const int col = col0 + n;
+        const int nn = e % kCols, s = e / kCols;
+        const int col = col0 + nn;
         float2 v = make_float2(0.f, 0.f);
         if (col < a.Vc)
             v = a.reads_f ? head_value(a, bm, s, col)
                           : a.in[(p * a.r_in + s) * a.Vc + col];
         xs[e] = v;
     }
-    const int nS = a.r_out * a.r_in;
-    const float2* S = a.S + p * nS;
-    for (int e = threadIdx.x; e < nS; e += nthr) {
-        const int t = e / a.r_in, s = e - t * a.r_in;
-        Ss[t * ldS + s] = S[e];
-    }
     __syncthreads();
-    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kq = lane >> 4, n = lane & 15;
-    const int KS = (a.r_in + 3) >> 2;
-    const int row = 16 * m + n;
     floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
-    for (int ks = 0; ks < KS; ++ks) {
-        const int s = 4 * ks + kq;
-        float2 sv = make_float2(0.f, 0.f), xv = make_float2(0.f, 0.f);
-        if (s < a.r_in) {
-            xv = xs[s * kCols + n];
-            if (row < a.r_out) sv = Ss[row * ldS + s];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        if (ks < KS) {                                  // uniform
+            const int s = 4 * ks + kq;
+            const float2 xv = s < a.r_in ? xs[s * kCols + n]
+                                         : make_float2(0.f, 0.f);
+            p1 = mma(sv[ks].x, xv.x, p1);
+            p2 = mma(sv[ks].y, xv.y, p2);
+            p3 = mma(sv[ks].x, xv.y, p3);
+            p4 = mma(sv[ks].y, xv.x, p4);
         }
-        p1 = mma(sv.x, xv.x, p1);
-        p2 = mma(sv.y, xv.y, p2);
-        p3 = mma(sv.x, xv.y, p3);
-        p4 = mma(sv.y, xv.x, p4);
     }
     const int col = col0 + n;
     if (col >= a.Vc) return;
@@ -248,9 +251,7 @@ __global__ void __launch_bounds__(kMaxMT * 64) switch_step_mfma(StepArgs a) {
 
 // LDS bytes of one block of the step's kernel.
 size_t step_mfma_lds(const Plan& p, const Step& s) {
-    if (s.kind == STEP_SWITCH)
-        return ((size_t)s.r_in * kCols + (size_t)s.r_out * (s.r_in + 1)) *
-               sizeof(float2);
+    if (s.kind == STEP_SWITCH) return (size_t)s.r_in * kCols * sizeof(float2);
     const int rt = s.kind == STEP_XI ? s.r_in : s.r_out;
     return ((size_t)p.R * s.r_in * kCols + (size_t)p.R * p.R * rt) *
            sizeof(float2);
