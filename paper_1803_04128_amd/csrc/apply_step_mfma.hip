@@ -74,16 +74,27 @@ __global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
         const float* am = a.amat + (size_t)c * MT * KS * 64 + lane;
         const float2* w = ws + (i * R + c) * a.r_in;
         const float2* x = xs + (size_t)c * a.r_in * kCols + n;
+        // the next K step's A operands are read while this one multiplies
+        float an[kMaxMT];
+#pragma unroll
+        for (int m = 0; m < kMaxMT; ++m) an[m] = m < MT ? am[m * KS * 64] : 0.f;
         for (int ks = 0; ks < KS; ++ks) {
+            float ac[kMaxMT];
+#pragma unroll
+            for (int m = 0; m < kMaxMT; ++m) ac[m] = an[m];
+            if (ks + 1 < KS) {
+#pragma unroll
+                for (int m = 0; m < kMaxMT; ++m)
+                    if (m < MT) an[m] = am[(m * KS + ks + 1) * 64];
+            }
             const int s = 4 * ks + kq;
             float2 z = make_float2(0.f, 0.f);
             if (s < a.r_in) z = cmul(w[s], x[s * kCols]);
 #pragma unroll
             for (int m = 0; m < kMaxMT; ++m) {
                 if (m < MT) {
-                    const float av = am[(m * KS + ks) * 64];
-                    accr[m] = mma(av, z.x, accr[m]);
-                    acci[m] = mma(av, z.y, acci[m]);
+                    accr[m] = mma(ac[m], z.x, accr[m]);
+                    acci[m] = mma(ac[m], z.y, acci[m]);
                 }
             }
         }
@@ -145,15 +156,26 @@ __global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
 #pragma unroll
         for (int m = 0; m < kMaxMT; ++m) yr[m] = yi[m] = zero4();
         const float2* x = xs + (size_t)c * a.r_in * kCols + n;
+        // the next K step's A operands are read while this one multiplies
+        float an[kMaxMT];
+#pragma unroll
+        for (int m = 0; m < kMaxMT; ++m) an[m] = m < MT ? am[m * KS * 64] : 0.f;
         for (int ks = 0; ks < KS; ++ks) {
+            float ac[kMaxMT];
+#pragma unroll
+            for (int m = 0; m < kMaxMT; ++m) ac[m] = an[m];
+            if (ks + 1 < KS) {
+#pragma unroll
+                for (int m = 0; m < kMaxMT; ++m)
+                    if (m < MT) an[m] = am[(m * KS + ks + 1) * 64];
+            }
             const int s = 4 * ks + kq;
             const float2 xv = s < a.r_in ? x[s * kCols] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int m = 0; m < kMaxMT; ++m) {
                 if (m < MT) {
-                    const float av = am[(m * KS + ks) * 64];
-                    yr[m] = mma(av, xv.x, yr[m]);
-                    yi[m] = mma(av, xv.y, yi[m]);
+                    yr[m] = mma(ac[m], xv.x, yr[m]);
+                    yi[m] = mma(ac[m], xv.y, yi[m]);
                 }
             }
         }
