@@ -107,10 +107,17 @@ template <> struct Split<BF_FP16X3> {
 // m is this lane's largest magnitude; the lanes 16, 32 and 48 apart hold
 // the same B column (other K rows), so after the exchange every lane of the
 // column has the column maximum M = f 2^e, f in [0.5, 1), and the column
-// scaled by 2^-e lies in (-1, 1) (zero columns get e = 0).
+// scaled by 2^-e lies in (-1, 1) (zero columns get e = 0).  The exchange
+// uses the row-swapping lane permutes (checked by an in-bounds probe: with
+// both operands v, permlane16_swap returns rows {0,0,2,2} and {1,1,3,3} of
+// v, permlane32_swap the lower and the upper half of v).
 __device__ __forceinline__ int column_exponent(float m) {
-    m = fmaxf(m, __shfl_xor(m, 16));
-    m = fmaxf(m, __shfl_xor(m, 32));
+    const auto p16 = __builtin_amdgcn_permlane16_swap(
+        __float_as_uint(m), __float_as_uint(m), false, false);
+    m = fmaxf(__uint_as_float(p16[0]), __uint_as_float(p16[1]));
+    const auto p32 = __builtin_amdgcn_permlane32_swap(
+        __float_as_uint(m), __float_as_uint(m), false, false);
+    m = fmaxf(__uint_as_float(p32[0]), __uint_as_float(p32[1]));
     int e = 0;
     (void)frexpf(m, &e);
     return e;

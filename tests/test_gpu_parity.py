@@ -197,7 +197,8 @@ SPLIT_TOL = {"bf16x3": 1e-4, "fp16x3": 1e-5}
 
 @pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
 @pytest.mark.parametrize("n,q,r,nvec", [(4096, 10, 4, 3), (1 << 14, 8, 1, 2),
-                                        (1 << 13, 10, 2, 5)])
+                                        (1 << 13, 10, 2, 5), (1 << 13, 7, 1, 3),
+                                        (1 << 12, 13, 2, 2)])
 def test_split_precision_accuracy(apply_path, precision, n, q, r, nvec):
     if apply_path != "fused":
         pytest.skip("split precisions run on the fused MFMA passes only")
