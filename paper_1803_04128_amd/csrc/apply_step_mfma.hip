@@ -32,10 +32,12 @@ __device__ __forceinline__ floatx4 zero4() {
 
 }  // namespace
 
-// xi step (eq. (eqn:2) regrouped), block = (unit, 16-column tile), wave i =
-// output child i: D_i = sum_c M_c (W_{i,c} . X_c).
-template <int R>
-__global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
+// xi step (eq. (eqn:2) regrouped), block = (unit, 16-column tile); WPC waves
+// per output child i share its row tiles (wave h takes tiles h, h + WPC,
+// ...): D_i = sum_c M_c (W_{i,c} . X_c).
+template <int R, int WPC>
+__global__ void __launch_bounds__(R * 64 * WPC) xi_step_mfma(StepArgs a) {
+    constexpr int NT = kMaxMT / WPC;                    // tiles per wave
     extern __shared__ float2 lds_step[];
     float2* xs = lds_step;                              // [R][r_in][16]
     float2* ws = xs + (size_t)R * a.r_in * kCols;       // [R][R][r_in]
@@ -45,7 +47,7 @@ __global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
     const int shiftB = a.dim * (a.L - a.level);
     const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nin = R * a.r_in * kCols;
-    for (int e = threadIdx.x; e < nin; e += R * 64) {
+    for (int e = threadIdx.x; e < nin; e += R * 64 * WPC) {
         const int n = e % kCols, cs = e / kCols;
         const int c = cs / a.r_in, s = cs - c * a.r_in;
         const int col = col0 + n;
@@ -61,40 +63,46 @@ __global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
         xs[e] = v;
     }
     const int ntw = R * R * a.r_in;
-    for (int e = threadIdx.x; e < ntw; e += R * 64)
+    for (int e = threadIdx.x; e < ntw; e += R * 64 * WPC)
         ws[e] = a.tw[u * ntw + e];
     __syncthreads();
-    const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = wave / WPC, h = wave - i * WPC;
     const int kq = lane >> 4, n = lane & 15;
     const int MT = (a.r_out + 15) >> 4, KS = (a.r_in + 3) >> 2;
-    floatx4 accr[kMaxMT], acci[kMaxMT];
+    floatx4 accr[NT], acci[NT];
 #pragma unroll
-    for (int m = 0; m < kMaxMT; ++m) accr[m] = acci[m] = zero4();
+    for (int q = 0; q < NT; ++q) accr[q] = acci[q] = zero4();
     for (int c = 0; c < R; ++c) {
         const float* am = a.amat + (size_t)c * MT * KS * 64 + lane;
         const float2* w = ws + (i * R + c) * a.r_in;
         const float2* x = xs + (size_t)c * a.r_in * kCols + n;
         // the next K step's A operands are read while this one multiplies
-        float an[kMaxMT];
+        float an[NT];
 #pragma unroll
-        for (int m = 0; m < kMaxMT; ++m) an[m] = m < MT ? am[m * KS * 64] : 0.f;
+        for (int q = 0; q < NT; ++q) {
+            const int m = h + q * WPC;
+            an[q] = m < MT ? am[m * KS * 64] : 0.f;
+        }
         for (int ks = 0; ks < KS; ++ks) {
-            float ac[kMaxMT];
+            float ac[NT];
 #pragma unroll
-            for (int m = 0; m < kMaxMT; ++m) ac[m] = an[m];
+            for (int q = 0; q < NT; ++q) ac[q] = an[q];
             if (ks + 1 < KS) {
 #pragma unroll
-                for (int m = 0; m < kMaxMT; ++m)
-                    if (m < MT) an[m] = am[(m * KS + ks + 1) * 64];
+                for (int q = 0; q < NT; ++q) {
+                    const int m = h + q * WPC;
+                    if (m < MT) an[q] = am[(m * KS + ks + 1) * 64];
+                }
             }
             const int s = 4 * ks + kq;
             float2 z = make_float2(0.f, 0.f);
             if (s < a.r_in) z = cmul(w[s], x[s * kCols]);
 #pragma unroll
-            for (int m = 0; m < kMaxMT; ++m) {
-                if (m < MT) {
-                    accr[m] = mma(ac[m], z.x, accr[m]);
-                    acci[m] = mma(ac[m], z.y, acci[m]);
+            for (int q = 0; q < NT; ++q) {
+                if (h + q * WPC < MT) {                 // uniform
+                    accr[q] = mma(ac[q], z.x, accr[q]);
+                    acci[q] = mma(ac[q], z.y, acci[q]);
                 }
             }
         }
@@ -104,22 +112,25 @@ __global__ void __launch_bounds__(R * 64) xi_step_mfma(StepArgs a) {
     const long long pout = ((ap * R + i) << shiftB) + b;
     float2* o = a.out + pout * a.r_out * a.Vc + col;
 #pragma unroll
-    for (int m = 0; m < kMaxMT; ++m) {
+    for (int q = 0; q < NT; ++q) {
+        const int m = h + q * WPC;
         if (m < MT) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int t = 16 * m + 4 * kq + j;
                 if (t < a.r_out)
-                    o[(size_t)t * a.Vc] = make_float2(accr[m][j], acci[m][j]);
+                    o[(size_t)t * a.Vc] = make_float2(accr[q][j], acci[q][j]);
             }
         }
     }
 }
 
-// x step (eq. (eqn:3) regrouped), block = (unit, 16-column tile), wave i =
-// output child i: D_i = sum_c T_{i,c} . (M_i X_c).
-template <int R>
-__global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
+// x step (eq. (eqn:3) regrouped), block = (unit, 16-column tile); WPC waves
+// per output child i share its row tiles (wave h takes tiles h, h + WPC,
+// ...): D_i = sum_c T_{i,c} . (M_i X_c).
+template <int R, int WPC>
+__global__ void __launch_bounds__(R * 64 * WPC) x_step_mfma(StepArgs a) {
+    constexpr int NT = kMaxMT / WPC;                    // tiles per wave
     extern __shared__ float2 lds_step[];
     float2* xs = lds_step;                              // [R][r_in][16]
     float2* ts = xs + (size_t)R * a.r_in * kCols;       // [R][R][r_out]
@@ -129,7 +140,7 @@ __global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
     const int shiftB = a.dim * (a.L - a.level);
     const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nin = R * a.r_in * kCols;
-    for (int e = threadIdx.x; e < nin; e += R * 64) {
+    for (int e = threadIdx.x; e < nin; e += R * 64 * WPC) {
         const int n = e % kCols, cs = e / kCols;
         const int c = cs / a.r_in, s = cs - c * a.r_in;
         const int col = col0 + n;
@@ -141,54 +152,61 @@ __global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
         xs[e] = v;
     }
     const int ntw = R * R * a.r_out;
-    for (int e = threadIdx.x; e < ntw; e += R * 64)
+    for (int e = threadIdx.x; e < ntw; e += R * 64 * WPC)
         ts[e] = a.tw[u * ntw + e];
     __syncthreads();
-    const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = wave / WPC, h = wave - i * WPC;
     const int kq = lane >> 4, n = lane & 15;
     const int MT = (a.r_out + 15) >> 4, KS = (a.r_in + 3) >> 2;
     const float* am = a.amat + (size_t)i * MT * KS * 64 + lane;
-    floatx4 accr[kMaxMT], acci[kMaxMT];
+    floatx4 accr[NT], acci[NT];
 #pragma unroll
-    for (int m = 0; m < kMaxMT; ++m) accr[m] = acci[m] = zero4();
+    for (int q = 0; q < NT; ++q) accr[q] = acci[q] = zero4();
     for (int c = 0; c < R; ++c) {
-        floatx4 yr[kMaxMT], yi[kMaxMT];
+        floatx4 yr[NT], yi[NT];
 #pragma unroll
-        for (int m = 0; m < kMaxMT; ++m) yr[m] = yi[m] = zero4();
+        for (int q = 0; q < NT; ++q) yr[q] = yi[q] = zero4();
         const float2* x = xs + (size_t)c * a.r_in * kCols + n;
         // the next K step's A operands are read while this one multiplies
-        float an[kMaxMT];
+        float an[NT];
 #pragma unroll
-        for (int m = 0; m < kMaxMT; ++m) an[m] = m < MT ? am[m * KS * 64] : 0.f;
+        for (int q = 0; q < NT; ++q) {
+            const int m = h + q * WPC;
+            an[q] = m < MT ? am[m * KS * 64] : 0.f;
+        }
         for (int ks = 0; ks < KS; ++ks) {
-            float ac[kMaxMT];
+            float ac[NT];
 #pragma unroll
-            for (int m = 0; m < kMaxMT; ++m) ac[m] = an[m];
+            for (int q = 0; q < NT; ++q) ac[q] = an[q];
             if (ks + 1 < KS) {
 #pragma unroll
-                for (int m = 0; m < kMaxMT; ++m)
-                    if (m < MT) an[m] = am[(m * KS + ks + 1) * 64];
+                for (int q = 0; q < NT; ++q) {
+                    const int m = h + q * WPC;
+                    if (m < MT) an[q] = am[(m * KS + ks + 1) * 64];
+                }
             }
             const int s = 4 * ks + kq;
             const float2 xv = s < a.r_in ? x[s * kCols] : make_float2(0.f, 0.f);
 #pragma unroll
-            for (int m = 0; m < kMaxMT; ++m) {
-                if (m < MT) {
-                    yr[m] = mma(ac[m], xv.x, yr[m]);
-                    yi[m] = mma(ac[m], xv.y, yi[m]);
+            for (int q = 0; q < NT; ++q) {
+                if (h + q * WPC < MT) {                 // uniform
+                    yr[q] = mma(ac[q], xv.x, yr[q]);
+                    yi[q] = mma(ac[q], xv.y, yi[q]);
                 }
             }
         }
         const float2* tw = ts + (i * R + c) * a.r_out;
 #pragma unroll
-        for (int m = 0; m < kMaxMT; ++m) {
+        for (int q = 0; q < NT; ++q) {
+            const int m = h + q * WPC;
             if (m < MT) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int t = 16 * m + 4 * kq + j;
                     const float2 T = t < a.r_out ? tw[t] : make_float2(0.f, 0.f);
-                    accr[m][j] += T.x * yr[m][j] - T.y * yi[m][j];
-                    acci[m][j] += T.x * yi[m][j] + T.y * yr[m][j];
+                    accr[q][j] += T.x * yr[q][j] - T.y * yi[q][j];
+                    acci[q][j] += T.x * yi[q][j] + T.y * yr[q][j];
                 }
             }
         }
@@ -198,13 +216,14 @@ __global__ void __launch_bounds__(R * 64) x_step_mfma(StepArgs a) {
     const long long pout = ((ap * R + i) << shiftB) + b;
     float2* o = a.out + pout * a.r_out * a.Vc + col;
 #pragma unroll
-    for (int m = 0; m < kMaxMT; ++m) {
+    for (int q = 0; q < NT; ++q) {
+        const int m = h + q * WPC;
         if (m < MT) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int t = 16 * m + 4 * kq + j;
                 if (t < a.r_out)
-                    o[(size_t)t * a.Vc] = make_float2(accr[m][j], acci[m][j]);
+                    o[(size_t)t * a.Vc] = make_float2(accr[q][j], acci[q][j]);
             }
         }
     }
@@ -282,8 +301,8 @@ size_t step_mfma_lds(const Plan& p, const Step& s) {
 void init_step_mfma_attrs() {
     static bool done = false;
     if (done) return;
-    const void* fns[] = {(const void*)xi_step_mfma<2>, (const void*)xi_step_mfma<4>,
-                         (const void*)x_step_mfma<2>, (const void*)x_step_mfma<4>,
+    const void* fns[] = {(const void*)xi_step_mfma<2, 1>, (const void*)xi_step_mfma<4, 2>,
+                         (const void*)x_step_mfma<2, 1>, (const void*)x_step_mfma<4, 2>,
                          (const void*)switch_step_mfma};
     for (const void* fn : fns)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -310,18 +329,18 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
         if (nb > 0x7fffffffLL) return "step grid too large";
         if (p.R == 2) {
             if (s.kind == STEP_XI)
-                hipLaunchKernelGGL((xi_step_mfma<2>), dim3((unsigned)nb),
+                hipLaunchKernelGGL((xi_step_mfma<2, 1>), dim3((unsigned)nb),
                                    dim3(128), lds, st, a);
             else
-                hipLaunchKernelGGL((x_step_mfma<2>), dim3((unsigned)nb),
+                hipLaunchKernelGGL((x_step_mfma<2, 1>), dim3((unsigned)nb),
                                    dim3(128), lds, st, a);
         } else {
             if (s.kind == STEP_XI)
-                hipLaunchKernelGGL((xi_step_mfma<4>), dim3((unsigned)nb),
-                                   dim3(256), lds, st, a);
+                hipLaunchKernelGGL((xi_step_mfma<4, 2>), dim3((unsigned)nb),
+                                   dim3(512), lds, st, a);
             else
-                hipLaunchKernelGGL((x_step_mfma<4>), dim3((unsigned)nb),
-                                   dim3(256), lds, st, a);
+                hipLaunchKernelGGL((x_step_mfma<4, 2>), dim3((unsigned)nb),
+                                   dim3(512), lds, st, a);
         }
     }
     hipError_t e = hipGetLastError();
