@@ -148,20 +148,32 @@ def _contract(Lag, z):
     return np.moveaxis(out.reshape(lead + (Lag.shape[0],)), -1, -2)
 
 
-def butterfly_apply(dim, n, phase_kind, phase_params, q, f, a_block=None):
+def butterfly_apply(dim, n, phase_kind, phase_params, q, f, a_block=None,
+                    transpose=False, conjugate=False):
     """Butterfly algorithm (Algorithm 4.1) applied to the columns of
     ``f`` ([V][N], user index order) for the kernel exp(2 pi i Phi).
 
     Returns complex128 [V][N].  ``a_block`` bounds the number of T_X boxes
     handled at once in the switch (memory only, not arithmetic order).
+
+    transpose: factorize the transposed kernel instead (the operator of
+    Scenario 2 in Section 1, applied to vectors indexed by x, giving values
+    indexed by xi): its entry at output index j and input index i is
+    exp(2 pi i Phi(x_i, xi_j)).  The algorithm is unchanged; only the phase
+    evaluation swaps its index roles.  conjugate: the conjugate kernel
+    (with transpose, the adjoint K^H).
     """
     T = Trees(dim, n, q)
     L, h = T.L, T.L // 2
     f = np.atleast_2d(np.asarray(f, np.complex128))
     V = f.shape[0]
+    sgn = -1 if conjugate else 1
 
     def E(ix, jx, sign=1):
-        return expi_phase(phase_kind, phase_params, ix, jx, n, sign)
+        # ix: indices of the output tree, jx: of the input tree
+        if transpose:
+            return expi_phase(phase_kind, phase_params, jx, ix, n, sgn * sign)
+        return expi_phase(phase_kind, phase_params, ix, jx, n, sgn * sign)
 
     # -- Step 2, initialization: A = root of T_X, B = every leaf of T_Omega
     # (eq. (eqn:1)).  A single-index leaf has one point and M_1 = 1.
@@ -253,14 +265,25 @@ def butterfly_apply(dim, n, phase_kind, phase_params, q, f, a_block=None):
     return g
 
 
-def butterfly_matvec(dim, n, phase_kind, phase_params, q, a, b, f):
+def butterfly_matvec(dim, n, phase_kind, phase_params, q, a, b, f,
+                     transpose=False, conjugate=False):
     """g_v = sum_k a_k * BF(b_k * f_v) (eq. (eqn:tg)) for f [nvec][N] and
-    amplitude factors a, b [r][N].  Returns complex128 [nvec][N]."""
+    amplitude factors a, b [r][N].  Returns complex128 [nvec][N].
+
+    transpose: the transposed operator, alpha(x_i, xi_j) exp(2 pi i
+    Phi(x_i, xi_j)) at output j, input i, so the b_k (functions of xi)
+    weight the output and the a_k (functions of x) the input; conjugate:
+    all of it conjugated (with transpose, the adjoint K^H)."""
     f = np.atleast_2d(np.asarray(f, np.complex128))
     a = np.atleast_2d(np.asarray(a, np.complex128))
     b = np.atleast_2d(np.asarray(b, np.complex128))
+    if transpose:
+        a, b = b, a
+    if conjugate:
+        a, b = np.conj(a), np.conj(b)
     r = a.shape[0]
     cols = (b[None, :, :] * f[:, None, :]).reshape(-1, f.shape[1])
-    u = butterfly_apply(dim, n, phase_kind, phase_params, q, cols)
+    u = butterfly_apply(dim, n, phase_kind, phase_params, q, cols,
+                        transpose=transpose, conjugate=conjugate)
     u = u.reshape(f.shape[0], r, f.shape[1])
     return np.sum(a[None, :, :] * u, axis=1)

@@ -13,20 +13,27 @@ import numpy as np
 from .kernel import coords, expi_phase, amplitude
 
 
-def kernel_rows(dim, n, phase_kind, phase_params, amp_kind, rows):
-    """Rows ``rows`` of K as a complex128 array (len(rows), N)."""
+def kernel_rows(dim, n, phase_kind, phase_params, amp_kind, rows,
+                transpose=False, conjugate=False):
+    """Rows ``rows`` of K as a complex128 array (len(rows), N).
+
+    transpose: rows of the transposed matrix K^T (row j holds
+    K(x_i, xi_j) for every i); conjugate: conjugated entries (with
+    transpose, rows of the adjoint K^H)."""
     N = n ** dim
-    ix = coords(np.asarray(rows), dim, n)[:, None, :]
-    jx = coords(np.arange(N), dim, n)[None, :, :]
+    r_idx = coords(np.asarray(rows), dim, n)[:, None, :]
+    a_idx = coords(np.arange(N), dim, n)[None, :, :]
+    ix, jx = (a_idx, r_idx) if transpose else (r_idx, a_idx)
     K = expi_phase(phase_kind, phase_params, ix, jx, n)
     if amp_kind != "one":
         K = K * amplitude(amp_kind, ix, jx, n)
-    return K
+    return np.conj(K) if conjugate else K
 
 
 def dense_rows(dim, n, phase_kind, phase_params, amp_kind, f, rows,
-               block=8):
-    """g[v, rows] = sum_j K[rows, j] f[v, j] for every vector v of ``f``.
+               block=8, transpose=False, conjugate=False):
+    """g[v, rows] = sum_j K[rows, j] f[v, j] for every vector v of ``f``
+    (K^T, conj K or K^H with the flags of kernel_rows).
 
     f: complex array [nvec][N].  Returns complex128 [nvec][len(rows)].
     """
@@ -35,7 +42,7 @@ def dense_rows(dim, n, phase_kind, phase_params, amp_kind, f, rows,
     out = np.empty((f.shape[0], rows.size), np.complex128)
     for s in range(0, rows.size, block):
         K = kernel_rows(dim, n, phase_kind, phase_params, amp_kind,
-                        rows[s:s + block])
+                        rows[s:s + block], transpose, conjugate)
         out[:, s:s + block] = f @ K.T
     return out
 
