@@ -117,6 +117,30 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
             const bf_amplitude* amp, int q, int precision, int max_nvec,
             bf_plan_t* out);
 
+/* ---- transposed and conjugate operators ---------------------------------
+ * Scenario 2 of Section 1 (iterative solvers and preconditioners built on
+ * K) needs K^T and K^H besides K.  K^T(xi_j, x_i) = alpha(x_i, xi_j)
+ * exp(2 pi i Phi(x_i, xi_j)) maps vectors on the x grid to vectors on the
+ * xi grid; it has the form of eq. (eqn:FIO) with x and xi exchanged, so
+ * Algorithm 4.1 factorizes it with the same trees, points and Lagrange
+ * matrices, the phase evaluated with its arguments exchanged (and negated
+ * for the conjugates), and the amplitude factors swapped: b_k weights the
+ * output and a_k the input (conjugated for the conjugates).  The error is
+ * of the same order as for K (Section 3 bounds the ranks in both
+ * variables).  Index order of both grids is the user order of bf_grid.   */
+#define BF_OP_N  0   /* K                         */
+#define BF_OP_T  1   /* K^T                       */
+#define BF_OP_C  2   /* conj(K), entrywise        */
+#define BF_OP_H  3   /* K^H = conj(K)^T           */
+
+/* As bf_plan, for the operator op (BF_OP_*); bf_apply then computes
+ * g[v] = op(K) f[v].  bf_plan(...) equals bf_plan_op(..., BF_OP_N, ...).
+ * The amplitude pointers keep their meaning (a_k on x, b_k on xi).
+ * Returns BF_EINVAL for an unknown op, otherwise as bf_plan.             */
+int bf_plan_op(const bf_grid* grid, const bf_phase* phase,
+               const bf_amplitude* amp, int q, int precision, int max_nvec,
+               int op, bf_plan_t* out);
+
 /* Apply: g[v] = sum_k a_k * BF(b_k * f[v]) for v < nvec (eq. (eqn:tg) with
  * Algorithm 4.1).
  * f, g: device complex64 interleaved, layout [nvec][N], contiguous, owned
@@ -154,6 +178,7 @@ typedef struct bf_plan_info {
     size_t workspace_bytes;/* default workspace (for chunk_nvec vectors)  */
     double flops_per_column;  /* algorithmic flops per apply column       */
     double factor_stream_bytes; /* factor bytes read per apply            */
+    int op;                /* BF_OP_* the plan applies                    */
 } bf_plan_info;
 
 int bf_query(bf_plan_t plan, bf_plan_info* info);

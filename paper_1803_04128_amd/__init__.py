@@ -13,7 +13,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BfError, PATHS, PHASES, PRECISIONS  # noqa: F401
+from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load"]
 
@@ -52,10 +52,15 @@ class Plan:
     q: interpolation points per box and dimension.
     amplitude: None (alpha = 1) or (a, b), complex arrays [r][N].
     precision: "fp32" | "bf16x3" | "fp16x3".
+    op: "N" (K), "T" (K^T), "C" (entrywise conjugate) or "H" (K^H): the
+    operator apply() computes (Scenario 2 of Section 1); a, b keep their
+    meaning (a_k on the x grid, b_k on the xi grid).
     """
 
     def __init__(self, dim, n, phase, params=(), q=8, amplitude=None,
-                 precision="fp32", max_nvec=1):
+                 precision="fp32", max_nvec=1, op="N"):
+        if op not in OPS:
+            raise ValueError(f"op must be one of {sorted(OPS)}")
         self._lib = _lib.load()
         self._h = C.c_void_p()
         grid = _lib.BfGrid(int(dim), int(n))
@@ -73,9 +78,11 @@ class Plan:
             amp = _lib.BfAmplitude(
                 self.r, a.ctypes.data_as(C.POINTER(C.c_double)),
                 b.ctypes.data_as(C.POINTER(C.c_double)))
-        _lib.check(self._lib.bf_plan(
+        _lib.check(self._lib.bf_plan_op(
             C.byref(grid), C.byref(ph), C.byref(amp) if amp else None,
-            int(q), PRECISIONS[precision], int(max_nvec), C.byref(self._h)))
+            int(q), PRECISIONS[precision], int(max_nvec), OPS[op],
+            C.byref(self._h)))
+        self.op = op
         self.dim, self.n, self.q = dim, n, q
         self.N = n ** dim
         self.max_nvec = max_nvec

@@ -10,6 +10,7 @@ BF_OK, BF_EINVAL, BF_ENOMEM, BF_EHIP, BF_EUNSUPPORTED, BF_EBUSY = (
     0, -1, -2, -3, -4, -5)
 PHASES = {"dft": 0, "fio1d": 1, "radon2d": 2, "separable": 3}
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
 
 
 class BfGrid(C.Structure):
@@ -36,7 +37,7 @@ class BfPlanInfo(C.Structure):
                 ("factor_bytes", C.c_size_t),
                 ("workspace_bytes", C.c_size_t),
                 ("flops_per_column", C.c_double),
-                ("factor_stream_bytes", C.c_double)]
+                ("factor_stream_bytes", C.c_double), ("op", C.c_int)]
 
 
 class BfKernelStat(C.Structure):
@@ -57,7 +58,7 @@ class BfTuneEntry(C.Structure):
     _fields_ = [("config", BfConfig), ("ms", C.c_double)]
 
 
-EXPORTS = ["bf_plan", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
            "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
            "bf_set_config", "bf_autotune", "bf_graph_create",
@@ -92,6 +93,9 @@ def load():
     P = C.POINTER
     lib.bf_plan.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude), C.c_int,
                             C.c_int, C.c_int, P(C.c_void_p)]
+    lib.bf_plan_op.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude),
+                               C.c_int, C.c_int, C.c_int, C.c_int,
+                               P(C.c_void_p)]
     lib.bf_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                              C.c_void_p]
     lib.bf_workspace_bytes.argtypes = [C.c_void_p, C.c_int, P(C.c_size_t)]

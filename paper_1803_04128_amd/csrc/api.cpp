@@ -120,9 +120,9 @@ int bf_lagrange(const int* nodes, int r, const double* y, int m,
     return BF_OK;
 }
 
-int bf_plan(const bf_grid* grid, const bf_phase* phase,
-            const bf_amplitude* amp, int q, int precision, int max_nvec,
-            bf_plan_t* out) {
+static int plan_impl(const bf_grid* grid, const bf_phase* phase,
+                     const bf_amplitude* amp, int q, int precision,
+                     int max_nvec, int op, bf_plan_t* out) {
     if (!out) return fail(BF_EINVAL, "bf_plan: out is NULL");
     *out = nullptr;
     if (!grid || !phase) return fail(BF_EINVAL, "bf_plan: NULL grid/phase");
@@ -137,6 +137,8 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
         precision != BF_FP16X3)
         return fail(BF_EINVAL, "bf_plan: unknown precision");
     if (max_nvec < 1) return fail(BF_EINVAL, "bf_plan: max_nvec < 1");
+    if (op < BF_OP_N || op > BF_OP_H)
+        return fail(BF_EINVAL, "bf_plan_op: unknown op");
     if (precision != BF_FP32 && dim != 1)
         return fail(BF_EUNSUPPORTED,
                     "bf_plan: split precisions are implemented for 1D grids");
@@ -178,6 +180,9 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     p.phase.kind = phase->kind;
     p.phase.dim = dim;
     p.phase.n = n;
+    p.op = op;
+    p.phase.transpose = (op & BF_OP_T) != 0;
+    p.phase.conjugate = (op & BF_OP_C) != 0;
     for (int i = 0; i < need; ++i) p.phase.p[i] = phase->params[i];
     // initial execution form (bf_set_config / bf_autotune change it later)
     // default: fused passes in 1D, per-step MFMA launches in 2D (whose
@@ -243,6 +248,18 @@ int bf_plan(const bf_grid* grid, const bf_phase* phase,
     }
     *out = h;
     return BF_OK;
+}
+
+int bf_plan(const bf_grid* grid, const bf_phase* phase,
+            const bf_amplitude* amp, int q, int precision, int max_nvec,
+            bf_plan_t* out) {
+    return plan_impl(grid, phase, amp, q, precision, max_nvec, BF_OP_N, out);
+}
+
+int bf_plan_op(const bf_grid* grid, const bf_phase* phase,
+               const bf_amplitude* amp, int q, int precision, int max_nvec,
+               int op, bf_plan_t* out) {
+    return plan_impl(grid, phase, amp, q, precision, max_nvec, op, out);
 }
 
 static int check_plan(bf_plan_t plan) {
@@ -374,6 +391,7 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
     info->h = p.h;
     info->q = p.q;
     info->r = p.r_amp;
+    info->op = p.op;
     info->precision = p.precision;
     info->N = p.N;
     info->first_xi_level = p.l0;

@@ -77,8 +77,9 @@ __device__ __forceinline__ long long user_index(const int* g, int dim,
 // Phase Phi(x_ix, xi_jx) in FP64.  The bilinear part x . xi =
 // sum_d ix_d (jx_d - n/2) / n is reduced modulo 1 exactly in integers; only
 // the fractional part of Phi is ever used.
-__device__ __forceinline__ double phase_value(const PhaseSpec& P,
-                                              const int* ix, const int* jx) {
+__device__ __forceinline__ double phase_formula(const PhaseSpec& P,
+                                                const int* ix,
+                                                const int* jx) {
     const int n = P.n;
     const double invn = 1.0 / (double)n;
     double bil = 0.0;
@@ -114,6 +115,18 @@ __device__ __forceinline__ double phase_value(const PhaseSpec& P,
             return px + P.p[1] * sqrt(nrm2) + P.p[2] * nrm2 * invn;
         }
     }
+}
+
+// Phase of the factorized kernel at output-tree index ix and input-tree
+// index jx.  For K that is Phi(x_ix, xi_jx).  The transposed kernel K^T
+// (Scenario 2 of Section 1) has the output on the xi grid and the input on
+// the x grid, so its phase is Phi(x_jx, xi_ix); the conjugate kernels
+// negate it.  Algorithm 4.1 is otherwise unchanged.
+__device__ __forceinline__ double phase_value(const PhaseSpec& P,
+                                              const int* ix, const int* jx) {
+    const double v = P.transpose ? phase_formula(P, jx, ix)
+                                 : phase_formula(P, ix, jx);
+    return P.conjugate ? -v : v;
 }
 
 // exp(2 pi i v) with v reduced to [-1/2, 1/2] first (FP64), stored FP32

@@ -88,6 +88,8 @@ struct PhaseSpec {
     int kind;
     int dim;
     int n;
+    int transpose;   // factorize K^T: phase roles of x and xi exchanged
+    int conjugate;   // factorize the conjugate kernel: phase negated
     double p[6];
 };
 
@@ -134,6 +136,7 @@ struct Plan {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     bool has_amp = false;     // false: alpha = 1 (r = 1)
+    int op = 0;               // BF_OP_*: which of K, K^T, conj K, K^H
     float2* a_dev = nullptr;  // [r][N] complex64, nullptr when alpha = 1
     float2* b_dev = nullptr;
     void* ws = nullptr;

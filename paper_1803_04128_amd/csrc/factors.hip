@@ -110,11 +110,14 @@ __global__ void switch_blocks(TwArgs a) {
     }
 }
 
-// complex128 host amplitude factors -> complex64 device
-__global__ void narrow_complex(const double2* in, float2* out, long long m) {
+// complex128 host amplitude factors -> complex64 device (conjugated for
+// the conjugate kernels)
+__global__ void narrow_complex(const double2* in, float2* out, long long m,
+                               int conj) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
          i < m; i += (long long)gridDim.x * blockDim.x)
-        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+        out[i] = make_float2((float)in[i].x,
+                             conj ? -(float)in[i].y : (float)in[i].y);
 }
 
 // 16-bit hi/lo split of the FP32 Lagrange matrices (bfloat16 or half).
@@ -315,8 +318,12 @@ std::string upload_amplitude(Plan& p, const double* a, const double* b) {
     const long long m = (long long)p.r_amp * p.N;
     void* tmp = nullptr;
     HIPCHK(hipMalloc(&tmp, (size_t)m * sizeof(double2)));
-    const double* src[2] = {a, b};
+    // a_k weights the output and b_k the input of K; K^T has its output on
+    // the xi grid, so there the b_k weight the output and the a_k the input
+    const bool tr = (p.op & BF_OP_T) != 0;
+    const double* src[2] = {tr ? b : a, tr ? a : b};
     float2* dst[2] = {p.a_dev, p.b_dev};
+    const int conj = (p.op & BF_OP_C) != 0;
     for (int k = 0; k < 2; ++k) {
         hipError_t e = hipMemcpy(tmp, src[k], (size_t)m * sizeof(double2),
                                  hipMemcpyHostToDevice);
@@ -326,7 +333,7 @@ std::string upload_amplitude(Plan& p, const double* a, const double* b) {
         }
         hipLaunchKernelGGL(narrow_complex, dim3(grid_for(m)),
                            dim3(kFactorBlock), 0, 0, (const double2*)tmp,
-                           dst[k], m);
+                           dst[k], m, conj);
         e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             (void)hipFree(tmp);

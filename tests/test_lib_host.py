@@ -109,3 +109,23 @@ def test_split_precision_2d_unsupported_before_device_use():
                      prec=1)
     assert rc == _lib.BF_EUNSUPPORTED
     assert not h.value
+
+
+@pytest.mark.parametrize("op", [-1, 4, 7])
+def test_plan_op_rejects_unknown_op(op):
+    lib = _lib.load()
+    g = _lib.BfGrid(1, 64)
+    params = (C.c_double * 3)(2.0, 1.0, 8.0)
+    ph = _lib.BfPhase(1, 3, params)
+    h = C.c_void_p()
+    rc = lib.bf_plan_op(C.byref(g), C.byref(ph), None, 8, 0, 1, op,
+                        C.byref(h))
+    assert rc == _lib.BF_EINVAL
+    assert not h.value
+    assert b"op" in lib.bf_last_error()
+
+
+def test_python_plan_rejects_unknown_op():
+    import paper_1803_04128_amd as bfm
+    with pytest.raises(ValueError):
+        bfm.Plan(1, 64, "fio1d", (2.0, 1.0, 8.0), q=8, op="X")
