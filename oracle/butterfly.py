@@ -287,3 +287,16 @@ def butterfly_matvec(dim, n, phase_kind, phase_params, q, a, b, f,
                         transpose=transpose, conjugate=conjugate)
     u = u.reshape(f.shape[0], r, f.shape[1])
     return np.sum(a[None, :, :] * u, axis=1)
+
+
+def butterfly_composition(n, phase_kind, phase_params, q, fhat):
+    """g = L(L f) (eq. (eq:example4)) with every operator applied by its
+    butterfly factorization: the FIO of eq. (eq:example3), then the
+    Fourier coefficients of its output (the DFT-phase kernel's adjoint,
+    scaled by 1/n), then the FIO again.  Each factor has the error of
+    Algorithm 4.1 at q points; the composed error adds them."""
+    inner = butterfly_apply(1, n, phase_kind, phase_params, q, fhat)
+    coef = butterfly_apply(1, n, "dft", (), q, inner, transpose=True,
+                           conjugate=True) / n
+    return butterfly_apply(1, n, phase_kind, phase_params, q, coef)
+

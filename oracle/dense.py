@@ -55,3 +55,25 @@ def rel_err(approx, exact):
     num = np.sqrt(np.sum(np.abs(approx - exact) ** 2, axis=-1))
     den = np.sqrt(np.sum(np.abs(exact) ** 2, axis=-1))
     return num / den
+
+
+def fourier_coefficients(n, h):
+    """Coefficients of the 1D grid function h [nvec][n] in the basis of the
+    DFT-phase kernel: hat_j = (1/n) sum_i h_i exp(-2 pi i x_i xi_j) on the
+    grid of eq. (eqn:1D-xandxi), so that h_i = sum_j hat_j exp(2 pi i x_i
+    xi_j).  This is the transform that turns the output of one FIO of the
+    form of eq. (eq:example3) into the input of the next."""
+    return dense_rows(1, n, "dft", (), "one", h, np.arange(n),
+                      transpose=True, conjugate=True) / n
+
+
+def composition_rows(n, phase_kind, phase_params, fhat, rows):
+    """Rows ``rows`` of g = L(L f) (eq. (eq:example4)), L the FIO of eq.
+    (eq:example3) discretized as eq. (eqn:1D-FIO): L maps coefficients hat f
+    to grid values K hat f; the inner result is re-expanded into Fourier
+    coefficients before the outer L.  fhat: [nvec][n]."""
+    inner = dense_rows(1, n, phase_kind, phase_params, "one", fhat,
+                       np.arange(n))
+    return dense_rows(1, n, phase_kind, phase_params, "one",
+                      fourier_coefficients(n, inner), rows)
+

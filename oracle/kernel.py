@@ -16,7 +16,7 @@ import numpy as np
 
 TWO_PI = 2.0 * np.pi
 # phase kinds whose formula contains the bilinear term x . xi
-BILINEAR_KINDS = ("dft", "fio1d", "radon2d")
+BILINEAR_KINDS = ("dft", "fio1d", "radon2d", "fio1d_warp")
 
 
 def coords(user_idx, dim, n):
@@ -46,6 +46,11 @@ def _smooth(kind, params, ix, jx, n):
         p0, p1, p2 = params
         c = (p0 + p1 * np.sin(TWO_PI * x[..., 0])) / p2
         return c * np.abs(xi[..., 0])
+    if kind == "fio1d_warp":
+        # eq. (eqn:FIOK2): Phi = x xi + c(x) xi (the composition example)
+        p0, p1, p2 = params
+        c = (p0 + p1 * np.sin(TWO_PI * x[..., 0])) / p2
+        return c * xi[..., 0]
     if kind == "radon2d":
         p0, p1, p2, p3, p4, p5 = params
         s1, s2 = np.sin(TWO_PI * x[..., 0]), np.sin(TWO_PI * x[..., 1])

@@ -5,6 +5,8 @@ HIP library; here they are only named and parameterised):
 
 * ``dft``       Phi = x . xi
 * ``fio1d``     Phi = x xi + c(x) |xi|, c(x) = (p0 + p1 sin 2 pi x) / p2
+* ``fio1d_warp`` Phi = x xi + c(x) xi with the same c(x) (the composition
+                example, eq. (eqn:FIOK2))
 * ``radon2d``   Phi = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
                 c1 = (p0 + p1 sin 2 pi x1 sin 2 pi x2) / p2,
                 c2 = (p3 + p4 cos 2 pi x1 cos 2 pi x2) / p5
@@ -23,6 +25,9 @@ PHASE_PARAMS = {
     # the paper's 1D FIO experiment: c(x) = (2 + 0.2 sin 2 pi x) / 16
     "fio1d_paper": (2.0, 0.2, 16.0),
     "radon2d": (2.0, 1.0, 16.0, 2.0, 1.0, 16.0),
+    # the composition example: Phi = x xi + c(x) xi,
+    # c(x) = (2 + 0.2 sin 2 pi x) / 16
+    "fio1d_warp": (2.0, 0.2, 16.0),
     "separable": (3.7, 0.37, 0.011),
 }
 
@@ -50,7 +55,7 @@ class Workload:
 
     @property
     def phase_kind(self):
-        return "fio1d" if self.phase.startswith("fio1d") else self.phase
+        return "fio1d" if self.phase == "fio1d_paper" else self.phase
 
     @property
     def phase_params(self):
