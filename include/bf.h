@@ -47,6 +47,10 @@ extern "C" {
 /* BF_PHASE_DFT:       Phi = x . xi                                 (no params)
  * BF_PHASE_FIO1D:     Phi = x xi + c(x)|xi|, c(x) = (p0 + p1 sin 2 pi x)/p2
  *                     (Section 5, eq. (eqn:1D-FIO-kernal) with general c)
+ * BF_PHASE_FIO1D_WARP: Phi = x xi + c(x) xi with the same c(x) (1D): the
+ *                     FIO of the composition example, eq. (eqn:FIOK2); it
+ *                     evaluates the Fourier series of its input at
+ *                     x + c(x).
  * BF_PHASE_RADON2D:   Phi = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
  *                     c1 = (p0 + p1 sin 2 pi x1 sin 2 pi x2) / p2,
  *                     c2 = (p3 + p4 cos 2 pi x1 cos 2 pi x2) / p5
@@ -58,6 +62,7 @@ extern "C" {
 #define BF_PHASE_FIO1D      1
 #define BF_PHASE_RADON2D    2
 #define BF_PHASE_SEPARABLE  3
+#define BF_PHASE_FIO1D_WARP 4
 
 /* ---- arithmetic of the apply ------------------------------------------- */
 /* BF_FP32:   FP32 complex state and factors, FP32 vector arithmetic.
@@ -151,6 +156,24 @@ int bf_plan_op(const bf_grid* grid, const bf_phase* phase,
  * Returns BF_EINVAL for nvec < 1, nvec > max_nvec, null or overlapping
  * pointers.                                                               */
 int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream);
+
+/* Chained applies: g = P_{count-1}( ... P_1(P_0 f)) for the plans
+ * plans[0 .. count-1] (the same plan may appear more than once), e.g. the
+ * composition of two FIOs of eq. (eq:example4): the FIO, then the Fourier
+ * coefficients of its output (a BF_OP_H plan of the DFT phase with the
+ * constant amplitude 1/N), then the FIO again.  Every plan must have the
+ * same N, live on the current device and accept nvec vectors.
+ * f, g: device complex64 [nvec][N], g must not overlap f.
+ * tmp: device complex64 [nvec][N] owned by the caller, the intermediate
+ *    results ping-pong between tmp and g (f is only read); may be NULL for
+ *    count == 1, must not overlap f or g.
+ * Asynchronous on stream like bf_apply, and each apply uses its plan's
+ * own workspace, so chains that share a plan must not overlap in time.
+ * Returns BF_EINVAL (checked before anything is launched) for count < 1,
+ * an invalid plan, mismatched N, nvec out of a plan's range, or null or
+ * overlapping buffers.                                                   */
+int bf_apply_chain(const bf_plan_t* plans, int count, int nvec,
+                   const void* f, void* g, void* tmp, void* stream);
 
 /* Workspace bytes bf_apply_ws needs for nvec vectors. */
 int bf_workspace_bytes(bf_plan_t plan, int nvec, size_t* bytes);

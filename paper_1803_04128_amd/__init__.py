@@ -15,7 +15,8 @@ import numpy as np
 from . import _lib
 from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
-__all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load"]
+__all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
+           "apply_chain", "fourier_coefficients_plan"]
 
 
 def load():
@@ -239,3 +240,40 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def apply_chain(plans, f, out=None, tmp=None, stream=None):
+    """g = P_m(... P_2(P_1 f)) through bf_apply_chain, e.g. the composition
+    of two FIOs of eq. (eq:example4) as [L, F, L] with F from
+    fourier_coefficients_plan.  tmp: an optional complex64 tensor like f
+    for the intermediate results (allocated when not given)."""
+    plans = list(plans)
+    if not plans:
+        raise ValueError("apply_chain needs at least one plan")
+    squeeze = f.dim() == 1
+    f2, out, nvec = plans[0]._args(f, out)
+    if tmp is None and len(plans) > 1:
+        import torch
+        tmp = torch.empty_like(f2)
+    if tmp is not None and (tmp.shape != f2.shape or tmp.dtype != f2.dtype
+                            or not tmp.is_contiguous()):
+        raise ValueError("tmp must be a contiguous complex64 like f")
+    arr = (C.c_void_p * len(plans))(*[p._h.value for p in plans])
+    _lib.check(plans[0]._lib.bf_apply_chain(
+        arr, len(plans), nvec, C.c_void_p(f2.data_ptr()),
+        C.c_void_p(out.data_ptr()),
+        C.c_void_p(tmp.data_ptr() if tmp is not None else None),
+        Plan._stream(stream)))
+    return out.reshape(-1) if squeeze else out
+
+
+def fourier_coefficients_plan(n, q=10, precision="fp32", max_nvec=1):
+    """The plan of hat_j = (1/n) sum_i h_i exp(-2 pi i x_i xi_j): the
+    adjoint of the DFT-phase kernel with the constant amplitude 1/n, which
+    turns the grid values one FIO of eq. (eq:example3) produces into the
+    coefficients the next one takes."""
+    a = np.full((1, n), 1.0 / n, np.complex128)
+    b = np.ones((1, n), np.complex128)
+    return Plan(1, n, "dft", (), q=q, amplitude=(a, b), precision=precision,
+                max_nvec=max_nvec, op="H")
+

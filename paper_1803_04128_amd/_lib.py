@@ -8,7 +8,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbf.so")
 
 BF_OK, BF_EINVAL, BF_ENOMEM, BF_EHIP, BF_EUNSUPPORTED, BF_EBUSY = (
     0, -1, -2, -3, -4, -5)
-PHASES = {"dft": 0, "fio1d": 1, "radon2d": 2, "separable": 3}
+PHASES = {"dft": 0, "fio1d": 1, "radon2d": 2, "separable": 3,
+          "fio1d_warp": 4}
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
 
@@ -58,7 +59,7 @@ class BfTuneEntry(C.Structure):
     _fields_ = [("config", BfConfig), ("ms", C.c_double)]
 
 
-EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
            "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
            "bf_set_config", "bf_autotune", "bf_graph_create",
@@ -96,6 +97,9 @@ def load():
     lib.bf_plan_op.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude),
                                C.c_int, C.c_int, C.c_int, C.c_int,
                                P(C.c_void_p)]
+    lib.bf_apply_chain.argtypes = [P(C.c_void_p), C.c_int, C.c_int,
+                                   C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
     lib.bf_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                              C.c_void_p]
     lib.bf_workspace_bytes.argtypes = [C.c_void_p, C.c_int, P(C.c_size_t)]

@@ -148,6 +148,7 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
         case BF_PHASE_FIO1D: need = dim == 1 ? 3 : -1; break;
         case BF_PHASE_RADON2D: need = dim == 2 ? 6 : -1; break;
         case BF_PHASE_SEPARABLE: need = 3; break;
+        case BF_PHASE_FIO1D_WARP: need = dim == 1 ? 3 : -1; break;
         default: return fail(BF_EINVAL, "bf_plan: unknown phase kind");
     }
     if (need < 0) return fail(BF_EINVAL, "bf_plan: phase kind needs another dim");
@@ -307,6 +308,43 @@ int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
 int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream) {
     if (int e = check_plan(plan)) return e;
     return bf_apply_ws(plan, nvec, f, g, plan->p.ws, plan->p.ws_bytes, stream);
+}
+
+static bool overlap(const void* a, const void* b, size_t bytes) {
+    const char* ab = (const char*)a;
+    const char* bb = (const char*)b;
+    return ab < bb + bytes && bb < ab + bytes;
+}
+
+int bf_apply_chain(const bf_plan_t* plans, int count, int nvec,
+                   const void* f, void* g, void* tmp, void* stream) {
+    if (!plans || count < 1)
+        return fail(BF_EINVAL, "bf_apply_chain: no plans");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return fail(BF_EHIP, "bf_apply_chain: no HIP device");
+    long long N = -1;
+    for (int k = 0; k < count; ++k) {
+        if (int e = check_apply(plans[k], nvec, f, g)) return e;
+        const bfi::Plan& p = plans[k]->p;
+        if (N >= 0 && p.N != N)
+            return fail(BF_EINVAL, "bf_apply_chain: plans differ in N");
+        if (p.device != cur)
+            return fail(BF_EINVAL, "bf_apply_chain: plan on another device");
+        N = p.N;
+    }
+    const size_t bytes = (size_t)nvec * N * 8;
+    if (count > 1 && (!tmp || overlap(tmp, f, bytes) || overlap(tmp, g, bytes)))
+        return fail(BF_EINVAL, "bf_apply_chain: tmp NULL or overlapping");
+    // apply k writes g when count - 1 - k is even, tmp otherwise, so the
+    // last one writes g and consecutive applies never read what they write
+    const void* in = f;
+    for (int k = 0; k < count; ++k) {
+        void* out = ((count - 1 - k) % 2 == 0) ? g : tmp;
+        if (int e = bf_apply(plans[k], nvec, in, out, stream)) return e;
+        in = out;
+    }
+    return BF_OK;
 }
 
 int bf_destroy(bf_plan_t plan) {

@@ -97,6 +97,10 @@ __device__ __forceinline__ double phase_formula(const PhaseSpec& P,
             double c = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
             return bil + c * fabs((double)(jx[0] - n / 2));
         }
+        case BF_PHASE_FIO1D_WARP: {
+            double c = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
+            return bil + c * (double)(jx[0] - n / 2);
+        }
         case BF_PHASE_RADON2D: {
             double u = 2.0 * ix[0] * invn, v = 2.0 * ix[1] * invn;
             double c1 = (P.p[0] + P.p[1] * sinpi(u) * sinpi(v)) / P.p[2];

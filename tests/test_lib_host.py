@@ -129,3 +129,12 @@ def test_python_plan_rejects_unknown_op():
     import paper_1803_04128_amd as bfm
     with pytest.raises(ValueError):
         bfm.Plan(1, 64, "fio1d", (2.0, 1.0, 8.0), q=8, op="X")
+
+
+def test_apply_chain_rejects_empty_chain():
+    lib = _lib.load()
+    arr = (C.c_void_p * 1)(None)
+    assert lib.bf_apply_chain(None, 1, 1, None, None, None,
+                              None) == _lib.BF_EINVAL
+    assert lib.bf_apply_chain(arr, 0, 1, None, None, None,
+                              None) == _lib.BF_EINVAL
