@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the execution forms first and keep the "
                          "fastest (bf_autotune)")
+    ap.add_argument("--switch-otf", action="store_true",
+                    help="per-step MFMA form with the switch blocks "
+                         "generated during the apply")
     ap.add_argument("--precision", default=None,
                     choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--nvec", type=int, default=None,
@@ -161,6 +164,8 @@ def main():
     plan_s = time.perf_counter() - t0
     info = plan.info()
 
+    if args.switch_otf:
+        plan.set_config("per_step_mfma", switch_otf=True)
     tune = None
     if args.autotune:
         tune = plan.autotune(f, out=g, reps=2)

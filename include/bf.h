@@ -219,7 +219,11 @@ int bf_query(bf_plan_t plan, bf_plan_info* info);
  *                     vector ALU.
  * BF_PATH_PER_STEP_MFMA: one kernel per computed level with the level's
  *                     shared-matrix and switch contractions on MFMA (ranks
- *                     up to 64: the 2D form).
+ *                     up to 64: the 2D form); optionally with the switch
+ *                     blocks generated during the apply (switch_otf), which
+ *                     trades the N r^2 complex factor stream and its
+ *                     storage for one FP64 phase evaluation and one FP32
+ *                     sincospi per block entry.
  * The initial form is BF_PATH_FUSED (1D) or BF_PATH_PER_STEP_MFMA (2D) with
  * the default tile width; the environment variables BF_FUSED=0|1, BF_MFMA=0
  * and BF_TILE_COLS=<w>, read when the plan is built, override it.  A plan
@@ -236,6 +240,11 @@ typedef struct bf_config {
                             round it down to a power of two that fits   */
     int tile_cols_used;  /* out (bf_get_config, bf_autotune): the width
                             the passes use for a full chunk; 0 per step */
+    int switch_otf;      /* BF_PATH_PER_STEP_MFMA only: 1 = generate each
+                            switch block during the apply (FP64 phase
+                            reduced modulo 1, FP32 sincospi) instead of
+                            reading the stored blocks; a plan whose form
+                            never reads them does not store them        */
 } bf_config;
 
 /* Current execution form of the plan. */
@@ -254,7 +263,9 @@ int bf_set_config(bf_plan_t plan, const bf_config* cfg);
  * (f, g as for bf_apply, nvec vectors, on stream): one warm-up apply, then
  * reps timed applies (hipEvents), and makes the fastest the plan's form.
  * Candidates: BF_PATH_FUSED and BF_PATH_FUSED_VALU at tile widths r * 2^j
- * <= 16, BF_PATH_PER_STEP and BF_PATH_PER_STEP_MFMA; out (capacity cap) receives one entry per
+ * <= 16, BF_PATH_PER_STEP, and BF_PATH_PER_STEP_MFMA with stored and with
+ * on-the-fly switch blocks (the stored blocks are built first if the plan
+ * has none); out (capacity cap) receives one entry per
  * candidate with its mean milliseconds per apply, -1 when the form cannot
  * run the plan, -2 when it resolves to kernels already timed; *count
  * receives the number of candidates.  Synchronous; allocates a temporary

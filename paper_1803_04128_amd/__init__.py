@@ -139,15 +139,20 @@ class Plan:
         return out.reshape(-1) if squeeze else out
 
     def config(self):
-        """Execution form: {"path", "tile_cols", "tile_cols_used"}."""
+        """Execution form: {"path", "tile_cols", "tile_cols_used",
+        "switch_otf"}."""
         c = _lib.BfConfig()
         _lib.check(self._lib.bf_get_config(self._h, C.byref(c)))
         names = {v: k for k, v in PATHS.items()}
         return dict(path=names[c.path], tile_cols=c.tile_cols,
-                    tile_cols_used=c.tile_cols_used)
+                    tile_cols_used=c.tile_cols_used,
+                    switch_otf=bool(c.switch_otf))
 
-    def set_config(self, path="fused", tile_cols=0):
-        c = _lib.BfConfig(PATHS[path], int(tile_cols), 0)
+    def set_config(self, path="fused", tile_cols=0, switch_otf=False):
+        """switch_otf (per_step_mfma only): generate the switch blocks
+        during the apply instead of storing them."""
+        c = _lib.BfConfig(PATHS[path], int(tile_cols), 0,
+                          1 if switch_otf else 0)
         _lib.check(self._lib.bf_set_config(self._h, C.byref(c)))
 
     def autotune(self, f, out=None, reps=3, stream=None):
@@ -163,7 +168,8 @@ class Plan:
             cap, C.byref(cnt)))
         names = {v: k for k, v in PATHS.items()}
         return [dict(path=names[e.config.path], tile_cols=e.config.tile_cols,
-                     tile_cols_used=e.config.tile_cols_used, ms=e.ms)
+                     tile_cols_used=e.config.tile_cols_used,
+                     switch_otf=bool(e.config.switch_otf), ms=e.ms)
                 for e in arr[:min(cnt.value, cap)]]
 
     def graph(self, f, out=None):

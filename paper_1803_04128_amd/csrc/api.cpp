@@ -50,10 +50,11 @@ int path_of(const bfi::Plan& p) {
     return p.mfma ? BF_PATH_FUSED : BF_PATH_FUSED_VALU;
 }
 
-void put_path(bfi::Plan& p, int path, int tile_cols) {
+void put_path(bfi::Plan& p, int path, int tile_cols, int switch_otf) {
     p.fused = path == BF_PATH_FUSED || path == BF_PATH_FUSED_VALU;
     p.mfma = path == BF_PATH_FUSED || path == BF_PATH_PER_STEP_MFMA;
     p.tile_cols = tile_cols;
+    p.switch_otf = switch_otf != 0;
 }
 
 // Validates cfg against the plan and makes it current; the default workspace
@@ -67,13 +68,30 @@ int apply_config(bfi::Plan& p, const bf_config& cfg) {
         return fail(BF_EINVAL,
                     "bf_set_config: tile_cols must be 0 or a multiple of r "
                     "up to 64");
-    const bool f0 = p.fused, m0 = p.mfma;
+    if (cfg.switch_otf != 0 && cfg.switch_otf != 1)
+        return fail(BF_EINVAL, "bf_set_config: switch_otf must be 0 or 1");
+    if (cfg.switch_otf && cfg.path != BF_PATH_PER_STEP_MFMA)
+        return fail(BF_EUNSUPPORTED,
+                    "bf_set_config: on-the-fly switch blocks exist in "
+                    "BF_PATH_PER_STEP_MFMA only");
+    const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
     const int t0 = p.tile_cols;
-    put_path(p, cfg.path, cfg.tile_cols);
+    auto restore = [&] {
+        p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
+    };
+    put_path(p, cfg.path, cfg.tile_cols, cfg.switch_otf);
     std::string err = bfi::check_config(p);
     if (!err.empty()) {
-        p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+        restore();
         return fail(BF_EUNSUPPORTED, "bf_set_config: " + err);
+    }
+    if (bfi::reads_stored_switch(p) && !p.S_arena) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            !bfi::build_switch_blocks(p).empty()) {
+            (void)hipGetLastError();
+            restore();
+            return fail(BF_ENOMEM, "bf_set_config: switch block storage");
+        }
     }
     const size_t need = bfi::workspace_bytes(p, p.max_nvec);
     if (need > p.ws_bytes) {
@@ -81,7 +99,7 @@ int apply_config(bfi::Plan& p, const bf_config& cfg) {
         if (hipDeviceSynchronize() != hipSuccess ||
             hipMalloc(&nw, need) != hipSuccess) {
             (void)hipGetLastError();
-            p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+            restore();
             return fail(BF_ENOMEM, "bf_set_config: workspace allocation");
         }
         (void)hipFree(p.ws);
@@ -181,6 +199,7 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     p.phase.kind = phase->kind;
     p.phase.dim = dim;
     p.phase.n = n;
+    p.phase.invn = 1.0 / (double)n;
     p.op = op;
     p.phase.transpose = (op & BF_OP_T) != 0;
     p.phase.conjugate = (op & BF_OP_C) != 0;
@@ -195,6 +214,8 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     p.mfma = menv ? std::atoi(menv) != 0 : true;
     const char* tenv = std::getenv("BF_TILE_COLS");
     p.tile_cols = tenv ? std::max(0, std::atoi(tenv)) : 0;
+    const char* oenv = std::getenv("BF_SWITCH_OTF");
+    p.switch_otf = oenv && std::atoi(oenv) != 0 && !p.fused && p.mfma;
     if (hipGetDevice(&p.device) != hipSuccess) {
         delete h;
         return fail(BF_EHIP, "bf_plan: no HIP device");
@@ -228,6 +249,8 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     }
     bfi::init_kernel_attrs();
     err = bfi::build_factors(p);
+    if (err.empty() && bfi::reads_stored_switch(p))
+        err = bfi::build_switch_blocks(p);
     if (err.empty() && p.has_amp) err = bfi::upload_amplitude(p, a, b);
     if (err.empty()) {
         p.ws_bytes = bfi::workspace_bytes(p, max_nvec);
@@ -238,6 +261,7 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     }
     if (!err.empty()) {
         if (p.arena) (void)hipFree(p.arena);
+        if (p.S_arena) (void)hipFree(p.S_arena);
         if (p.ws) (void)hipFree(p.ws);
         (void)hipGetLastError();
         delete h;
@@ -356,6 +380,7 @@ int bf_destroy(bf_plan_t plan) {
     int rc = BF_OK;
     if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
     if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
+    if (p.S_arena && hipFree(p.S_arena) != hipSuccess) rc = BF_EHIP;
     if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
     for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
     plan->magic = 0;
@@ -439,7 +464,7 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
                              : (int)p.steps.size() + 1;
     info->max_rank = p.max_rank;
     info->chunk_nvec = p.chunk_nvec;
-    info->factor_bytes = p.arena_bytes;
+    info->factor_bytes = p.arena_bytes + p.S_bytes;
     info->workspace_bytes = p.ws_bytes;
     info->flops_per_column = p.flops_per_column;
     info->factor_stream_bytes = p.factor_stream_bytes;
@@ -454,6 +479,7 @@ int bf_get_config(bf_plan_t plan, bf_config* cfg) {
     cfg->tile_cols = p.tile_cols;
     cfg->tile_cols_used =
         p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
+    cfg->switch_otf = p.switch_otf ? 1 : 0;
     return BF_OK;
 }
 
@@ -481,16 +507,23 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
     // per-step launches; forms that resolve to the same kernels are timed once
     std::vector<bf_config> cand;
     for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
-        for (int tc = p.r_amp; tc <= 16; tc *= 2) cand.push_back({path, tc, 0});
-    cand.push_back({BF_PATH_PER_STEP, 0, 0});
-    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0});
-    const bool f0 = p.fused, m0 = p.mfma;
+        for (int tc = p.r_amp; tc <= 16; tc *= 2)
+            cand.push_back({path, tc, 0, 0});
+    cand.push_back({BF_PATH_PER_STEP, 0, 0, 0});
+    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0});
+    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1});
+    // the stored switch blocks are read by every candidate but one
+    if (!p.S_arena && !bfi::build_switch_blocks(p).empty()) {
+        (void)hipGetLastError();
+        return fail(BF_ENOMEM, "bf_autotune: switch block storage");
+    }
+    const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
     const int t0 = p.tile_cols;
     std::vector<bf_tune_entry> res;
     std::vector<std::pair<int, int>> seen;   // (path, tile width) timed
     size_t ws_need = 0;
     for (auto& c : cand) {
-        put_path(p, c.path, c.tile_cols);
+        put_path(p, c.path, c.tile_cols, c.switch_otf);
         bf_tune_entry e{};
         e.config = c;
         e.ms = -1.0;
@@ -503,7 +536,8 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
             // fused form is then the vector-ALU one
             const bool mf = p.fused && p.mfma && p.dim == 1 &&
                             (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
-            const int key = !p.fused ? (p.mfma ? 3 : 2) : (mf ? 0 : 1);
+            const int key = !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) : 2)
+                                     : (mf ? 0 : 1);
             std::pair<int, int> k{key, e.config.tile_cols_used};
             bool dup = false;
             for (auto& s2 : seen) dup |= s2 == k;
@@ -530,7 +564,8 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
     int best = -1;
     for (size_t i = 0; i < res.size() && err.empty(); ++i) {
         if (res[i].ms != 0.0) continue;
-        put_path(p, res[i].config.path, res[i].config.tile_cols);
+        put_path(p, res[i].config.path, res[i].config.tile_cols,
+                 res[i].config.switch_otf);
         err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);   // warm-up
         if (!err.empty()) break;
         if (hipEventRecord(e0, st) != hipSuccess) { err = "event record"; break; }
@@ -552,7 +587,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    p.fused = f0, p.mfma = m0, p.tile_cols = t0;
+    p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
     if (!err.empty()) {
         (void)hipGetLastError();
         return fail(BF_EHIP, "bf_autotune: " + err);

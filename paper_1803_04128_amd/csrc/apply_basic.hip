@@ -207,9 +207,10 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
     const double head_bytes = N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0);
     for (auto& s : p.steps) {
         StepArgs a = make_step_args(p, s, Vc, f, cur, bufs[which]);
+        const bool otf = p.mfma && p.switch_otf && s.kind == STEP_SWITCH;
         double bytes = (s.reads_f ? head_bytes : N * s.r_in * c8) +
-                       N * s.r_out * c8 + s.tw_elems * 8.0 + s.S_elems * 8.0 +
-                       s.mat_elems * 4.0;
+                       N * s.r_out * c8 + s.tw_elems * 8.0 +
+                       (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
         double flops;
         const char* name;
         if (s.kind == STEP_XI) {
@@ -230,8 +231,9 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
             std::string err = launch_step_mfma(p, s, a, st);
             if (!err.empty()) return err;
             name = s.kind == STEP_XI ? "xi_step_mfma"
-                                     : (s.kind == STEP_X ? "x_step_mfma"
-                                                         : "switch_step_mfma");
+                   : s.kind == STEP_X    ? "x_step_mfma"
+                   : otf                 ? "switch_otf_mfma"
+                                         : "switch_step_mfma";
         } else if (p.dim == 1) {
             if (p.max_rank <= 16) launch_step_basic<2, 16>(s, a, st);
             else return "1D rank above 16";

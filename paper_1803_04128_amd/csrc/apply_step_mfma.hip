@@ -290,9 +290,145 @@ __global__ void __launch_bounds__(kMaxMT * 64) switch_step_mfma(StepArgs a) {
     }
 }
 
+// Switch step with its block generated in registers instead of read from
+// HBM (the factor construction's S, computed during the apply): one block
+// per pair (A, B) of the switch level.  The phase terms that depend on one
+// side only, Phi(c_A, xi_s) and Phi(x_t, c_B), and the x quantities of the
+// phase formula are evaluated once per pair in FP64 into LDS; each lane then
+// forms its A-operand entries
+//   S[t][s] = exp(2 pi i [Phi(x_t, xi_s) - Phi(c_A, xi_s) - Phi(x_t, c_B)])
+// with the phase difference in FP64, reduced modulo 1, then an FP32
+// sincospi, and the block is applied to every 16-column tile of the pair.
+struct OtfArgs {
+    StepArgs s;
+    PhaseSpec P;
+    Axis ax_in, ax_out;
+    int writes_lambda;
+};
+
+constexpr int kOtfRank = kMaxMT * 16;
+
+__device__ __forceinline__ float2 expi_frac32(double v) {
+    const float t = (float)(v - rint(v));
+    float sn, cs;
+    sincospif(2.0f * t, &sn, &cs);
+    return make_float2(cs, sn);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kMaxMT * 64) switch_otf_mfma(OtfArgs o) {
+    const StepArgs& a = o.s;
+    extern __shared__ float2 lds_step[];
+    float2* xs = lds_step;                              // [r_in][16]
+    double* phs = (double*)(xs + (size_t)a.r_in * kCols);  // [r_in]
+    double* pht = phs + kOtfRank;                       // [r_out]
+    XPre* xq = (XPre*)(pht + kOtfRank);                 // [r_out] or [r_in]
+    int2* xig = (int2*)(xq + kOtfRank);                 // [r_in] grid of xi_s
+    const long long p = blockIdx.x;
+    const int shiftB = a.dim * (a.L - a.level);
+    const long long am = p >> shiftB, bm = p & ((1LL << shiftB) - 1);
+    int Ac[2], Bc[2], cA[2], cB[2];
+    box_coords(am, a.dim, Ac);
+    box_coords(bm, a.dim, Bc);
+    center_grid(Ac, a.n >> a.level, a.dim, cA);
+    center_grid(Bc, a.n >> (a.L - a.level), a.dim, cB);
+    // the formula's x argument is the output point x_t, or for K^T the
+    // input point xi_s
+    const bool tr = o.P.transpose != 0;
+    for (int e = threadIdx.x; e < a.r_in; e += blockDim.x) {
+        int xi[2];
+        point_grid(Bc, o.ax_in, e, a.dim, xi);
+        phs[e] = a.reads_f ? 0.0 : phase_value(o.P, cA, xi);
+        if (tr) xq[e] = phase_xpre(o.P, xi);
+        xig[e] = make_int2(xi[0], a.dim > 1 ? xi[1] : 0);
+    }
+    for (int e = threadIdx.x; e < a.r_out; e += blockDim.x) {
+        int x[2];
+        point_grid(Ac, o.ax_out, e, a.dim, x);
+        pht[e] = o.writes_lambda ? 0.0 : phase_value(o.P, x, cB);
+        if (!tr) xq[e] = phase_xpre(o.P, x);
+    }
+    __syncthreads();
+    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, n = lane & 15;
+    const int KS = (a.r_in + 3) >> 2;
+    const int row = 16 * m + n;
+    const double sg = o.P.conjugate ? -1.0 : 1.0;
+    int x[2] = {0, 0};
+    XPre qrow{0.0, 0.0};
+    double prow = 0.0;
+    if (row < a.r_out) {
+        point_grid(Ac, o.ax_out, row, a.dim, x);
+        if (!tr) qrow = xq[row];
+        prow = pht[row];
+    }
+    float2 sv[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        const int s = 4 * ks + kq;
+        sv[ks] = make_float2(0.f, 0.f);
+        if (ks < KS && row < a.r_out && s < a.r_in) {
+            const int2 g = xig[s];
+            const int xi[2] = {g.x, g.y};
+            double v = tr ? phase_formula_k<KIND>(o.P, xq[s], xi, x)
+                          : phase_formula_k<KIND>(o.P, qrow, x, xi);
+            v = sg * v - phs[s];
+            v -= prow;
+            sv[ks] = expi_frac32(v);
+        }
+    }
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    for (int ct = 0; ct < nct; ++ct) {
+        const int col0 = ct * kCols;
+        if (ct > 0) __syncthreads();                    // tile ct-1 read
+        for (int e = threadIdx.x; e < a.r_in * kCols; e += blockDim.x) {
+            const int nn = e % kCols, s = e / kCols;
+            const int col = col0 + nn;
+            float2 v = make_float2(0.f, 0.f);
+            if (col < a.Vc)
+                v = a.reads_f ? head_value(a, bm, s, col)
+                              : a.in[(p * a.r_in + s) * a.Vc + col];
+            xs[e] = v;
+        }
+        __syncthreads();
+        floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            if (ks < KS) {                              // uniform
+                const int s = 4 * ks + kq;
+                const float2 xv = s < a.r_in ? xs[s * kCols + n]
+                                             : make_float2(0.f, 0.f);
+                p1 = mma(sv[ks].x, xv.x, p1);
+                p2 = mma(sv[ks].y, xv.y, p2);
+                p3 = mma(sv[ks].x, xv.y, p3);
+                p4 = mma(sv[ks].y, xv.x, p4);
+            }
+        }
+        const int col = col0 + n;
+        if (col < a.Vc) {
+            float2* out = a.out + p * a.r_out * a.Vc + col;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = 16 * m + 4 * kq + j;
+                if (t < a.r_out)
+                    out[(size_t)t * a.Vc] =
+                        make_float2(p1[j] - p2[j], p3[j] + p4[j]);
+            }
+        }
+    }
+}
+
+static size_t otf_lds(const Step& s) {
+    return (size_t)s.r_in * kCols * sizeof(float2) +
+           2 * kOtfRank * sizeof(double) + kOtfRank * sizeof(XPre) +
+           kOtfRank * sizeof(int2);
+}
+
 // LDS bytes of one block of the step's kernel.
 size_t step_mfma_lds(const Plan& p, const Step& s) {
-    if (s.kind == STEP_SWITCH) return (size_t)s.r_in * kCols * sizeof(float2);
+    if (s.kind == STEP_SWITCH)
+        return p.switch_otf ? otf_lds(s)
+                            : (size_t)s.r_in * kCols * sizeof(float2);
     const int rt = s.kind == STEP_XI ? s.r_in : s.r_out;
     return ((size_t)p.R * s.r_in * kCols + (size_t)p.R * p.R * rt) *
            sizeof(float2);
@@ -303,7 +439,12 @@ void init_step_mfma_attrs() {
     if (done) return;
     const void* fns[] = {(const void*)xi_step_mfma<2, 1>, (const void*)xi_step_mfma<4, 2>,
                          (const void*)x_step_mfma<2, 1>, (const void*)x_step_mfma<4, 2>,
-                         (const void*)switch_step_mfma};
+                         (const void*)switch_step_mfma,
+                         (const void*)switch_otf_mfma<BF_PHASE_DFT>,
+                         (const void*)switch_otf_mfma<BF_PHASE_FIO1D>,
+                         (const void*)switch_otf_mfma<BF_PHASE_RADON2D>,
+                         (const void*)switch_otf_mfma<BF_PHASE_SEPARABLE>,
+                         (const void*)switch_otf_mfma<BF_PHASE_FIO1D_WARP>};
     for (const void* fn : fns)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
@@ -318,7 +459,40 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
     const size_t lds = step_mfma_lds(p, s);
     if (lds > 160 * 1024) return "step does not fit in LDS";
     init_step_mfma_attrs();
-    if (s.kind == STEP_SWITCH) {
+    if (s.kind == STEP_SWITCH && p.switch_otf) {
+        if (s.units > 0x7fffffffLL) return "switch grid too large";
+        if (s.r_in > kOtfRank) return "switch rank above 64";
+        const int MT = (s.r_out + 15) / 16;
+        OtfArgs o{};
+        o.s = a;
+        o.P = p.phase;
+        o.ax_in = s.ax_in;
+        o.ax_out = s.ax_out;
+        o.writes_lambda = s.writes_lambda ? 1 : 0;
+        const dim3 grid((unsigned)s.units), block(64 * MT);
+        switch (p.phase.kind) {
+            case BF_PHASE_DFT:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_DFT>, grid, block,
+                                   lds, st, o);
+                break;
+            case BF_PHASE_FIO1D:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_FIO1D>, grid,
+                                   block, lds, st, o);
+                break;
+            case BF_PHASE_RADON2D:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_RADON2D>, grid,
+                                   block, lds, st, o);
+                break;
+            case BF_PHASE_SEPARABLE:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_SEPARABLE>, grid,
+                                   block, lds, st, o);
+                break;
+            default:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_FIO1D_WARP>, grid,
+                                   block, lds, st, o);
+                break;
+        }
+    } else if (s.kind == STEP_SWITCH) {
         const long long nb = s.units * nct;
         if (nb > 0x7fffffffLL) return "switch grid too large";
         const int MT = (s.r_out + 15) / 16;

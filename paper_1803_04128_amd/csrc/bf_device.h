@@ -74,51 +74,101 @@ __device__ __forceinline__ long long user_index(const int* g, int dim,
     return dim == 1 ? (long long)g[0] : (long long)g[0] * n + g[1];
 }
 
-// Phase Phi(x_ix, xi_jx) in FP64.  The bilinear part x . xi =
-// sum_d ix_d (jx_d - n/2) / n is reduced modulo 1 exactly in integers; only
-// the fractional part of Phi is ever used.
+// Quantities of the phase formula that depend on its x argument alone
+// (the coefficient functions c(x), c1(x), c2(x), the x part of a separable
+// phase), so that a block of entries sharing x points evaluates them once.
+struct XPre {
+    double c1, c2;
+};
+
+__device__ __forceinline__ XPre phase_xpre(const PhaseSpec& P,
+                                           const int* ix) {
+    const double invn = P.invn;
+    XPre q{0.0, 0.0};
+    switch (P.kind) {
+        case BF_PHASE_FIO1D:
+        case BF_PHASE_FIO1D_WARP:
+            q.c1 = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
+            break;
+        case BF_PHASE_RADON2D: {
+            double u = 2.0 * ix[0] * invn, v = 2.0 * ix[1] * invn;
+            q.c1 = (P.p[0] + P.p[1] * sinpi(u) * sinpi(v)) / P.p[2];
+            q.c2 = (P.p[3] + P.p[4] * cospi(u) * cospi(v)) / P.p[5];
+            break;
+        }
+        case BF_PHASE_SEPARABLE: {
+            double x2 = P.dim > 1 ? ix[1] * invn : 0.0;
+            q.c1 = P.p[0] * sinpi(2.0 * ix[0] * invn) * (1.0 + x2);
+            break;
+        }
+        default:
+            break;
+    }
+    return q;
+}
+
+// Phase Phi(x_ix, xi_jx) in FP64 from the x quantities q = phase_xpre(ix),
+// for the phase kind KIND.  The bilinear part x . xi = sum_d ix_d (jx_d -
+// n/2) / n is reduced modulo 1 exactly in integers: n is a power of two, so
+// the products may wrap modulo 2^32 and the sum is reduced with a mask.
+// Only the fractional part of Phi is ever used.
+template <int KIND>
+__device__ __forceinline__ double phase_formula_k(const PhaseSpec& P,
+                                                  const XPre& q,
+                                                  const int* ix,
+                                                  const int* jx) {
+    const int n = P.n;
+    const int dim = KIND == BF_PHASE_RADON2D ? 2
+                    : (KIND == BF_PHASE_FIO1D || KIND == BF_PHASE_FIO1D_WARP)
+                        ? 1
+                        : P.dim;
+    double bil = 0.0;
+    if (KIND != BF_PHASE_SEPARABLE) {
+        unsigned acc = 0;
+        for (int d = 0; d < dim; ++d)
+            acc += (unsigned)ix[d] * (unsigned)(jx[d] - n / 2);
+        bil = (double)(acc & (unsigned)(n - 1)) * P.invn;
+    }
+    if (KIND == BF_PHASE_DFT) return bil;
+    if (KIND == BF_PHASE_FIO1D)
+        return bil + q.c1 * fabs((double)(jx[0] - n / 2));
+    if (KIND == BF_PHASE_FIO1D_WARP)
+        return bil + q.c1 * (double)(jx[0] - n / 2);
+    if (KIND == BF_PHASE_RADON2D) {
+        double x1 = (double)(jx[0] - n / 2), x2 = (double)(jx[1] - n / 2);
+        return bil + sqrt(q.c1 * q.c1 * x1 * x1 + q.c2 * q.c2 * x2 * x2);
+    }
+    // BF_PHASE_SEPARABLE
+    double nrm2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        double x = (double)(jx[d] - n / 2);
+        nrm2 += x * x;
+    }
+    return q.c1 + P.p[1] * sqrt(nrm2) + P.p[2] * nrm2 * P.invn;
+}
+
+__device__ __forceinline__ double phase_formula_pre(const PhaseSpec& P,
+                                                    const XPre& q,
+                                                    const int* ix,
+                                                    const int* jx) {
+    switch (P.kind) {
+        case BF_PHASE_DFT:
+            return phase_formula_k<BF_PHASE_DFT>(P, q, ix, jx);
+        case BF_PHASE_FIO1D:
+            return phase_formula_k<BF_PHASE_FIO1D>(P, q, ix, jx);
+        case BF_PHASE_FIO1D_WARP:
+            return phase_formula_k<BF_PHASE_FIO1D_WARP>(P, q, ix, jx);
+        case BF_PHASE_RADON2D:
+            return phase_formula_k<BF_PHASE_RADON2D>(P, q, ix, jx);
+        default:
+            return phase_formula_k<BF_PHASE_SEPARABLE>(P, q, ix, jx);
+    }
+}
+
 __device__ __forceinline__ double phase_formula(const PhaseSpec& P,
                                                 const int* ix,
                                                 const int* jx) {
-    const int n = P.n;
-    const double invn = 1.0 / (double)n;
-    double bil = 0.0;
-    if (P.kind != BF_PHASE_SEPARABLE) {
-        long long acc = 0;
-        for (int d = 0; d < P.dim; ++d)
-            acc = (acc + (long long)ix[d] * (long long)(jx[d] - n / 2)) % n;
-        if (acc < 0) acc += n;
-        bil = (double)acc * invn;
-    }
-    switch (P.kind) {
-        case BF_PHASE_DFT:
-            return bil;
-        case BF_PHASE_FIO1D: {
-            double c = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
-            return bil + c * fabs((double)(jx[0] - n / 2));
-        }
-        case BF_PHASE_FIO1D_WARP: {
-            double c = (P.p[0] + P.p[1] * sinpi(2.0 * ix[0] * invn)) / P.p[2];
-            return bil + c * (double)(jx[0] - n / 2);
-        }
-        case BF_PHASE_RADON2D: {
-            double u = 2.0 * ix[0] * invn, v = 2.0 * ix[1] * invn;
-            double c1 = (P.p[0] + P.p[1] * sinpi(u) * sinpi(v)) / P.p[2];
-            double c2 = (P.p[3] + P.p[4] * cospi(u) * cospi(v)) / P.p[5];
-            double x1 = (double)(jx[0] - n / 2), x2 = (double)(jx[1] - n / 2);
-            return bil + sqrt(c1 * c1 * x1 * x1 + c2 * c2 * x2 * x2);
-        }
-        default: {  // BF_PHASE_SEPARABLE
-            double x2 = P.dim > 1 ? ix[1] * invn : 0.0;
-            double px = P.p[0] * sinpi(2.0 * ix[0] * invn) * (1.0 + x2);
-            double nrm2 = 0.0;
-            for (int d = 0; d < P.dim; ++d) {
-                double x = (double)(jx[d] - n / 2);
-                nrm2 += x * x;
-            }
-            return px + P.p[1] * sqrt(nrm2) + P.p[2] * nrm2 * invn;
-        }
-    }
+    return phase_formula_pre(P, phase_xpre(P, ix), ix, jx);
 }
 
 // Phase of the factorized kernel at output-tree index ix and input-tree

@@ -90,6 +90,7 @@ struct PhaseSpec {
     int n;
     int transpose;   // factorize K^T: phase roles of x and xi exchanged
     int conjugate;   // factorize the conjugate kernel: phase negated
+    double invn;     // 1 / n (exact: n is a power of two)
     double p[6];
 };
 
@@ -135,8 +136,13 @@ struct Plan {
     // device memory
     void* arena = nullptr;
     size_t arena_bytes = 0;
+    void* S_arena = nullptr;  // stored switch blocks (build_switch_blocks)
+    size_t S_bytes = 0;
     bool has_amp = false;     // false: alpha = 1 (r = 1)
     int op = 0;               // BF_OP_*: which of K, K^T, conj K, K^H
+    // per-step MFMA form: generate the switch blocks during the apply
+    // instead of reading the stored S
+    bool switch_otf = false;
     float2* a_dev = nullptr;  // [r][N] complex64, nullptr when alpha = 1
     float2* b_dev = nullptr;
     void* ws = nullptr;
@@ -171,6 +177,11 @@ std::string build_schedule(Plan& p);   // "" on success, else a message
 // factors.hip
 std::string build_factors(Plan& p);
 std::string upload_amplitude(Plan& p, const double* a, const double* b);
+std::string build_switch_blocks(Plan& p);
+// whether the plan's current execution form reads the stored switch blocks
+inline bool reads_stored_switch(const Plan& p) {
+    return !(p.switch_otf && !p.fused && p.mfma);
+}
 // apply.hip
 std::string launch_apply(Plan& p, int nvec, const void* f, void* g, void* ws,
                          size_t ws_bytes, hipStream_t stream);

@@ -46,6 +46,10 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
         return "workspace too small for one vector";
     if (!p.fused && p.precision != BF_FP32)
         return "split precision needs the fused passes";
+    if (reads_stored_switch(p) && !p.S_arena) {
+        for (const auto& s : p.steps)
+            if (s.S_elems) return "switch blocks are not stored";
+    }
     const float2* f = (const float2*)fv;
     float2* g = (float2*)gv;
     for (int v0 = 0; v0 < nvec; v0 += chunk) {

@@ -164,7 +164,7 @@ std::string build_factors(Plan& p) {
     // arena layout
     size_t bytes = 0;
     const bool split = p.precision != BF_FP32;
-    std::vector<size_t> off_tw, off_m, off_S, off_hi, off_lo, off_am, off_ax, off_af;
+    std::vector<size_t> off_tw, off_m, off_hi, off_lo, off_am, off_ax, off_af;
     for (auto& s : p.steps) {
         off_am.push_back(bytes);
         bytes = align_up(bytes + s.amat_elems * sizeof(float));
@@ -172,8 +172,6 @@ std::string build_factors(Plan& p) {
         bytes = align_up(bytes + s.amat_xi_elems * sizeof(float));
         off_tw.push_back(bytes);
         bytes = align_up(bytes + s.tw_elems * sizeof(float2));
-        off_S.push_back(bytes);
-        bytes = align_up(bytes + s.S_elems * sizeof(float2));
         off_m.push_back(bytes);
         bytes = align_up(bytes + s.mat_elems * sizeof(float));
         // split precisions: the arranged FP32 table, then its hi and lo parts
@@ -201,7 +199,7 @@ std::string build_factors(Plan& p) {
     for (size_t k = 0; k < p.steps.size(); ++k) {
         Step& s = p.steps[k];
         s.tw = s.tw_elems ? (float2*)(base + off_tw[k]) : nullptr;
-        s.S = s.S_elems ? (float2*)(base + off_S[k]) : nullptr;
+        s.S = nullptr;   // build_switch_blocks
         s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
         s.amat = s.amat_elems ? (float*)(base + off_am[k]) : nullptr;
         s.amat_xi = s.amat_xi_elems ? (float*)(base + off_ax[k]) : nullptr;
@@ -214,7 +212,9 @@ std::string build_factors(Plan& p) {
         t.level = s.level;
         t.reads_f = s.reads_f;
         t.writes_lambda = s.writes_lambda;
-        if (s.kind == STEP_XI) {
+        if (s.kind == STEP_SWITCH) {
+            // stored switch blocks are built by build_switch_blocks
+        } else if (s.kind == STEP_XI) {
             t.total = (long long)s.tw_elems;
             t.out = s.tw;
             hipLaunchKernelGGL(xi_twiddles, dim3(grid_for(t.total)),
@@ -223,11 +223,6 @@ std::string build_factors(Plan& p) {
             t.total = (long long)s.tw_elems;
             t.out = s.tw;
             hipLaunchKernelGGL(x_twiddles, dim3(grid_for(t.total)),
-                               dim3(kFactorBlock), 0, 0, t);
-        } else {
-            t.total = (long long)s.S_elems;
-            t.out = s.S;
-            hipLaunchKernelGGL(switch_blocks, dim3(grid_for(t.total)),
                                dim3(kFactorBlock), 0, 0, t);
         }
         HIPCHK(hipGetLastError());
@@ -314,6 +309,49 @@ std::string build_factors(Plan& p) {
 }
 
 // Upload and narrow the amplitude factors (host complex128 [r][N]).
+// The switch blocks S of every switch step in an allocation of their own:
+// built when the plan's execution form reads them (all forms but the
+// per-step MFMA form with on-the-fly blocks), kept until bf_destroy.
+std::string build_switch_blocks(Plan& p) {
+    if (p.S_arena) return "";
+    size_t bytes = 0;
+    std::vector<size_t> off;
+    for (auto& s : p.steps) {
+        off.push_back(bytes);
+        bytes = align_up(bytes + s.S_elems * sizeof(float2));
+    }
+    if (bytes == 0) return "";
+    void* mem = nullptr;
+    HIPCHK(hipMalloc(&mem, bytes));
+    TwArgs t{};
+    t.P = p.phase;
+    t.L = p.L;
+    for (size_t k = 0; k < p.steps.size(); ++k) {
+        Step& s = p.steps[k];
+        if (s.kind != STEP_SWITCH || !s.S_elems) continue;
+        s.S = (float2*)((char*)mem + off[k]);
+        t.ax_in = s.ax_in;
+        t.ax_out = s.ax_out;
+        t.level = s.level;
+        t.reads_f = s.reads_f;
+        t.writes_lambda = s.writes_lambda;
+        t.total = (long long)s.S_elems;
+        t.out = s.S;
+        hipLaunchKernelGGL(switch_blocks, dim3(grid_for(t.total)),
+                           dim3(kFactorBlock), 0, 0, t);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        for (auto& s : p.steps) s.S = nullptr;
+        (void)hipFree(mem);
+        return std::string("switch blocks: ") + hipGetErrorString(e);
+    }
+    p.S_arena = mem;
+    p.S_bytes = bytes;
+    return "";
+}
+
 std::string upload_amplitude(Plan& p, const double* a, const double* b) {
     const long long m = (long long)p.r_amp * p.N;
     void* tmp = nullptr;
