@@ -158,6 +158,10 @@ def main():
     g = torch.empty_like(f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if args.switch_otf:
+        # read at plan construction: the plan then stores no switch blocks
+        os.environ["BF_FUSED"] = "0"
+        os.environ["BF_SWITCH_OTF"] = "1"
     plan = bfm.Plan(w.dim, w.n, w.phase_kind, w.phase_params, q=w.q,
                     amplitude=ab, precision=precision, max_nvec=nvec)
     torch.cuda.synchronize()
