@@ -10,6 +10,10 @@ x . xi = sum_d i_d (j_d - n/2) / n is reduced modulo 1 exactly, with the
 integer product taken modulo n before the division; the remaining smooth part
 is added in FP64 and the sum is reduced to [-1/2, 1/2] before the exponential.
 Only the fractional part of the phase matters for exp(2 pi i Phi).
+
+Phase kind "lowrank" (Algorithm 2's input form) takes params = (U, V), real
+[N][rank] factors in user index order, and Phi(x_i, xi_j) = U[i] . V[j] in
+FP64 with no separate bilinear term.
 """
 
 import numpy as np
@@ -36,8 +40,19 @@ def _bilinear_frac(ix, jx, n):
     return prod.astype(np.float64) / n
 
 
+def _user_index(g, n):
+    """Per-dimension grid index (..., dim) -> user index (row-major in 2D)."""
+    return g[..., 0] if g.shape[-1] == 1 else g[..., 0] * n + g[..., 1]
+
+
 def _smooth(kind, params, ix, jx, n):
     """Non-bilinear part of the phase (FP64).  ix, jx: (..., dim) integers."""
+    if kind == "lowrank":
+        # Algorithm 2's input form: Phi(m, n) = U(m, :) V(n, :)^T with real
+        # factors, evaluated entry by entry
+        U, V = params
+        i, j = _user_index(ix, n), _user_index(jx, n)
+        return np.sum(U[i] * V[j], axis=-1)
     x = ix.astype(np.float64) / n
     xi = (jx - n // 2).astype(np.float64)
     if kind == "dft":

@@ -12,6 +12,7 @@ from .inputs import (  # noqa: F401
     sample_rows,
     amplitude_factors,
     orthogonal_mix,
+    lowrank_phase,
 )
 from .configs import (  # noqa: F401
     CONFIGS,

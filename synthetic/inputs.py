@@ -68,3 +68,38 @@ def amplitude_factors(kind, dim, n, r, seed):
     B = B @ Q
     return (np.ascontiguousarray(A.T).astype(np.complex128),
             np.ascontiguousarray(B.T).astype(np.complex128))
+
+
+def lowrank_phase(dim, n, rank, seed):
+    """Real factors ``U[N][rank]``, ``V[N][rank]`` (float64, user index
+    order) of a phase given in low-rank form, Phi(x_i, xi_j) = sum_k U[i, k]
+    V[j, k]: x . xi plus ``rank - dim`` terms u_k(x) w_k(xi), each u_k a
+    small smooth periodic function of x (0.02 to 0.08 times 1 + sin/2 of a
+    random low frequency and shift) and w_k the Euclidean norm |xi| or one
+    coordinate of xi, so that the phase is smooth in x and homogeneous of
+    degree 1 in xi like the workloads' phases.  The columns are mixed by a
+    seeded orthogonal matrix (U <- U Q, V <- V Q), which leaves U V^T
+    unchanged.  Grid: x = i/n, xi = j - n/2 per dimension, 2D user index
+    i1 * n + i2."""
+    if rank < dim:
+        raise ValueError("rank must be at least dim")
+    N = n ** dim
+    rng = np.random.default_rng(seed)
+    idx = np.arange(N, dtype=np.int64)
+    g = idx[:, None] if dim == 1 else np.stack([idx // n, idx % n], axis=1)
+    x = g / n
+    xi = (g - n // 2).astype(np.float64)
+    nrm = np.sqrt(np.sum(xi * xi, axis=1))
+    cu = [x[:, d] for d in range(dim)]
+    cv = [xi[:, d] for d in range(dim)]
+    for k in range(rank - dim):
+        m = rng.integers(1, 3, size=dim)
+        th = rng.uniform(0.0, 2 * np.pi)
+        amp = rng.uniform(0.02, 0.08)
+        cu.append(amp * (1.0 + 0.5 * np.sin(2 * np.pi * (x @ m) + th)))
+        cv.append(nrm if k % 2 == 0 else xi[:, k % dim])
+    Q = orthogonal_mix(rank, seed + 1)
+    U = np.stack(cu, axis=1) @ Q
+    V = np.stack(cv, axis=1) @ Q
+    return np.ascontiguousarray(U), np.ascontiguousarray(V)
+
