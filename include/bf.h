@@ -51,6 +51,9 @@ extern "C" {
  *                     FIO of the composition example, eq. (eqn:FIOK2); it
  *                     evaluates the Fourier series of its input at
  *                     x + c(x).
+ * BF_PHASE_LOWRANK:   Phi(x_i, xi_j) = sum_{k<rank} U[i][k] V[j][k], the
+ *                     phase given by real low-rank factors (the input form
+ *                     of Algorithm 2), any dim; U and V come in bf_phase.
  * BF_PHASE_RADON2D:   Phi = x . xi + sqrt(c1(x)^2 xi1^2 + c2(x)^2 xi2^2),
  *                     c1 = (p0 + p1 sin 2 pi x1 sin 2 pi x2) / p2,
  *                     c2 = (p3 + p4 cos 2 pi x1 cos 2 pi x2) / p5
@@ -63,6 +66,7 @@ extern "C" {
 #define BF_PHASE_RADON2D    2
 #define BF_PHASE_SEPARABLE  3
 #define BF_PHASE_FIO1D_WARP 4
+#define BF_PHASE_LOWRANK    5
 
 /* ---- arithmetic of the apply ------------------------------------------- */
 /* BF_FP32:   FP32 complex state and factors, FP32 vector arithmetic.
@@ -87,6 +91,16 @@ typedef struct bf_phase {
     int kind;              /* BF_PHASE_* */
     int nparams;           /* number of entries in params (0, 3 or 6) */
     const double* params;  /* host, read during bf_plan only */
+    /* BF_PHASE_LOWRANK only (nparams = 0): 1 <= rank <= 64 and the factors,
+     * host float64 [N][rank] row-major in user index order (row i of U
+     * belongs to x_i, row j of V to xi_j); copied to the device by bf_plan
+     * (2 N rank doubles, freed by bf_destroy) and read during applies only
+     * by the on-the-fly switch form.  The FP64 sum carries an error of
+     * about |Phi| 2^-52 cycles, so FP32-level results need |Phi| below
+     * about 2^25 (the built-in kinds reduce their bilinear part exactly). */
+    int rank;
+    const double* U;
+    const double* V;
 } bf_phase;
 
 /* Low-rank amplitude alpha(x, xi) = sum_{k<r} a_k(x) b_k(xi) (eq. (eqn:tg)).

@@ -49,7 +49,9 @@ class Plan:
     """A device-resident butterfly plan (bf_plan ... bf_destroy).
 
     dim, n: grid (x_i = i/n, xi_j = j - n/2 per dimension).
-    phase: "dft" | "fio1d" | "radon2d" | "separable"; params: its numbers.
+    phase: "dft" | "fio1d" | "fio1d_warp" | "radon2d" | "separable" with
+    params its numbers, or "lowrank" with params = (U, V), real [N][rank]
+    factors of Phi = U V^T.
     q: interpolation points per box and dimension.
     amplitude: None (alpha = 1) or (a, b), complex arrays [r][N].
     precision: "fp32" | "bf16x3" | "fp16x3".
@@ -65,8 +67,19 @@ class Plan:
         self._lib = _lib.load()
         self._h = C.c_void_p()
         grid = _lib.BfGrid(int(dim), int(n))
-        self._params = (C.c_double * max(1, len(params)))(*params)
-        ph = _lib.BfPhase(PHASES[phase], len(params), self._params)
+        if phase == "lowrank":
+            # params = (U, V): real factors [N][rank], Phi = U V^T
+            U, V = (np.ascontiguousarray(m, dtype=np.float64) for m in params)
+            if U.ndim != 2 or U.shape != V.shape or U.shape[0] != n ** dim:
+                raise ValueError("low-rank phase factors must both be "
+                                 "[N][rank]")
+            self._params = (C.c_double * 1)()
+            ph = _lib.BfPhase(PHASES[phase], 0, self._params, U.shape[1],
+                              U.ctypes.data_as(C.POINTER(C.c_double)),
+                              V.ctypes.data_as(C.POINTER(C.c_double)))
+        else:
+            self._params = (C.c_double * max(1, len(params)))(*params)
+            ph = _lib.BfPhase(PHASES[phase], len(params), self._params)
         amp = None
         self.r = 1
         if amplitude is not None:

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbf.so")
 BF_OK, BF_EINVAL, BF_ENOMEM, BF_EHIP, BF_EUNSUPPORTED, BF_EBUSY = (
     0, -1, -2, -3, -4, -5)
 PHASES = {"dft": 0, "fio1d": 1, "radon2d": 2, "separable": 3,
-          "fio1d_warp": 4}
+          "fio1d_warp": 4, "lowrank": 5}
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
 
@@ -20,7 +20,8 @@ class BfGrid(C.Structure):
 
 class BfPhase(C.Structure):
     _fields_ = [("kind", C.c_int), ("nparams", C.c_int),
-                ("params", C.POINTER(C.c_double))]
+                ("params", C.POINTER(C.c_double)), ("rank", C.c_int),
+                ("U", C.POINTER(C.c_double)), ("V", C.POINTER(C.c_double))]
 
 
 class BfAmplitude(C.Structure):

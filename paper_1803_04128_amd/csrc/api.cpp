@@ -167,11 +167,16 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
         case BF_PHASE_RADON2D: need = dim == 2 ? 6 : -1; break;
         case BF_PHASE_SEPARABLE: need = 3; break;
         case BF_PHASE_FIO1D_WARP: need = dim == 1 ? 3 : -1; break;
+        case BF_PHASE_LOWRANK: need = 0; break;
         default: return fail(BF_EINVAL, "bf_plan: unknown phase kind");
     }
     if (need < 0) return fail(BF_EINVAL, "bf_plan: phase kind needs another dim");
     if (phase->nparams != need || (need > 0 && !phase->params))
         return fail(BF_EINVAL, "bf_plan: wrong number of phase parameters");
+    if (phase->kind == BF_PHASE_LOWRANK &&
+        (phase->rank < 1 || phase->rank > 64 || !phase->U || !phase->V))
+        return fail(BF_EINVAL,
+                    "bf_plan: low-rank phase needs 1 <= rank <= 64, U and V");
     int r = 1;
     const double *a = nullptr, *b = nullptr;
     if (amp) {
@@ -233,7 +238,10 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
                                                          ws_cap / per_vec));
     p.chunk_nvec = chunk;
     size_t factor_est = (size_t)p.factor_stream_bytes +
-                        (p.has_amp ? 2 * (size_t)r * p.N * 8 : 0);
+                        (p.has_amp ? 2 * (size_t)r * p.N * 8 : 0) +
+                        (phase->kind == BF_PHASE_LOWRANK
+                             ? 2 * (size_t)phase->rank * p.N * 8
+                             : 0);
     if (factor_est + per_vec * chunk > cap) {
         delete h;
         return fail(BF_ENOMEM, "bf_plan: plan exceeds BF_MEM_CAP_BYTES");
@@ -248,7 +256,25 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
         p.fused = false;
     }
     bfi::init_kernel_attrs();
-    err = bfi::build_factors(p);
+    if (phase->kind == BF_PHASE_LOWRANK) {
+        const size_t fb = (size_t)p.N * phase->rank * sizeof(double);
+        if (hipMalloc(&p.phase_arena, 2 * fb) != hipSuccess) {
+            p.phase_arena = nullptr;
+            err = "hipMalloc low-rank phase";
+        } else {
+            double* U = (double*)p.phase_arena;
+            double* V = U + (size_t)p.N * phase->rank;
+            if (hipMemcpy(U, phase->U, fb, hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                hipMemcpy(V, phase->V, fb, hipMemcpyHostToDevice) !=
+                    hipSuccess)
+                err = "hipMemcpy low-rank phase";
+            p.phase.U = U;
+            p.phase.V = V;
+            p.phase.rank = phase->rank;
+        }
+    }
+    if (err.empty()) err = bfi::build_factors(p);
     if (err.empty() && bfi::reads_stored_switch(p))
         err = bfi::build_switch_blocks(p);
     if (err.empty() && p.has_amp) err = bfi::upload_amplitude(p, a, b);
@@ -262,6 +288,7 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     if (!err.empty()) {
         if (p.arena) (void)hipFree(p.arena);
         if (p.S_arena) (void)hipFree(p.S_arena);
+        if (p.phase_arena) (void)hipFree(p.phase_arena);
         if (p.ws) (void)hipFree(p.ws);
         (void)hipGetLastError();
         delete h;
@@ -381,6 +408,7 @@ int bf_destroy(bf_plan_t plan) {
     if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
     if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
     if (p.S_arena && hipFree(p.S_arena) != hipSuccess) rc = BF_EHIP;
+    if (p.phase_arena && hipFree(p.phase_arena) != hipSuccess) rc = BF_EHIP;
     if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
     for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
     plan->magic = 0;
@@ -464,7 +492,9 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
                              : (int)p.steps.size() + 1;
     info->max_rank = p.max_rank;
     info->chunk_nvec = p.chunk_nvec;
-    info->factor_bytes = p.arena_bytes + p.S_bytes;
+    info->factor_bytes = p.arena_bytes + p.S_bytes +
+                         (p.phase_arena ? 2 * (size_t)p.phase.rank * p.N * 8
+                                        : 0);
     info->workspace_bytes = p.ws_bytes;
     info->flops_per_column = p.flops_per_column;
     info->factor_stream_bytes = p.factor_stream_bytes;

@@ -444,7 +444,8 @@ void init_step_mfma_attrs() {
                          (const void*)switch_otf_mfma<BF_PHASE_FIO1D>,
                          (const void*)switch_otf_mfma<BF_PHASE_RADON2D>,
                          (const void*)switch_otf_mfma<BF_PHASE_SEPARABLE>,
-                         (const void*)switch_otf_mfma<BF_PHASE_FIO1D_WARP>};
+                         (const void*)switch_otf_mfma<BF_PHASE_FIO1D_WARP>,
+                         (const void*)switch_otf_mfma<BF_PHASE_LOWRANK>};
     for (const void* fn : fns)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
@@ -487,10 +488,16 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
                 hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_SEPARABLE>, grid,
                                    block, lds, st, o);
                 break;
-            default:
+            case BF_PHASE_FIO1D_WARP:
                 hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_FIO1D_WARP>, grid,
                                    block, lds, st, o);
                 break;
+            case BF_PHASE_LOWRANK:
+                hipLaunchKernelGGL(switch_otf_mfma<BF_PHASE_LOWRANK>, grid,
+                                   block, lds, st, o);
+                break;
+            default:
+                return "unknown phase kind";
         }
     } else if (s.kind == STEP_SWITCH) {
         const long long nb = s.units * nct;

@@ -122,6 +122,14 @@ __device__ __forceinline__ double phase_formula_k(const PhaseSpec& P,
                     : (KIND == BF_PHASE_FIO1D || KIND == BF_PHASE_FIO1D_WARP)
                         ? 1
                         : P.dim;
+    if (KIND == BF_PHASE_LOWRANK) {
+        // Algorithm 2's input form: Phi = U(i, :) V(j, :)^T
+        const double* u = P.U + user_index(ix, P.dim, n) * P.rank;
+        const double* v = P.V + user_index(jx, P.dim, n) * P.rank;
+        double s = 0.0;
+        for (int k = 0; k < P.rank; ++k) s = fma(u[k], v[k], s);
+        return s;
+    }
     double bil = 0.0;
     if (KIND != BF_PHASE_SEPARABLE) {
         unsigned acc = 0;
@@ -160,6 +168,8 @@ __device__ __forceinline__ double phase_formula_pre(const PhaseSpec& P,
             return phase_formula_k<BF_PHASE_FIO1D_WARP>(P, q, ix, jx);
         case BF_PHASE_RADON2D:
             return phase_formula_k<BF_PHASE_RADON2D>(P, q, ix, jx);
+        case BF_PHASE_LOWRANK:
+            return phase_formula_k<BF_PHASE_LOWRANK>(P, q, ix, jx);
         default:
             return phase_formula_k<BF_PHASE_SEPARABLE>(P, q, ix, jx);
     }

@@ -92,6 +92,10 @@ struct PhaseSpec {
     int conjugate;   // factorize the conjugate kernel: phase negated
     double invn;     // 1 / n (exact: n is a power of two)
     double p[6];
+    // BF_PHASE_LOWRANK: device factors [N][rank] (Plan::phase_arena)
+    const double* U;
+    const double* V;
+    int rank;
 };
 
 // A fused kernel pass: consecutive steps [first, last] executed by one
@@ -137,6 +141,7 @@ struct Plan {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     void* S_arena = nullptr;  // stored switch blocks (build_switch_blocks)
+    void* phase_arena = nullptr;  // low-rank phase factors on the device
     size_t S_bytes = 0;
     bool has_amp = false;     // false: alpha = 1 (r = 1)
     int op = 0;               // BF_OP_*: which of K, K^T, conj K, K^H

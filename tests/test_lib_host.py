@@ -138,3 +138,22 @@ def test_apply_chain_rejects_empty_chain():
                               None) == _lib.BF_EINVAL
     assert lib.bf_apply_chain(arr, 0, 1, None, None, None,
                               None) == _lib.BF_EINVAL
+
+
+@pytest.mark.parametrize("rank,have_u,have_v", [(0, True, True),
+                                                (65, True, True),
+                                                (4, False, True),
+                                                (4, True, False)])
+def test_lowrank_phase_arguments_checked(rank, have_u, have_v):
+    lib = _lib.load()
+    n = 64
+    U = np.zeros((n, max(rank, 1)))
+    g = _lib.BfGrid(1, n)
+    dp = C.POINTER(C.c_double)
+    ph = _lib.BfPhase(5, 0, None, rank,
+                      U.ctypes.data_as(dp) if have_u else None,
+                      U.ctypes.data_as(dp) if have_v else None)
+    h = C.c_void_p()
+    rc = lib.bf_plan(C.byref(g), C.byref(ph), None, 8, 0, 1, C.byref(h))
+    assert rc == _lib.BF_EINVAL
+    assert not h.value
