@@ -232,6 +232,56 @@ __device__ __forceinline__ void load_amat(const PassLevel& lv, bool xi,
     }
 }
 
+// FP32 tile loop of one xi level with NK K steps (pairs of coefficients).
+template <int VT, int NK>
+__device__ __forceinline__ void xi_tiles_fp32(const PassArgs& a,
+                                              const float2* src, int RS,
+                                              float2* dst, const float2* twl,
+                                              int j, const float (&aM)[8],
+                                              int xoff, int woff) {
+    const PassLevel& lv = a.lv[j - 1];
+    const int r_in = lv.r_in, r_out = lv.r_out;
+    const int kj = a.k - j;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    constexpr int CPT = 16 / VT;             // (unit, i) combinations per tile
+    const int sub = n / VT, col = n & (VT - 1);
+    const int ntiles = (a.Gk + CPT - 1) / CPT;
+    const int DS = a.rmax * VT;
+    for (int tau = wave; tau < ntiles; tau += nwaves) {
+        int ui = tau * CPT + sub;
+        const bool ok = ui < a.Gk;
+        if (!ok) ui = 0;                        // padding column: any valid data
+        const int unit = ui >> 1, i = ui & 1;
+        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
+        const int rv = digit_rev(apl, j - 1, 1);
+        const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
+        const float2* wp = twl + (unit * 4 + i * 2) * r_in + woff;
+        float2 xs[NK], ws[NK];
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+            xs[kk] = xp[kk * 2 * VT];
+            ws[kk] = wp[2 * kk];
+        }
+        floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+            const float2 x = xs[kk], w = ws[kk];
+            accr = mfma4(aM[kk], w.x * x.x - w.y * x.y, accr);
+            acci = mfma4(aM[kk], w.x * x.y + w.y * x.x, acci);
+        }
+        if (ok) {
+            float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int t = 4 * g + jj;
+                if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
+            }
+        }
+    }
+}
+
 // One xi level: src (stride src_r coefficients per slot) -> dst.
 template <int VT, int PREC>
 __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
@@ -328,45 +378,96 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
     // child c = g % 2, coefficient s = 2 kk + g / 2.  Every lane then reads
     // x and w at a fixed base plus a compile-time step per kk, and A comes
     // pre-arranged in this order (lv.amat, zero past r_in and r_out).  Steps
-    // past r_in read finite data: the pass zeroes its LDS before use.
+    // past r_in read finite data: the pass zeroes its LDS before use.  The
+    // tile loop is instantiated per number of K steps so that a level runs
+    // straight-line code.
     (void)K;
+    (void)tA;
     const int nks2 = (r_in + 1) >> 1;
-    const float (&aM)[8] = aMin;            // loaded by the caller
     const int cg = g & 1, sg = g >> 1;
     const int xoff = cg * cstride + sg * VT + col;
     const int woff = cg * r_in + sg;
-    const int ntiles = (a.Gk + CPT - 1) / CPT;
-    const int DS = a.rmax * VT;
-    for (int tau = wave; tau < ntiles; tau += nwaves) {
-        int ui = tau * CPT + sub;
-        const bool ok = ui < a.Gk;
-        if (!ok) ui = 0;                        // padding column: any valid data
-        const int unit = ui >> 1, i = ui & 1;
+    switch (nks2) {
+#define BF_XI_CASE(NK)                                                     \
+        case NK:                                                           \
+            xi_tiles_fp32<VT, NK>(a, src, RS, dst, twl, j, aMin, xoff,     \
+                                  woff);                                   \
+            break;
+        BF_XI_CASE(1) BF_XI_CASE(2) BF_XI_CASE(3) BF_XI_CASE(4)
+        BF_XI_CASE(5) BF_XI_CASE(6) BF_XI_CASE(7) default: BF_XI_CASE(8)
+#undef BF_XI_CASE
+    }
+}
+
+// FP32 tile loop of one x level with NK K steps.
+template <int VT, int NK>
+__device__ __forceinline__ void x_tiles_fp32(const PassArgs& a,
+                                             const float2* src, float2* dst,
+                                             const float2* twl, int j,
+                                             bool to_tail, floatx4* tacc,
+                                             const float (&aM)[8]) {
+    const PassLevel& lv = a.lv[j - 1];
+    const int r_out = lv.r_out;
+    const int kj = a.k - j;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    constexpr int UPT = 16 / VT;             // units per tile
+    const int sub = n / VT, col = n & (VT - 1);
+    const int RS = a.rmax * VT;
+    const int xoff = g * VT + col;
+    const int nunits = a.Gk >> 1;
+    const int ntiles = (nunits + UPT - 1) / UPT;
+#pragma unroll
+    for (int m = 0; m < wave_tiles<VT>() / 2; ++m) {
+        const int tau = wave + m * nwaves;
+        if (tau >= ntiles) break;
+        int unit = tau * UPT + sub;
+        const bool ok = unit < nunits;
+        if (!ok) unit = 0;
         const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
         const int rv = digit_rev(apl, j - 1, 1);
-        const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
-        const float2* wp = twl + (unit * 4 + i * 2) * r_in + woff;
-        float2 xs[8], ws[8];
+        const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
+        const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
+        float2 x0[NK], x1[NK];
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            if (kk >= nks2) break;
-            xs[kk] = xp[kk * 2 * VT];
-            ws[kk] = wp[2 * kk];
+        for (int kk = 0; kk < NK; ++kk) {
+            x0[kk] = xp0[kk * 4 * VT];
+            x1[kk] = xp1[kk * 4 * VT];
         }
-        floatx4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            if (kk >= nks2) break;
-            const float2 x = xs[kk], w = ws[kk];
-            accr = mfma4(aM[kk], w.x * x.x - w.y * x.y, accr);
-            acci = mfma4(aM[kk], w.x * x.y + w.y * x.x, acci);
-        }
-        if (ok) {
-            float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
+        for (int i = 0; i < 2; ++i) {
+            floatx4 y0r = {0.f, 0.f, 0.f, 0.f}, y0i = y0r, y1r = y0r, y1i = y0r;
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+                const float am = aM[4 * i + kk];
+                y0r = mfma4(am, x0[kk].x, y0r);
+                y0i = mfma4(am, x0[kk].y, y0i);
+                y1r = mfma4(am, x1[kk].x, y1r);
+                y1i = mfma4(am, x1[kk].y, y1i);
+            }
+            // rows t >= r_out read finite (zeroed or stale) twiddles and are
+            // never stored
+            const float2* tp = twl + (unit * 4 + i * 2) * r_out + 4 * g;
+            floatx4 orr, oii;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                const int t = 4 * g + jj;
-                if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
+                const float2 T0 = tp[jj];
+                const float2 T1 = tp[r_out + jj];
+                orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
+                oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
+            }
+            if (to_tail) {
+                // fixed (tau, lane) -> (A box, point, column) across subs
+                tacc[4 * m + 2 * i] += orr;
+                tacc[4 * m + 2 * i + 1] += oii;
+            } else if (ok) {
+                float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int t = 4 * g + jj;
+                    if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
+                }
             }
         }
     }
@@ -496,65 +597,16 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     }
     // FP32: coefficient s = 4 kk + g, so each lane reads x at a fixed base
     // plus a compile-time step per kk; A comes pre-arranged (lv.amat, zero
-    // past r_in and r_out) and steps past r_in read finite (zeroed) LDS
-    const float (&aM)[8] = aMin;            // loaded by the caller
-    const int xoff = g * VT + col;
-    const int nunits = a.Gk >> 1;
-    const int ntiles = (nunits + UPT - 1) / UPT;
-#pragma unroll
-    for (int m = 0; m < wave_tiles<VT>() / 2; ++m) {
-        const int tau = wave + m * nwaves;
-        if (tau >= ntiles) break;
-        int unit = tau * UPT + sub;
-        const bool ok = unit < nunits;
-        if (!ok) unit = 0;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const int rv = digit_rev(apl, j - 1, 1);
-        const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
-        const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
-        float2 x0[4], x1[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            if (kk >= nks) break;
-            x0[kk] = xp0[kk * 4 * VT];
-            x1[kk] = xp1[kk * 4 * VT];
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            floatx4 y0r = {0.f, 0.f, 0.f, 0.f}, y0i = y0r, y1r = y0r, y1i = y0r;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                if (kk >= nks) break;
-                const float am = aM[4 * i + kk];
-                y0r = mfma4(am, x0[kk].x, y0r);
-                y0i = mfma4(am, x0[kk].y, y0i);
-                y1r = mfma4(am, x1[kk].x, y1r);
-                y1i = mfma4(am, x1[kk].y, y1i);
-            }
-            // rows t >= r_out read finite (zeroed or stale) twiddles and are
-            // never stored
-            const float2* tp = twl + (unit * 4 + i * 2) * r_out + 4 * g;
-            floatx4 orr, oii;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const float2 T0 = tp[jj];
-                const float2 T1 = tp[r_out + jj];
-                orr[jj] = T0.x * y0r[jj] - T0.y * y0i[jj] + T1.x * y1r[jj] - T1.y * y1i[jj];
-                oii[jj] = T0.x * y0i[jj] + T0.y * y0r[jj] + T1.x * y1i[jj] + T1.y * y1r[jj];
-            }
-            if (to_tail) {
-                // fixed (tau, lane) -> (A box, point, column) across subs
-                tacc[4 * m + 2 * i] += orr;
-                tacc[4 * m + 2 * i + 1] += oii;
-            } else if (ok) {
-                float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int t = 4 * g + jj;
-                    if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
-                }
-            }
-        }
+    // past r_in and r_out) and steps past r_in read finite (zeroed) LDS.
+    // The tile loop is instantiated per number of K steps.
+    (void)tA;
+    switch (nks) {
+#define BF_X_CASE(NK)                                                      \
+        case NK:                                                           \
+            x_tiles_fp32<VT, NK>(a, src, dst, twl, j, to_tail, tacc, aMin); \
+            break;
+        BF_X_CASE(1) BF_X_CASE(2) BF_X_CASE(3) default: BF_X_CASE(4)
+#undef BF_X_CASE
     }
 }
 
