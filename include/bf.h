@@ -347,6 +347,46 @@ int bf_points(int box_size, int q, int* out, int cap, int* count);
  * 2.1).                                                                   */
 int bf_lagrange(const int* nodes, int r, const double* y, int m, double* out);
 
+/* ---- phase recovery under indirect access (Section 3.2) ------------------
+ * When K is known only through entry evaluation (Scenario 1 of Table
+ * (tab:sc)) or applies of K and K^T (Scenario 2), its samples fix the phase
+ * modulo 1 only.  These host routines (FP64, synchronous, no device use)
+ * recover a low-rank Psi = U V^T with exp(2 pi i Psi) = exp(2 pi i Phi) for
+ * a BF_PHASE_LOWRANK plan.  Phases are in cycles; indices are 0-based.     */
+
+/* Algorithm 3: v (length n) equal to u modulo 1, continued by matching
+ * second differences, restarting where 2 pi |second difference| > tau (an
+ * angle; the paper uses pi / 2).  disc (capacity cap) receives the restart
+ * indices, disc[0] = 0; *ndisc their number (may exceed cap).
+ * Returns BF_EINVAL for n < 3, tau <= 0 or NULL pointers.                   */
+int bf_unwrap(const double* u, long long n, double tau, double* v,
+              long long* disc, int cap, int* ndisc);
+
+/* Sampler callback of bf_recover_phase: the phase modulo 1 of count columns
+ * (is_row = 0; out [N][count], out[i * count + k] = Phi(i, idx[k])) or rows
+ * (is_row = 1; out [count][N], out[k * N + j] = Phi(idx[k], j)).  Returns 0
+ * on success.  Scenario 2: the columns of K are K e_j, its rows K^T e_i;
+ * the phase is arg(K) / (2 pi) after the amplitude is divided out.        */
+typedef int (*bf_phase_sampler)(void* ctx, int is_row, int count,
+                                const long long* idx, double* out);
+
+/* Algorithm 5 for a 1D phase: from the sampled columns C (nc indices) and
+ * rows R (nr indices), both sorted, distinct, in [0, N) and drawn by the
+ * caller (the method's random choice, e.g. rank * oversampling of each),
+ * Algorithm 4 recovers unwrapped columns and rows that agree where they
+ * meet (sampling the discontinuity rows and columns it detects and each
+ * block's first three rows and columns; the detection threshold is tau as
+ * in bf_unwrap, none inside a block), then Algorithm 1's factorization
+ * restricted to those samples gives Psi ~ U V^T of rank
+ * k = *rank_out <= min(rank, cap_rank).  U, V: host [N][cap_rank]
+ * row-major, columns past k zero.  Memory: about (nc + nr + 2 k) N doubles
+ * of host scratch.  Returns BF_EINVAL for bad arguments, too few samples
+ * for the rank, or a failing sampler.                                     */
+int bf_recover_phase(long long N, const long long* C, int nc,
+                     const long long* R, int nr, int rank, double tau,
+                     bf_phase_sampler sample, void* ctx, int cap_rank,
+                     double* U, double* V, int* rank_out);
+
 #ifdef __cplusplus
 }
 #endif

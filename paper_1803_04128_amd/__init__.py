@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
-           "apply_chain", "fourier_coefficients_plan"]
+           "apply_chain", "fourier_coefficients_plan", "unwrap",
+           "recover_phase", "kernel_phase_sampler"]
 
 
 def load():
@@ -295,4 +296,90 @@ def fourier_coefficients_plan(n, q=10, precision="fp32", max_nvec=1):
     b = np.ones((1, n), np.complex128)
     return Plan(1, n, "dft", (), q=q, amplitude=(a, b), precision=precision,
                 max_nvec=max_nvec, op="H")
+
+
+def unwrap(u, tau=np.pi / 2):
+    """Algorithm 3 (bf_unwrap): v equal to u modulo 1 with matched second
+    differences, and the restart (discontinuity) indices."""
+    lib = _lib.load()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.empty_like(u)
+    cap = 64
+    disc = (C.c_longlong * cap)()
+    nd = C.c_int()
+    dp = C.POINTER(C.c_double)
+    _lib.check(lib.bf_unwrap(u.ctypes.data_as(dp), u.size, float(tau),
+                             v.ctypes.data_as(dp), disc, cap, C.byref(nd)))
+    if nd.value > cap:
+        raise RuntimeError("more restarts than the buffer holds")
+    return v, np.asarray(disc[:nd.value], np.int64)
+
+
+def recover_phase(N, C_idx, R_idx, sampler, rank=8, tau=np.pi / 2):
+    """Algorithm 5 (bf_recover_phase) for a 1D phase known modulo 1 through
+    sampler(is_row, idx) -> [N][len(idx)] (columns) or [len(idx)][N] (rows),
+    phases in cycles.  C_idx, R_idx: the sampled column and row indices
+    (the caller's random choice).  Returns U, V [N][k] with exp(2 pi i U
+    V^T) = exp(2 pi i Phi), for Plan(..., "lowrank", (U, V))."""
+    lib = _lib.load()
+    Ci = np.ascontiguousarray(np.unique(C_idx), dtype=np.int64)
+    Ri = np.ascontiguousarray(np.unique(R_idx), dtype=np.int64)
+    failure = []
+
+    def cb(ctx, is_row, count, idx, out):
+        try:
+            ids = np.ctypeslib.as_array(idx, shape=(count,)).copy()
+            vals = np.asarray(sampler(bool(is_row), ids), np.float64)
+            want = (count, N) if is_row else (N, count)
+            if vals.shape != want:
+                raise ValueError(f"sampler returned {vals.shape}, "
+                                 f"expected {want}")
+            np.ctypeslib.as_array(out, shape=(count * N,))[:] = vals.ravel()
+            return 0
+        except Exception as e:          # reported after the call
+            failure.append(e)
+            return 1
+
+    cfun = _lib.SAMPLER(cb)
+    cap = int(rank)
+    U = np.zeros((N, cap))
+    V = np.zeros((N, cap))
+    k = C.c_int()
+    lp = C.POINTER(C.c_longlong)
+    dp = C.POINTER(C.c_double)
+    rc = lib.bf_recover_phase(int(N), Ci.ctypes.data_as(lp), Ci.size,
+                              Ri.ctypes.data_as(lp), Ri.size, int(rank),
+                              float(tau), cfun, None, cap,
+                              U.ctypes.data_as(dp), V.ctypes.data_as(dp),
+                              C.byref(k))
+    if failure:
+        raise failure[0]
+    _lib.check(rc)
+    return U[:, :k.value].copy(), V[:, :k.value].copy()
+
+
+def kernel_phase_sampler(plan, plan_t, amplitude=None):
+    """Scenario 2 sampler for recover_phase: the columns of K are K e_j
+    (applies of ``plan``), its rows K^T e_i (applies of ``plan_t``, a
+    BF_OP_T plan of the same kernel); the phase in cycles is arg(K / alpha)
+    / (2 pi).  amplitude: None (alpha = 1) or a callable (is_row, idx) ->
+    alpha on the same samples."""
+    import torch
+    N = plan.N
+
+    def sample(is_row, idx):
+        pl = plan_t if is_row else plan
+        out = np.empty((len(idx), N), np.complex128)
+        step = pl.max_nvec
+        for s in range(0, len(idx), step):
+            part = idx[s:s + step]
+            e = torch.zeros((len(part), N), dtype=torch.complex64,
+                            device="cuda")
+            e[torch.arange(len(part)), torch.as_tensor(part)] = 1.0
+            out[s:s + len(part)] = pl.apply(e).cpu().numpy()
+        if amplitude is not None:
+            out = out / np.asarray(amplitude(is_row, idx))
+        ph = np.angle(out) / (2 * np.pi)
+        return ph if is_row else ph.T
+    return sample
 

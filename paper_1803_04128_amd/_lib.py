@@ -60,7 +60,11 @@ class BfTuneEntry(C.Structure):
     _fields_ = [("config", BfConfig), ("ms", C.c_double)]
 
 
-EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
+SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
+                      C.POINTER(C.c_longlong), C.POINTER(C.c_double))
+
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain", "bf_unwrap",
+           "bf_recover_phase", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
            "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
            "bf_set_config", "bf_autotune", "bf_graph_create",
@@ -98,6 +102,14 @@ def load():
     lib.bf_plan_op.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude),
                                C.c_int, C.c_int, C.c_int, C.c_int,
                                P(C.c_void_p)]
+    lib.bf_unwrap.argtypes = [P(C.c_double), C.c_longlong, C.c_double,
+                              P(C.c_double), P(C.c_longlong), C.c_int,
+                              P(C.c_int)]
+    lib.bf_recover_phase.argtypes = [C.c_longlong, P(C.c_longlong), C.c_int,
+                                     P(C.c_longlong), C.c_int, C.c_int,
+                                     C.c_double, SAMPLER, C.c_void_p,
+                                     C.c_int, P(C.c_double), P(C.c_double),
+                                     P(C.c_int)]
     lib.bf_apply_chain.argtypes = [P(C.c_void_p), C.c_int, C.c_int,
                                    C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]

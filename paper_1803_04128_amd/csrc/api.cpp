@@ -126,6 +126,42 @@ int bf_points(int box_size, int q, int* out, int cap, int* count) {
     return BF_OK;
 }
 
+int bf_unwrap(const double* u, long long n, double tau, double* v,
+              long long* disc, int cap, int* ndisc) {
+    if (!u || !v || !ndisc || n < 3 || !(tau > 0) || (cap > 0 && !disc) ||
+        cap < 0)
+        return fail(BF_EINVAL, "bf_unwrap: bad argument");
+    return bfi::unwrap_vector(u, n, tau, v, disc, cap, ndisc);
+}
+
+static bool sorted_unique(const long long* a, int n, long long N) {
+    for (int i = 0; i < n; ++i) {
+        if (a[i] < 0 || a[i] >= N) return false;
+        if (i > 0 && a[i] <= a[i - 1]) return false;
+    }
+    return true;
+}
+
+int bf_recover_phase(long long N, const long long* C, int nc,
+                     const long long* R, int nr, int rank, double tau,
+                     bf_phase_sampler sample, void* ctx, int cap_rank,
+                     double* U, double* V, int* rank_out) {
+    if (N < 8 || !C || !R || nc < 1 || nr < 1 || rank < 1 || rank > 64 ||
+        cap_rank < 1 || cap_rank > 64 || !(tau > 0) || !sample || !U ||
+        !V || !rank_out)
+        return fail(BF_EINVAL, "bf_recover_phase: bad argument");
+    if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
+        return fail(BF_EINVAL,
+                    "bf_recover_phase: C and R must be sorted, distinct and "
+                    "in [0, N)");
+    const int rc = bfi::recover_phase(N, C, nc, R, nr, rank, tau, sample,
+                                      ctx, cap_rank, U, V, rank_out);
+    if (rc != BF_OK)
+        return fail(rc, std::string("bf_recover_phase: ") +
+                            bfi::recovery_error());
+    return BF_OK;
+}
+
 int bf_lagrange(const int* nodes, int r, const double* y, int m,
                 double* out) {
     if (!nodes || !y || !out || r < 1 || m < 0)

@@ -183,6 +183,14 @@ std::string build_schedule(Plan& p);   // "" on success, else a message
 std::string build_factors(Plan& p);
 std::string upload_amplitude(Plan& p, const double* a, const double* b);
 std::string build_switch_blocks(Plan& p);
+// phase recovery (recovery.cpp); arguments checked by the C ABI
+int recover_phase(long long N, const long long* C, int nc, const long long* R,
+                  int nr, int rank, double tau, bf_phase_sampler sample,
+                  void* ctx, int cap_rank, double* U, double* V,
+                  int* rank_out);
+int unwrap_vector(const double* u, long long n, double tau, double* v,
+                  long long* disc, int cap, int* ndisc);
+const char* recovery_error();
 // whether the plan's current execution form reads the stored switch blocks
 inline bool reads_stored_switch(const Plan& p) {
     return !(p.switch_otf && !p.fused && p.mfma);

@@ -1,0 +1,110 @@
+"""Parity of the library's phase recovery (bf_unwrap, bf_recover_phase:
+host C++, Section 3.2) with the oracle's (oracle/recovery.py), on the same
+samples: Algorithm 3 bit for bit (both decide in FP64), Algorithm 5 through
+the recovered Psi = U V^T (the factors themselves are unique only up to a
+rotation), plus argument checks.  No GPU is needed."""
+
+import numpy as np
+import pytest
+
+import oracle.recovery as rec
+from synthetic import lowrank_phase
+
+def _bfm():
+    import paper_1803_04128_amd as bfm
+    return bfm
+
+
+def _frac(x):
+    return x - np.round(x)
+
+
+def _vectors():
+    i = np.arange(3000)
+    t = i / i.size
+    yield 0.37 * i + 40 * t * t + 3 * np.sin(4 * np.pi * t)
+    yield 0.7 * i + 0.123
+    yield np.where(i < 500, 0.1 * i, 0.1 * 499 + 0.45 * (i - 499))
+    rng = np.random.default_rng(150)
+    yield np.cumsum(np.cumsum(rng.standard_normal(3000) * 0.02))
+    yield np.where(i % 700 < 350, 0.2 * i, -0.3 * i)
+
+
+@pytest.mark.parametrize("k", range(5))
+@pytest.mark.parametrize("tau", [np.pi / 2, 1.0, 2 * np.pi])
+def test_unwrap_bitwise_equal_to_oracle(k, tau):
+    v = list(_vectors())[k]
+    u = _frac(v)
+    w, S = _bfm().unwrap(u, tau)
+    wo, So = rec.unwrap_vector(u, tau)
+    assert np.array_equal(S, So)
+    assert np.array_equal(w, wo)
+
+
+def _phase_sampler(Phi):
+    def sample(is_row, idx):
+        return _frac(Phi[idx, :] if is_row else Phi[:, idx])
+    return sample
+
+
+def _fio_phase(N, params):
+    i = np.arange(N)
+    x, xi = i / N, i - N // 2
+    c = (params[0] + params[1] * np.sin(2 * np.pi * x)) / params[2]
+    return np.outer(x, xi) + np.outer(c, np.abs(xi))
+
+
+def _cases():
+    yield "fio paper", _fio_phase(2048, (2.0, 0.2, 16.0))
+    yield "fio wide", _fio_phase(2048, (2.0, 1.0, 8.0))
+    U, V = lowrank_phase(1, 1024, 4, 151)
+    yield "synthetic rank 4", U @ V.T
+    U, V = lowrank_phase(1, 2048, 3, 152)
+    yield "synthetic rank 3", U @ V.T
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_recover_phase_matches_oracle(case):
+    name, Phi = list(_cases())[case]
+    N = Phi.shape[0]
+    rng = np.random.default_rng(160 + case)
+    C = np.sort(rng.choice(N, 24, replace=False))
+    R = np.sort(rng.choice(N, 24, replace=False))
+    sampler = _phase_sampler(Phi)
+    U, V = _bfm().recover_phase(N, C, R, sampler, rank=8)
+    Cs, cols, Rs, rows = rec.unwrap_samples(
+        C, R, np.pi / 2, lambda idx: sampler(False, np.asarray(idx)),
+        lambda idx: sampler(True, np.asarray(idx)))
+    Uo, Vo = rec.lowrank_from_samples(cols, rows, Cs, Rs, 8)
+    assert U.shape[1] == Uo.shape[1], name
+    i, j = rng.integers(0, N, 4000), rng.integers(0, N, 4000)
+    psi = np.sum(U[i] * V[j], axis=1)
+    psio = np.sum(Uo[i] * Vo[j], axis=1)
+    scale = np.max(np.abs(psio))
+    assert np.max(np.abs(psi - psio)) < 1e-9 * scale, name
+    # and the recovered kernel is the original one on unsampled entries
+    assert np.max(np.abs(np.exp(2j * np.pi * psi) -
+                         np.exp(2j * np.pi * Phi[i, j]))) < 1e-8, name
+
+
+def test_recover_phase_argument_errors():
+    bfm = _bfm()
+    N = 64
+    Phi = _fio_phase(N, (2.0, 0.2, 16.0))
+    s = _phase_sampler(Phi)
+    with pytest.raises(bfm.BfError):
+        bfm.recover_phase(N, [5, 3], [1, 2], s, rank=0)
+    with pytest.raises(bfm.BfError):
+        bfm.recover_phase(N, [1, 2, N], [1, 2], s)
+
+    def bad_shape(is_row, idx):
+        return np.zeros((3, 3))
+    with pytest.raises(ValueError):
+        bfm.recover_phase(N, [1, 2, 3], [1, 2, 3], bad_shape)
+
+    def raising(is_row, idx):
+        raise KeyError("no access")
+    with pytest.raises(KeyError):
+        bfm.recover_phase(N, [1, 2, 3], [1, 2, 3], raising)
+    with pytest.raises(bfm.BfError):
+        bfm.unwrap(np.zeros(2))
