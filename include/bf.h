@@ -362,6 +362,21 @@ int bf_lagrange(const int* nodes, int r, const double* y, int m, double* out);
 int bf_unwrap(const double* u, long long n, double tau, double* v,
               long long* disc, int cap, int* ndisc);
 
+/* Algorithm 1 (randomized low-rank factorization) restricted to given
+ * samples of a real N x N matrix A: columns cols [nc][N] (cols[k * N + i] =
+ * A(i, C[k])) and rows rows [nr][N] (rows[k * N + j] = A(R[k], j)), C and R
+ * sorted, distinct, in [0, N), the rows and columns agreeing where they
+ * meet.  The important columns and rows are the pivots of pivoted QR / LQ
+ * of A(R, C); A ~ U V^T of rank k = *rank_out <= min(rank, cap_rank) (at
+ * most the numerical rank of A(R, C)), U, V host [N][cap_rank], columns
+ * past k zero.  Used for the amplitude of a kernel known through samples
+ * (A = |K|, Section 3.3) and inside bf_recover_phase.  Returns BF_EINVAL
+ * for bad arguments or too few samples.                                   */
+int bf_lowrank_samples(long long N, const double* cols, const long long* C,
+                       int nc, const double* rows, const long long* R, int nr,
+                       int rank, int cap_rank, double* U, double* V,
+                       int* rank_out);
+
 /* Sampler callback of bf_recover_phase: the phase modulo 1 of count columns
  * (is_row = 0; out [N][count], out[i * count + k] = Phi(i, idx[k])) or rows
  * (is_row = 1; out [count][N], out[k * N + j] = Phi(idx[k], j)).  Returns 0

@@ -17,7 +17,8 @@ from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
            "apply_chain", "fourier_coefficients_plan", "unwrap",
-           "recover_phase", "kernel_phase_sampler"]
+           "recover_phase", "kernel_phase_sampler", "lowrank_from_samples",
+           "kernel_samples", "recover_kernel"]
 
 
 def load():
@@ -358,28 +359,81 @@ def recover_phase(N, C_idx, R_idx, sampler, rank=8, tau=np.pi / 2):
     return U[:, :k.value].copy(), V[:, :k.value].copy()
 
 
+def lowrank_from_samples(N, cols, C_idx, rows, R_idx, rank=8):
+    """Algorithm 1 on given samples of a real N x N matrix A
+    (bf_lowrank_samples): cols [N][len(C_idx)] = A(:, C_idx), rows
+    [len(R_idx)][N] = A(R_idx, :), indices sorted and distinct.  Returns
+    U, V [N][k] with A ~ U V^T."""
+    lib = _lib.load()
+    Ci = np.ascontiguousarray(C_idx, dtype=np.int64)
+    Ri = np.ascontiguousarray(R_idx, dtype=np.int64)
+    cols_t = np.ascontiguousarray(np.asarray(cols, np.float64).T)
+    rows_c = np.ascontiguousarray(rows, dtype=np.float64)
+    if cols_t.shape != (Ci.size, N) or rows_c.shape != (Ri.size, N):
+        raise ValueError("cols must be [N][len(C)] and rows [len(R)][N]")
+    cap = int(rank)
+    U = np.zeros((N, cap))
+    V = np.zeros((N, cap))
+    k = C.c_int()
+    lp = C.POINTER(C.c_longlong)
+    dp = C.POINTER(C.c_double)
+    _lib.check(lib.bf_lowrank_samples(
+        int(N), cols_t.ctypes.data_as(dp), Ci.ctypes.data_as(lp), Ci.size,
+        rows_c.ctypes.data_as(dp), Ri.ctypes.data_as(lp), Ri.size, int(rank),
+        cap, U.ctypes.data_as(dp), V.ctypes.data_as(dp), C.byref(k)))
+    return U[:, :k.value].copy(), V[:, :k.value].copy()
+
+
+def kernel_samples(plan, plan_t, idx, rows):
+    """Columns K e_j (rows=False; [N][len(idx)]) or rows K^T e_i (rows=True;
+    [len(idx)][N]) of the kernel from applies of ``plan`` and of
+    ``plan_t`` (a BF_OP_T plan of the same kernel) to unit vectors."""
+    import torch
+    N = plan.N
+    pl = plan_t if rows else plan
+    out = np.empty((len(idx), N), np.complex128)
+    step = pl.max_nvec
+    for s in range(0, len(idx), step):
+        part = np.asarray(idx[s:s + step])
+        e = torch.zeros((len(part), N), dtype=torch.complex64, device="cuda")
+        e[torch.arange(len(part)), torch.as_tensor(part)] = 1.0
+        out[s:s + len(part)] = pl.apply(e).cpu().numpy()
+    return out if rows else out.T
+
+
+def recover_kernel(plan, plan_t, C_idx, R_idx, amp_rank=4, phase_rank=4,
+                   tau=np.pi / 2):
+    """Scenario 2 of Table (tab:sc), 1D: from applies of K and K^T only,
+    the amplitude's low-rank factors (Algorithm 1 on |K|) and the phase's
+    (Algorithm 5 on arg K, the amplitude being positive).  Returns
+    ((a, b), (U, V)): a, b complex [k][N] for Plan(amplitude=(a, b)) and
+    U, V for Plan(phase="lowrank", params=(U, V))."""
+    N = plan.N
+    Ci = np.unique(np.asarray(C_idx, np.int64))
+    Ri = np.unique(np.asarray(R_idx, np.int64))
+    cols = np.abs(kernel_samples(plan, plan_t, Ci, rows=False))
+    rows = np.abs(kernel_samples(plan, plan_t, Ri, rows=True))
+    # rows and columns must agree where they meet: take the row samples
+    # there (both are the same entries of |K| up to the applies' rounding)
+    cols[Ri, :] = rows[:, Ci]
+    Ua, Va = lowrank_from_samples(N, cols, Ci, rows, Ri, amp_rank)
+    U, V = recover_phase(N, Ci, Ri, kernel_phase_sampler(plan, plan_t),
+                         rank=phase_rank, tau=tau)
+    return ((Ua.T.astype(np.complex128), Va.T.astype(np.complex128)),
+            (U, V))
+
+
 def kernel_phase_sampler(plan, plan_t, amplitude=None):
     """Scenario 2 sampler for recover_phase: the columns of K are K e_j
     (applies of ``plan``), its rows K^T e_i (applies of ``plan_t``, a
     BF_OP_T plan of the same kernel); the phase in cycles is arg(K / alpha)
-    / (2 pi).  amplitude: None (alpha = 1) or a callable (is_row, idx) ->
-    alpha on the same samples."""
-    import torch
-    N = plan.N
-
+    / (2 pi), which for a positive amplitude is arg(K) / (2 pi).
+    amplitude: None or a callable (is_row, idx) -> alpha on the same
+    samples."""
     def sample(is_row, idx):
-        pl = plan_t if is_row else plan
-        out = np.empty((len(idx), N), np.complex128)
-        step = pl.max_nvec
-        for s in range(0, len(idx), step):
-            part = idx[s:s + step]
-            e = torch.zeros((len(part), N), dtype=torch.complex64,
-                            device="cuda")
-            e[torch.arange(len(part)), torch.as_tensor(part)] = 1.0
-            out[s:s + len(part)] = pl.apply(e).cpu().numpy()
+        k = kernel_samples(plan, plan_t, idx, rows=is_row)
         if amplitude is not None:
-            out = out / np.asarray(amplitude(is_row, idx))
-        ph = np.angle(out) / (2 * np.pi)
-        return ph if is_row else ph.T
+            k = k / np.asarray(amplitude(is_row, idx))
+        return np.angle(k) / (2 * np.pi)
     return sample
 

@@ -64,7 +64,7 @@ SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
 EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain", "bf_unwrap",
-           "bf_recover_phase", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
+           "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
            "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
            "bf_set_config", "bf_autotune", "bf_graph_create",
@@ -110,6 +110,12 @@ def load():
                                      C.c_double, SAMPLER, C.c_void_p,
                                      C.c_int, P(C.c_double), P(C.c_double),
                                      P(C.c_int)]
+    lib.bf_lowrank_samples.argtypes = [C.c_longlong, P(C.c_double),
+                                       P(C.c_longlong), C.c_int,
+                                       P(C.c_double), P(C.c_longlong),
+                                       C.c_int, C.c_int, C.c_int,
+                                       P(C.c_double), P(C.c_double),
+                                       P(C.c_int)]
     lib.bf_apply_chain.argtypes = [P(C.c_void_p), C.c_int, C.c_int,
                                    C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]

@@ -162,6 +162,26 @@ int bf_recover_phase(long long N, const long long* C, int nc,
     return BF_OK;
 }
 
+int bf_lowrank_samples(long long N, const double* cols, const long long* C,
+                       int nc, const double* rows, const long long* R, int nr,
+                       int rank, int cap_rank, double* U, double* V,
+                       int* rank_out) {
+    if (N < 1 || !cols || !rows || !C || !R || nc < 1 || nr < 1 ||
+        rank < 1 || rank > 64 || cap_rank < 1 || cap_rank > 64 || !U || !V ||
+        !rank_out)
+        return fail(BF_EINVAL, "bf_lowrank_samples: bad argument");
+    if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
+        return fail(BF_EINVAL,
+                    "bf_lowrank_samples: C and R must be sorted, distinct "
+                    "and in [0, N)");
+    const int rc = bfi::lowrank_fit(N, cols, C, nc, rows, R, nr, rank,
+                                    cap_rank, U, V, rank_out);
+    if (rc != BF_OK)
+        return fail(rc, std::string("bf_lowrank_samples: ") +
+                            bfi::recovery_error());
+    return BF_OK;
+}
+
 int bf_lagrange(const int* nodes, int r, const double* y, int m,
                 double* out) {
     if (!nodes || !y || !out || r < 1 || m < 0)

@@ -190,6 +190,9 @@ int recover_phase(long long N, const long long* C, int nc, const long long* R,
                   int* rank_out);
 int unwrap_vector(const double* u, long long n, double tau, double* v,
                   long long* disc, int cap, int* ndisc);
+int lowrank_fit(long long N, const double* cols, const long long* Cs, int mc,
+                const double* rows, const long long* Rs, int mr, int rank,
+                int cap_rank, double* U, double* V, int* rank_out);
 const char* recovery_error();
 // whether the plan's current execution form reads the stored switch blocks
 inline bool reads_stored_switch(const Plan& p) {

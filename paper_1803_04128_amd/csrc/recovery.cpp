@@ -224,6 +224,10 @@ namespace bfi {
 
 const char* recovery_error() { return g_rec_error.c_str(); }
 
+int lowrank_fit(long long N, const double* colsp, const long long* Cs,
+                int mc, const double* rowsp, const long long* Rs, int mr,
+                int rank, int cap_rank, double* U, double* V, int* rank_out);
+
 // Algorithm 4 + Algorithm 1 (see bf.h, bf_recover_phase).
 int recover_phase(long long N, const long long* C0, int nc,
                   const long long* R0, int nr, int rank, double tau,
@@ -314,10 +318,25 @@ int recover_phase(long long N, const long long* C0, int nc,
             }
         }
     }
-    // --- Algorithm 1 on the recovered samples
+    return lowrank_fit(N, cols.data(), Cs.data(), mc, rows.data(), Rs.data(),
+                       mr, rank, cap_rank, U, V, rank_out);
+}
+
+// Algorithm 1 on sampled columns cols [mc][N] (column-major, column k =
+// Psi(:, Cs[k])) and rows rows [mr][N] (row k = Psi(Rs[k], :)): important
+// columns and rows by pivoted QR / LQ of Psi(Rs, Cs), orthonormal bases of
+// the important columns and rows, M = Qc(Rs, :)^+ Psi(Rs, Cs) (Qr(Cs, :)^T)^+
+// and its SVD; Psi ~ U V^T with U = Qc U_M S, V = Qr V_M.
+int lowrank_fit(long long N, const double* colsp, const long long* Cs,
+                int mc, const double* rowsp, const long long* Rs, int mr,
+                int rank, int cap_rank, double* U, double* V, int* rank_out) {
+    auto err = [](const char* m) {
+        g_rec_error = m;
+        return BF_EINVAL;
+    };
     std::vector<double> W((size_t)mr * mc);     // Psi(Rs, Cs)
     for (int a = 0; a < mr; ++a)
-        for (int b = 0; b < mc; ++b) W[(size_t)a * mc + b] = rows[(size_t)a * N + Cs[b]];
+        for (int b = 0; b < mc; ++b) W[(size_t)a * mc + b] = rowsp[(size_t)a * N + Cs[b]];
     std::vector<int> pc, pr;
     std::vector<double> dc, dr;
     pivoted_qr(W, mr, mc, pc, dc);
@@ -333,8 +352,8 @@ int recover_phase(long long N, const long long* C0, int nc,
     // bases of Psi(:, Pi_col) and Psi(Pi_row, :)^T
     std::vector<double> X((size_t)k * N), Y((size_t)k * N);
     for (int j = 0; j < k; ++j) {
-        std::memcpy(&X[(size_t)j * N], &cols[(size_t)pc[j] * N], sizeof(double) * N);
-        std::memcpy(&Y[(size_t)j * N], &rows[(size_t)pr[j] * N], sizeof(double) * N);
+        std::memcpy(&X[(size_t)j * N], &colsp[(size_t)pc[j] * N], sizeof(double) * N);
+        std::memcpy(&Y[(size_t)j * N], &rowsp[(size_t)pr[j] * N], sizeof(double) * N);
     }
     const std::vector<double> Qc = orthonormal_basis(X, N, k);
     const std::vector<double> Qr = orthonormal_basis(Y, N, k);

@@ -108,3 +108,31 @@ def test_recover_phase_argument_errors():
         bfm.recover_phase(N, [1, 2, 3], [1, 2, 3], raising)
     with pytest.raises(bfm.BfError):
         bfm.unwrap(np.zeros(2))
+
+
+@pytest.mark.parametrize("rank", [1, 2, 4])
+def test_lowrank_samples_matches_oracle(rank):
+    # Algorithm 1 on samples of an exact rank-k matrix: library and oracle
+    # both reproduce it everywhere
+    rng = np.random.default_rng(180 + rank)
+    N = 1500
+    A = rng.standard_normal((N, rank)) @ rng.standard_normal((rank, N))
+    Cs = np.sort(rng.choice(N, 3 * rank + 5, replace=False))
+    Rs = np.sort(rng.choice(N, 3 * rank + 5, replace=False))
+    U, V = _bfm().lowrank_from_samples(N, A[:, Cs], Cs, A[Rs, :], Rs, 8)
+    Uo, Vo = rec.lowrank_from_samples(A[:, Cs], A[Rs, :], Cs, Rs, 8)
+    assert U.shape[1] == Uo.shape[1] == rank
+    scale = np.max(np.abs(A))
+    assert np.max(np.abs(U @ V.T - A)) < 1e-9 * scale
+    assert np.max(np.abs(U @ V.T - Uo @ Vo.T)) < 1e-9 * scale
+
+
+def test_lowrank_samples_argument_errors():
+    bfm = _bfm()
+    A = np.ones((16, 16))
+    with pytest.raises(bfm.BfError):
+        bfm.lowrank_from_samples(16, A[:, [3, 1]], [3, 1], A[[1, 2], :],
+                                 [1, 2])
+    with pytest.raises(ValueError):
+        bfm.lowrank_from_samples(16, A[:, [1, 3]], [1, 3, 5], A[[1, 2], :],
+                                 [1, 2])
