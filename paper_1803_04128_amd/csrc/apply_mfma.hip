@@ -238,7 +238,8 @@ __device__ __forceinline__ void xi_tiles_fp32(const PassArgs& a,
                                               const float2* src, int RS,
                                               float2* dst, const float2* twl,
                                               int j, const float (&aM)[8],
-                                              int xoff, int woff) {
+                                              int xoff, int woff,
+                                              float2* sink) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int kj = a.k - j;
@@ -271,13 +272,15 @@ __device__ __forceinline__ void xi_tiles_fp32(const PassArgs& a,
             accr = mfma4(aM[kk], w.x * x.x - w.y * x.y, accr);
             acci = mfma4(aM[kk], w.x * x.y + w.y * x.x, acci);
         }
-        if (ok) {
-            float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
+        // rows t >= r_out (exactly zero: A is zero there) and padding
+        // columns go to this lane's slot of the pass's pad instead of
+        // branching around the stores
+        float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int t = 4 * g + jj;
-                if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
-            }
+        for (int jj = 0; jj < 4; ++jj) {
+            const int t = 4 * g + jj;
+            float2* p = (ok && t < r_out) ? op + t * VT : sink + lane;
+            *p = make_float2(accr[jj], acci[jj]);
         }
     }
 }
@@ -287,7 +290,8 @@ template <int VT, int PREC>
 __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
                                               const float2* src, int src_r,
                                               float2* dst, const float2* twl,
-                                              int j, const float (&aMin)[8]) {
+                                              int j, const float (&aMin)[8],
+                                              float2* sink) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int K = 2 * r_in, nks = (K + 3) / 4;
@@ -391,7 +395,7 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
 #define BF_XI_CASE(NK)                                                     \
         case NK:                                                           \
             xi_tiles_fp32<VT, NK>(a, src, RS, dst, twl, j, aMin, xoff,     \
-                                  woff);                                   \
+                                  woff, sink);                             \
             break;
         BF_XI_CASE(1) BF_XI_CASE(2) BF_XI_CASE(3) BF_XI_CASE(4)
         BF_XI_CASE(5) BF_XI_CASE(6) BF_XI_CASE(7) default: BF_XI_CASE(8)
@@ -405,7 +409,8 @@ __device__ __forceinline__ void x_tiles_fp32(const PassArgs& a,
                                              const float2* src, float2* dst,
                                              const float2* twl, int j,
                                              bool to_tail, floatx4* tacc,
-                                             const float (&aM)[8]) {
+                                             const float (&aM)[8],
+                                             float2* sink) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_out = lv.r_out;
     const int kj = a.k - j;
@@ -461,12 +466,15 @@ __device__ __forceinline__ void x_tiles_fp32(const PassArgs& a,
                 // fixed (tau, lane) -> (A box, point, column) across subs
                 tacc[4 * m + 2 * i] += orr;
                 tacc[4 * m + 2 * i + 1] += oii;
-            } else if (ok) {
+            } else {
+                // rows t >= r_out (finite: zero A rows times twiddles) and
+                // padding units go to this lane's slot of the pass's pad
                 float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const int t = 4 * g + jj;
-                    if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
+                    float2* p = (ok && t < r_out) ? op + t * VT : sink + lane;
+                    *p = make_float2(orr[jj], oii[jj]);
                 }
             }
         }
@@ -480,7 +488,8 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                                              const float2* src, float2* dst,
                                              const float2* twl, int j,
                                              bool to_tail, floatx4* tacc,
-                                             const float (&aMin)[8]) {
+                                             const float (&aMin)[8],
+                                             float2* sink) {
     const PassLevel& lv = a.lv[j - 1];
     const int r_in = lv.r_in, r_out = lv.r_out;
     const int nks = (r_in + 3) / 4;
@@ -603,7 +612,8 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
     switch (nks) {
 #define BF_X_CASE(NK)                                                      \
         case NK:                                                           \
-            x_tiles_fp32<VT, NK>(a, src, dst, twl, j, to_tail, tacc, aMin); \
+            x_tiles_fp32<VT, NK>(a, src, dst, twl, j, to_tail, tacc, aMin, \
+                                 sink);                                    \
             break;
         BF_X_CASE(1) BF_X_CASE(2) BF_X_CASE(3) default: BF_X_CASE(4)
 #undef BF_X_CASE
@@ -756,8 +766,10 @@ xi_pass_mfma(PassArgs a) {
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
-    zero_pass_lds(lds, tsz + 2 * wsz,
-                  a.has_head ? ftile + a.Gk * a.head_r * VT : ftile);
+    // zeroed pad after the tiles: reads past a level's rank land here, and
+    // stores of rows past r_out and of padding columns go here (finite)
+    float2* const pad = a.has_head ? ftile + a.Gk * a.head_r * VT : ftile;
+    zero_pass_lds(lds, tsz + 2 * wsz, pad);
     const int part = (int)(spatial % a.sub_split);
     spatial /= a.sub_split;
     const long long bg = spatial % a.nbg;
@@ -789,7 +801,7 @@ xi_pass_mfma(PassArgs a) {
             const bool from_f = j == 1 && a.has_head;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
-                                    odd ? W0 : W1, j, aM);
+                                    odd ? W0 : W1, j, aM, pad);
             next.store(odd ? W1 : W0);
             __syncthreads();
 #pragma unroll
@@ -804,7 +816,7 @@ xi_pass_mfma(PassArgs a) {
             const bool from_f = j == 1 && a.has_head;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
-                                    (j & 1) ? W0 : W1, j, aM);
+                                    (j & 1) ? W0 : W1, j, aM, pad);
             __syncthreads();
             if (a.has_switch)
                 mfma_switch<VT, sw_pairs<PREC>(), sw_ahead<PREC>()>(
@@ -827,7 +839,8 @@ x_pass_mfma(PassArgs a) {
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
-    zero_pass_lds(lds, tsz + 2 * wsz, lds + tsz + 2 * wsz);
+    float2* const pad = lds + tsz + 2 * wsz;
+    zero_pass_lds(lds, tsz + 2 * wsz, pad);
     // with x_split > 1 the workgroup takes part `part` of the B groups
     const int part = (int)(spatial % a.x_split);
     spatial /= a.x_split;
@@ -854,7 +867,7 @@ x_pass_mfma(PassArgs a) {
                 next.load(a, j + 1, ap_grp, bg, false);
             }
             mfma_x_level<VT, PREC>(a, T, T, odd ? W0 : W1, j,
-                                   a.has_tail && j == a.k, tacc, aM);
+                                   a.has_tail && j == a.k, tacc, aM, pad);
             if (j < a.k) next.store(odd ? W1 : W0);
             __syncthreads();
 #pragma unroll
