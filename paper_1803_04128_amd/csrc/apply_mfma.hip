@@ -367,13 +367,13 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
                     acci[jj] = ldexpf(acci[jj], ex);
                 }
             }
-            if (ok) {
-                float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
+            // rows past r_out (zero A rows) and padding columns: the pad
+            float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * DS + col;
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int t = 4 * g + jj;
-                    if (t < r_out) op[t * VT] = make_float2(accr[jj], acci[jj]);
-                }
+            for (int jj = 0; jj < 4; ++jj) {
+                const int t = 4 * g + jj;
+                float2* p = (ok && t < r_out) ? op + t * VT : sink + lane;
+                *p = make_float2(accr[jj], acci[jj]);
             }
         }
         return;
@@ -592,12 +592,14 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
                 if (to_tail) {
                     tacc[4 * m + 2 * i] += orr;
                     tacc[4 * m + 2 * i + 1] += oii;
-                } else if (ok) {
+                } else {
+                    // rows past r_out and padding units: the pad
                     float2* op = dst + (((bl * 2 + i) << (j - 1)) + rv) * RS + col;
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int t = 4 * g + jj;
-                        if (t < r_out) op[t * VT] = make_float2(orr[jj], oii[jj]);
+                        float2* p = (ok && t < r_out) ? op + t * VT : sink + lane;
+                        *p = make_float2(orr[jj], oii[jj]);
                     }
                 }
             }
