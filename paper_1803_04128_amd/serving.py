@@ -52,6 +52,7 @@ class PlanSpec:
     q: int = 8
     precision: str = "fp32"
     amplitude: Any = None        # None (alpha = 1) or (a, b), [r][N] arrays
+    op: str = "N"                # "N", "T", "C" or "H": K, K^T, conj K, K^H
 
     @property
     def N(self):
@@ -189,15 +190,15 @@ class ResidentPlan:
         self.spec = spec
         self.plan = Plan(spec.dim, spec.n, spec.phase, spec.params, q=spec.q,
                          amplitude=spec.amplitude, precision=spec.precision,
-                         max_nvec=max_batch)
+                         max_nvec=max_batch, op=spec.op)
         self.fin = torch.empty((max_batch, spec.N), dtype=torch.complex64,
                                device="cuda")
         self.fout = torch.empty_like(self.fin)
         info = self.plan.info()
+        # factor_bytes covers every device allocation of the plan (factors,
+        # amplitude, stored switch blocks, low-rank phase factors)
         self.footprint = (info["factor_bytes"] + info["workspace_bytes"] +
-                          2 * self.fin.numel() * 8 +
-                          (2 * spec.r * spec.N * 8 if spec.amplitude
-                           is not None else 0))
+                          2 * self.fin.numel() * 8)
 
     def run(self, reqs, stream):
         """Stage the requests' vectors, apply once, copy results out, all on

@@ -7,27 +7,33 @@ import numpy as np
 import pytest
 
 from _util import inputs, rel, log
-from oracle.butterfly import butterfly_matvec
+from oracle.butterfly import butterfly_apply, butterfly_matvec
 from synthetic import PHASE_PARAMS, amplitude_factors
 
 pytestmark = pytest.mark.gpu
 
+# name -> (dim, n, phase kind, q, amplitude, op)
 SPECS = {
-    "fio4096": (1, 4096, "fio1d", 8, None),
-    "fio2048_r4": (1, 2048, "fio1d", 8, ("sincos", 4)),
-    "radon32": (2, 32, "radon2d", 7, None),
+    "fio4096": (1, 4096, "fio1d", 8, None, "N"),
+    "fio2048_r4": (1, 2048, "fio1d", 8, ("sincos", 4), "N"),
+    "radon32": (2, 32, "radon2d", 7, None, "N"),
+    "fio4096_adjoint": (1, 4096, "fio1d", 8, None, "H"),
+    "lowrank2048": (1, 2048, "lowrank", 8, None, "N"),
 }
 MAX_BATCH = 8
 
 
 def _spec(name):
     from paper_1803_04128_amd.serving import PlanSpec
-    dim, n, kind, q, amp = SPECS[name]
+    from synthetic import lowrank_phase
+    dim, n, kind, q, amp, op = SPECS[name]
     ab = None
     if amp:
         ab = amplitude_factors(amp[0], dim, n, amp[1], 11)
         ab = tuple(x.astype(np.complex64).astype(np.complex128) for x in ab)
-    return PlanSpec(dim, n, kind, PHASE_PARAMS[kind], q=q, amplitude=ab)
+    params = (lowrank_phase(dim, n, 4, 13) if kind == "lowrank"
+              else PHASE_PARAMS[kind])
+    return PlanSpec(dim, n, kind, params, q=q, amplitude=ab, op=op)
 
 
 def _requests(count, seed, rate):
@@ -54,7 +60,8 @@ def _alone(reqs):
     for name in SPECS:
         s = _spec(name)
         with bfm.Plan(s.dim, s.n, s.phase, s.params, q=s.q,
-                      amplitude=s.amplitude, max_nvec=MAX_BATCH) as pl:
+                      amplitude=s.amplitude, max_nvec=MAX_BATCH,
+                      op=s.op) as pl:
             for r in reqs:
                 if r.plan == name:
                     ref[r.rid] = pl.apply(r.f).cpu().numpy()
@@ -106,6 +113,16 @@ def test_batched_stream_matches_single_applies(budget_plans):
     f = r.f.cpu().numpy().astype(np.complex128)
     g = butterfly_matvec(1, 2048, "fio1d", PHASE_PARAMS["fio1d"], 8,
                          s.amplitude[0], s.amplitude[1], f)
+    assert np.max(rel(r.out.cpu().numpy().astype(np.complex128), g)) < 1e-5
+    # an adjoint request and a low-rank-phase request against the oracle
+    r = next(x for x in done if x.plan == "fio4096_adjoint")
+    f = r.f.cpu().numpy().astype(np.complex128)
+    g = butterfly_apply(1, 4096, "fio1d", PHASE_PARAMS["fio1d"], 8, f,
+                        transpose=True, conjugate=True)
+    assert np.max(rel(r.out.cpu().numpy().astype(np.complex128), g)) < 1e-5
+    r = next(x for x in done if x.plan == "lowrank2048")
+    f = r.f.cpu().numpy().astype(np.complex128)
+    g = butterfly_apply(1, 2048, "lowrank", _spec("lowrank2048").params, 8, f)
     assert np.max(rel(r.out.cpu().numpy().astype(np.complex128), g)) < 1e-5
 
 
