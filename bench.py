@@ -62,10 +62,11 @@ def traffic_from_profiles(workload, precision, kernel):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, f64, ab, g_gpu):
+def cpu_baseline(w, f64, ab, g_gpu, phase=None, op="N"):
     """The oracle's FP64 butterfly on the first vector (all r amplitude
     columns) of the workload, timed on the host; returns (report, rel err of
-    the GPU result for that vector)."""
+    the GPU result for that vector).  phase: (kind, params) replacing the
+    workload's; op: the operator the plan applies."""
     import numpy as np
     from oracle.butterfly import butterfly_apply, butterfly_matvec
     try:
@@ -74,13 +75,14 @@ def cpu_baseline(w, f64, ab, g_gpu):
                     [1])
     except Exception:
         cores = 1
+    kind, params = phase or (w.phase_kind, w.phase_params)
+    flags = dict(transpose=op in ("T", "H"), conjugate=op in ("C", "H"))
     t0 = time.perf_counter()
     if ab is None:
-        ref = butterfly_apply(w.dim, w.n, w.phase_kind, w.phase_params, w.q,
-                              f64[:1])
+        ref = butterfly_apply(w.dim, w.n, kind, params, w.q, f64[:1], **flags)
     else:
-        ref = butterfly_matvec(w.dim, w.n, w.phase_kind, w.phase_params, w.q,
-                               ab[0], ab[1], f64[:1])
+        ref = butterfly_matvec(w.dim, w.n, kind, params, w.q, ab[0], ab[1],
+                               f64[:1], **flags)
     dt = time.perf_counter() - t0
     err = float(np.linalg.norm(g_gpu[0] - ref[0]) / np.linalg.norm(ref[0]))
     rep = {"value": w.N * 1 / dt, "unit": "N·nvec/s", "cores": int(cores),
@@ -97,9 +99,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fio1d_n262144_batched",
-                    choices=sorted(WORKLOADS) + ["serving"],
+                    choices=sorted(WORKLOADS) + ["serving", "composition"],
                     help="'serving': the continuous-batching server on the "
-                         "mixed request stream (its own JSON line)")
+                         "mixed request stream; 'composition': the chained "
+                         "applies L(L f) (each its own JSON line)")
     ap.add_argument("--requests", type=int, default=2000,
                     help="serving: requests per load level")
     ap.add_argument("--graph", action="store_true",
@@ -111,6 +114,11 @@ def main():
     ap.add_argument("--switch-otf", action="store_true",
                     help="per-step MFMA form with the switch blocks "
                          "generated during the apply")
+    ap.add_argument("--op", default="N", choices=["N", "T", "C", "H"],
+                    help="operator: K, K^T, conj(K) or K^H (bf_plan_op)")
+    ap.add_argument("--lowrank-phase", type=int, default=0, metavar="RANK",
+                    help="replace the workload's phase by a seeded phase "
+                         "given as real low-rank factors of this rank")
     ap.add_argument("--precision", default=None,
                     choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--nvec", type=int, default=None,
@@ -129,6 +137,9 @@ def main():
 
     if args.workload == "serving":
         serve_bench(args)
+        return
+    if args.workload == "composition":
+        composition_bench(args)
         return
 
     import numpy as np
@@ -162,8 +173,12 @@ def main():
         # read at plan construction: the plan then stores no switch blocks
         os.environ["BF_FUSED"] = "0"
         os.environ["BF_SWITCH_OTF"] = "1"
-    plan = bfm.Plan(w.dim, w.n, w.phase_kind, w.phase_params, q=w.q,
-                    amplitude=ab, precision=precision, max_nvec=nvec)
+    phase = (w.phase_kind, w.phase_params)
+    if args.lowrank_phase:
+        from synthetic import lowrank_phase
+        phase = ("lowrank", lowrank_phase(w.dim, w.n, args.lowrank_phase, 21))
+    plan = bfm.Plan(w.dim, w.n, phase[0], phase[1], q=w.q, amplitude=ab,
+                    precision=precision, max_nvec=nvec, op=args.op)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -252,8 +267,10 @@ def main():
                   "fp16x3": "f16x3+f32"}[precision],
         "data": "synthetic",
         "config": {"workload": w.name, "dim": w.dim, "N": w.N, "nvec": nvec,
-                   "r": w.r, "q": w.q, "phase": w.phase,
-                   "precision": precision},
+                   "r": w.r, "q": w.q,
+                   "phase": (f"lowrank(rank {args.lowrank_phase})"
+                             if args.lowrank_phase else w.phase),
+                   "op": args.op, "precision": precision},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99))},
         "plan_s": plan_s,
@@ -268,12 +285,67 @@ def main():
     if not args.no_cpu_baseline:
         g_host = g[:1].cpu().numpy().astype(np.complex128)
         rep, err = cpu_baseline(w, f64.astype(np.complex64).astype(
-            np.complex128), ab, g_host)
+            np.complex128), ab, g_host, phase=phase, op=args.op)
         out["cpu_baseline"] = rep
         out["rel_err_vs_oracle"] = err
     if graph is not None:
         graph.close()
     plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def composition_bench(args):
+    """L(L f) of the composition example (eq. (eq:example4), phase of eq.
+    (eqn:FIOK2)) at the batched benchmark's size: N = 2^18, 64 vectors, q =
+    10, as the chain [L, F, L] (bf_apply_chain), F the Fourier-coefficient
+    plan.  One JSON line with the chain's throughput and per-kernel times."""
+    import numpy as np
+    import torch
+
+    import paper_1803_04128_amd as bfm
+    from synthetic import PHASE_PARAMS, gaussian_vectors
+
+    n, nvec, q = 1 << 18, args.nvec or 64, 10
+    f = torch.from_numpy(gaussian_vectors(n, nvec, 1).astype(
+        np.complex64)).to("cuda")
+    g = torch.empty_like(f)
+    tmp = torch.empty_like(f)
+    t0 = time.perf_counter()
+    L = bfm.Plan(1, n, "fio1d_warp", PHASE_PARAMS["fio1d_warp"], q=q,
+                 max_nvec=nvec)
+    F = bfm.fourier_coefficients_plan(n, q, max_nvec=nvec)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        bfm.apply_chain([L, F, L], f, out=g, tmp=tmp)
+    torch.cuda.synchronize()
+    for pl in (L, F):
+        pl.profile(True)
+        pl.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bfm.apply_chain([L, F, L], f, out=g, tmp=tmp)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = {}
+    for tag, pl in (("L", L), ("F", F)):
+        pl.profile(False)
+        for k, v in pl.profile_read().items():
+            kern[f"{tag}:{k}"] = {"launches": v["launches"],
+                                  "ms_per_launch": v["total_ms"] /
+                                  v["launches"]}
+    out = {"metric": "L(L f) applies: N·nvec/s",
+           "value": n * nvec * args.steps / elapsed, "unit": "N·nvec/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "fio1d_warp_composition", "N": n,
+                      "nvec": nvec, "q": q, "chain": "L, F, L"},
+           "plan_s": plan_s, "kernels": kern}
+    L.close()
+    F.close()
     print(json.dumps(out), flush=True)
 
 
