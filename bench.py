@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--lowrank-phase", type=int, default=0, metavar="RANK",
                     help="replace the workload's phase by a seeded phase "
                          "given as real low-rank factors of this rank")
+    ap.add_argument("--comp-n", type=int, default=1 << 18,
+                    help="composition: grid size N (a power of two)")
     ap.add_argument("--precision", default=None,
                     choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--nvec", type=int, default=None,
@@ -296,16 +298,17 @@ def main():
 
 def composition_bench(args):
     """L(L f) of the composition example (eq. (eq:example4), phase of eq.
-    (eqn:FIOK2)) at the batched benchmark's size: N = 2^18, 64 vectors, q =
-    10, as the chain [L, F, L] (bf_apply_chain), F the Fourier-coefficient
-    plan.  One JSON line with the chain's throughput and per-kernel times."""
+    (eqn:FIOK2)), by default at the batched benchmark's size (N = 2^18, 64
+    vectors, q = 10), as the chain [L, F, L] (bf_apply_chain, or one
+    captured graph with --graph), F the Fourier-coefficient plan.  One JSON
+    line with the chain's throughput and per-kernel times (eager applies)."""
     import numpy as np
     import torch
 
     import paper_1803_04128_amd as bfm
     from synthetic import PHASE_PARAMS, gaussian_vectors
 
-    n, nvec, q = 1 << 18, args.nvec or 64, 10
+    n, nvec, q = args.comp_n, args.nvec or 64, 10
     f = torch.from_numpy(gaussian_vectors(n, nvec, 1).astype(
         np.complex64)).to("cuda")
     g = torch.empty_like(f)
@@ -316,8 +319,16 @@ def composition_bench(args):
     F = bfm.fourier_coefficients_plan(n, q, max_nvec=nvec)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
+    graph = bfm.graph_chain([L, F, L], f, g, tmp) if args.graph else None
+
+    def step():
+        if graph is not None:
+            graph.launch()
+        else:
+            bfm.apply_chain([L, F, L], f, out=g, tmp=tmp)
+
     for _ in range(args.warmup):
-        bfm.apply_chain([L, F, L], f, out=g, tmp=tmp)
+        step()
     torch.cuda.synchronize()
     for pl in (L, F):
         pl.profile(True)
@@ -325,9 +336,11 @@ def composition_bench(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        bfm.apply_chain([L, F, L], f, out=g, tmp=tmp)
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if graph is not None:
+        graph.close()
     kern = {}
     for tag, pl in (("L", L), ("F", F)):
         pl.profile(False)
@@ -342,7 +355,8 @@ def composition_bench(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "fio1d_warp_composition", "N": n,
-                      "nvec": nvec, "q": q, "chain": "L, F, L"},
+                      "nvec": nvec, "q": q, "chain": "L, F, L",
+                      "graph": graph is not None},
            "plan_s": plan_s, "kernels": kern}
     L.close()
     F.close()

@@ -307,6 +307,16 @@ typedef struct bf_graph_s* bf_graph_t;
 
 int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
                     bf_graph_t* out);
+
+/* As bf_graph_create for the chain of bf_apply_chain (same arguments and
+ * checks): the applies of all plans, ping-ponging between tmp and g, in one
+ * graph.  Every plan of the chain holds a reference until bf_graph_destroy
+ * (bf_destroy and bf_set_config return BF_EBUSY meanwhile).  For chains of
+ * small applies whose launches dominate, e.g. a composition of FIOs.     */
+int bf_graph_create_chain(const bf_plan_t* plans, int count, int nvec,
+                          const void* f, void* g, void* tmp,
+                          bf_graph_t* out);
+
 int bf_graph_launch(bf_graph_t graph, void* stream);
 int bf_graph_destroy(bf_graph_t graph);
 

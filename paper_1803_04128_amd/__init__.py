@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
-           "apply_chain", "fourier_coefficients_plan", "unwrap",
+           "apply_chain", "graph_chain", "fourier_coefficients_plan",
+           "unwrap",
            "recover_phase", "kernel_phase_sampler", "lowrank_from_samples",
            "kernel_samples", "recover_kernel"]
 
@@ -228,17 +229,29 @@ class Plan:
 
 
 class Graph:
-    """A captured apply (bf_graph_create): replays K f for the tensors it was
-    built with, in one launch call.  Keep f and out alive while it exists."""
+    """A captured apply (bf_graph_create) or chain (bf_graph_create_chain):
+    replays it for the tensors it was built with, in one launch call.  Keep
+    f, out (and tmp) alive while it exists."""
 
-    def __init__(self, plan, f, out=None):
+    def __init__(self, plan, f, out=None, chain=None, tmp=None):
         self._lib = plan._lib
         self.plan = plan
         self.f, self.out, nvec = plan._args(f, out)
         self._h = C.c_void_p()
-        _lib.check(self._lib.bf_graph_create(
-            plan._h, nvec, C.c_void_p(self.f.data_ptr()),
-            C.c_void_p(self.out.data_ptr()), C.byref(self._h)))
+        if chain is None:
+            _lib.check(self._lib.bf_graph_create(
+                plan._h, nvec, C.c_void_p(self.f.data_ptr()),
+                C.c_void_p(self.out.data_ptr()), C.byref(self._h)))
+            return
+        import torch
+        self.tmp = tmp if tmp is not None or len(chain) == 1 else \
+            torch.empty_like(self.f)
+        arr = (C.c_void_p * len(chain))(*[p._h.value for p in chain])
+        _lib.check(self._lib.bf_graph_create_chain(
+            arr, len(chain), nvec, C.c_void_p(self.f.data_ptr()),
+            C.c_void_p(self.out.data_ptr()),
+            C.c_void_p(self.tmp.data_ptr() if self.tmp is not None
+                       else None), C.byref(self._h)))
 
     def launch(self, stream=None):
         _lib.check(self._lib.bf_graph_launch(self._h,
@@ -286,6 +299,13 @@ def apply_chain(plans, f, out=None, tmp=None, stream=None):
         C.c_void_p(tmp.data_ptr() if tmp is not None else None),
         Plan._stream(stream)))
     return out.reshape(-1) if squeeze else out
+
+
+def graph_chain(plans, f, out=None, tmp=None):
+    """Capture apply_chain(plans, f) into one HIP graph
+    (bf_graph_create_chain); launch() replays it."""
+    plans = list(plans)
+    return Graph(plans[0], f, out, chain=plans, tmp=tmp)
 
 
 def fourier_coefficients_plan(n, q=10, precision="fp32", max_nvec=1):

@@ -63,7 +63,8 @@ class BfTuneEntry(C.Structure):
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
-EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain", "bf_unwrap",
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain",
+           "bf_graph_create_chain", "bf_unwrap",
            "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
            "bf_lagrange", "bf_profile", "bf_profile_read", "bf_get_config",
@@ -116,6 +117,9 @@ def load():
                                        C.c_int, C.c_int, C.c_int,
                                        P(C.c_double), P(C.c_double),
                                        P(C.c_int)]
+    lib.bf_graph_create_chain.argtypes = [P(C.c_void_p), C.c_int, C.c_int,
+                                          C.c_void_p, C.c_void_p, C.c_void_p,
+                                          P(C.c_void_p)]
     lib.bf_apply_chain.argtypes = [P(C.c_void_p), C.c_int, C.c_int,
                                    C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]

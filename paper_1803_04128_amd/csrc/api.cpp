@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "bf_internal.h"
 
@@ -38,7 +39,7 @@ struct bf_plan_s {
 };
 
 struct bf_graph_s {
-    bf_plan_s* plan = nullptr;
+    std::vector<bf_plan_s*> plans;   // each holds one graph reference
     hipGraphExec_t exec = nullptr;
     unsigned magic = 0xbf09bf09u;
 };
@@ -423,34 +424,54 @@ static bool overlap(const void* a, const void* b, size_t bytes) {
     return ab < bb + bytes && bb < ab + bytes;
 }
 
-int bf_apply_chain(const bf_plan_t* plans, int count, int nvec,
-                   const void* f, void* g, void* tmp, void* stream) {
-    if (!plans || count < 1)
-        return fail(BF_EINVAL, "bf_apply_chain: no plans");
+// Arguments of a chain (bf_apply_chain, bf_graph_create_chain).
+static int check_chain(const char* who, const bf_plan_t* plans, int count,
+                       int nvec, const void* f, const void* g,
+                       const void* tmp) {
+    if (!plans || count < 1) return fail(BF_EINVAL, std::string(who) + ": no plans");
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess)
-        return fail(BF_EHIP, "bf_apply_chain: no HIP device");
+        return fail(BF_EHIP, std::string(who) + ": no HIP device");
     long long N = -1;
     for (int k = 0; k < count; ++k) {
         if (int e = check_apply(plans[k], nvec, f, g)) return e;
         const bfi::Plan& p = plans[k]->p;
         if (N >= 0 && p.N != N)
-            return fail(BF_EINVAL, "bf_apply_chain: plans differ in N");
+            return fail(BF_EINVAL, std::string(who) + ": plans differ in N");
         if (p.device != cur)
-            return fail(BF_EINVAL, "bf_apply_chain: plan on another device");
+            return fail(BF_EINVAL, std::string(who) + ": plan on another device");
         N = p.N;
     }
     const size_t bytes = (size_t)nvec * N * 8;
     if (count > 1 && (!tmp || overlap(tmp, f, bytes) || overlap(tmp, g, bytes)))
-        return fail(BF_EINVAL, "bf_apply_chain: tmp NULL or overlapping");
-    // apply k writes g when count - 1 - k is even, tmp otherwise, so the
-    // last one writes g and consecutive applies never read what they write
+        return fail(BF_EINVAL, std::string(who) + ": tmp NULL or overlapping");
+    return BF_OK;
+}
+
+// The chain's applies on stream: apply k writes g when count - 1 - k is
+// even, tmp otherwise, so the last one writes g and consecutive applies
+// never read what they write.
+static std::string launch_chain(const bf_plan_t* plans, int count, int nvec,
+                                const void* f, void* g, void* tmp,
+                                hipStream_t st) {
     const void* in = f;
     for (int k = 0; k < count; ++k) {
         void* out = ((count - 1 - k) % 2 == 0) ? g : tmp;
-        if (int e = bf_apply(plans[k], nvec, in, out, stream)) return e;
+        bfi::Plan& p = plans[k]->p;
+        std::string err = bfi::launch_apply(p, nvec, in, out, p.ws, p.ws_bytes, st);
+        if (!err.empty()) return err;
         in = out;
     }
+    return "";
+}
+
+int bf_apply_chain(const bf_plan_t* plans, int count, int nvec,
+                   const void* f, void* g, void* tmp, void* stream) {
+    if (int e = check_chain("bf_apply_chain", plans, count, nvec, f, g, tmp))
+        return e;
+    std::string err = launch_chain(plans, count, nvec, f, g, tmp,
+                                   (hipStream_t)stream);
+    if (!err.empty()) return fail(BF_EHIP, "bf_apply_chain: " + err);
     return BF_OK;
 }
 
@@ -686,17 +707,13 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
     return apply_config(p, chosen);
 }
 
-int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
-                    bf_graph_t* out) {
-    if (!out) return fail(BF_EINVAL, "bf_graph_create: out is NULL");
-    *out = nullptr;
-    if (int e = check_apply(plan, nvec, f, g)) return e;
-    bfi::Plan& p = plan->p;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
-        return fail(BF_EINVAL, "bf_graph_create: plan belongs to another device");
+// Captures the chain plans[0..count) (one plan: a plain apply) into an
+// executable graph on a private stream.
+static int capture_chain(const char* who, const bf_plan_t* plans, int count,
+                         int nvec, const void* f, void* g, void* tmp,
+                         bf_graph_t* out) {
     bf_graph_s* gr = new (std::nothrow) bf_graph_s();
-    if (!gr) return fail(BF_ENOMEM, "bf_graph_create: host allocation");
+    if (!gr) return fail(BF_ENOMEM, std::string(who) + ": host allocation");
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     std::string err;
@@ -706,9 +723,9 @@ int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
              hipSuccess)
         err = "begin capture";
     else {
-        p.capturing = true;
-        std::string aerr = bfi::launch_apply(p, nvec, f, g, p.ws, p.ws_bytes, cs);
-        p.capturing = false;
+        for (int k = 0; k < count; ++k) plans[k]->p.capturing = true;
+        std::string aerr = launch_chain(plans, count, nvec, f, g, tmp, cs);
+        for (int k = 0; k < count; ++k) plans[k]->p.capturing = false;
         hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (!aerr.empty()) err = aerr;
         else if (ee != hipSuccess || !graph) err = "end capture";
@@ -721,12 +738,38 @@ int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
     if (!err.empty()) {
         (void)hipGetLastError();
         delete gr;
-        return fail(BF_EHIP, "bf_graph_create: " + err);
+        return fail(BF_EHIP, std::string(who) + ": " + err);
     }
-    gr->plan = plan;
-    ++p.graphs;
+    for (int k = 0; k < count; ++k) {
+        gr->plans.push_back(plans[k]);
+        ++plans[k]->p.graphs;
+    }
     *out = gr;
     return BF_OK;
+}
+
+int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
+                    bf_graph_t* out) {
+    if (!out) return fail(BF_EINVAL, "bf_graph_create: out is NULL");
+    *out = nullptr;
+    if (int e = check_apply(plan, nvec, f, g)) return e;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != plan->p.device)
+        return fail(BF_EINVAL, "bf_graph_create: plan belongs to another device");
+    return capture_chain("bf_graph_create", &plan, 1, nvec, f, g, nullptr,
+                         out);
+}
+
+int bf_graph_create_chain(const bf_plan_t* plans, int count, int nvec,
+                          const void* f, void* g, void* tmp,
+                          bf_graph_t* out) {
+    if (!out) return fail(BF_EINVAL, "bf_graph_create_chain: out is NULL");
+    *out = nullptr;
+    if (int e = check_chain("bf_graph_create_chain", plans, count, nvec, f, g,
+                            tmp))
+        return e;
+    return capture_chain("bf_graph_create_chain", plans, count, nvec, f, g,
+                         tmp, out);
 }
 
 int bf_graph_launch(bf_graph_t graph, void* stream) {
@@ -746,7 +789,7 @@ int bf_graph_destroy(bf_graph_t graph) {
     int rc = BF_OK;
     if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
     if (hipGraphExecDestroy(graph->exec) != hipSuccess) rc = BF_EHIP;
-    --graph->plan->p.graphs;
+    for (bf_plan_s* pl : graph->plans) --pl->p.graphs;
     graph->magic = 0;
     delete graph;
     if (rc != BF_OK) return fail(rc, "bf_graph_destroy: HIP error");

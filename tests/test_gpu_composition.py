@@ -149,3 +149,38 @@ def test_composition_constant_shift_full_size():
     err = np.max(rel(g, ref))
     log(f"  rel err {err:.3e}")
     assert err < TOL
+
+
+def test_chain_graph_replays_match_eager():
+    # bf_graph_create_chain: one graph for [L, F, L]; every replay equals the
+    # eager chain bit for bit, with fresh input and other device work in
+    # between; the plans stay locked while the graph exists
+    import torch
+    import paper_1803_04128_amd as bfm
+    n, q, nvec = 4096, 8, 2
+    log("case chain graph")
+    rng = np.random.default_rng(2700)
+    with _warp(n, q, nvec) as L, bfm.fourier_coefficients_plan(
+            n, q, max_nvec=nvec) as F:
+        f = torch.zeros((nvec, n), dtype=torch.complex64, device="cuda")
+        gout = torch.zeros_like(f)
+        gr = bfm.graph_chain([L, F, L], f, gout)
+        try:
+            for rep in range(4):
+                x = (rng.standard_normal((nvec, n)) +
+                     1j * rng.standard_normal((nvec, n))).astype(np.complex64)
+                f.copy_(torch.from_numpy(x).to("cuda"))
+                eager = bfm.apply_chain([L, F, L], f)
+                junk = torch.randn(1 << 18, device="cuda").sum()
+                torch.cuda.synchronize()
+                gr.launch()
+                torch.cuda.synchronize()
+                assert torch.equal(gout, eager), rep
+                assert float(junk) == float(junk)
+            for pl in (L, F):
+                with pytest.raises(bfm.BfError) as ei:
+                    pl.set_config("per_step")
+                assert ei.value.code == bfm._lib.BF_EBUSY
+        finally:
+            gr.close()
+        L.set_config("per_step")          # released
