@@ -121,6 +121,24 @@ def test_separable_phase_exact_at_full_size(dim, n, q):
     assert np.max(rel(g[:, rows], ref)) < TOL
 
 
+@pytest.mark.parametrize("dim,n,q", [(1, 1 << 22, 8), (2, 1 << 11, 4)])
+def test_separable_phase_exact_at_maximum_size(dim, n, q):
+    # the largest grids bf_plan accepts (1D N = 2^22, 2D 2048 x 2048 = 2^22
+    # points): the factorization is exact for a separable phase, so sampled
+    # dense rows bound the FP32 apply at the maximum depth of the trees
+    log(f"case separable_max dim={dim} n={n} q={q}")
+    N = n ** dim
+    f32, f, _ = inputs(dim, n, 2, 710 + dim)
+    with _plan(dim, n, "separable", q, nvec=2) as pl:
+        g, _ = gpu_apply(pl, f32)
+    rows = sample_rows(N, 64, 711)
+    ref = dense_rows(dim, n, "separable", PHASE_PARAMS["separable"], "one", f,
+                     rows)
+    err = np.max(rel(g[:, rows], ref))
+    log(f"  rel err {err:.3e}")
+    assert err < TOL
+
+
 def test_dft_against_fft_full_size():
     n, q = 1 << 16, 10
     log(f"case dft_fft n={n} q={q}")
