@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +18,21 @@ thread_local std::string g_last_error;
 int fail(int code, const std::string& msg) {
     g_last_error = msg;
     return code;
+}
+
+// Runs an entry point's body with no C++ exception crossing the C ABI: a
+// failed host allocation becomes BF_ENOMEM, anything else BF_EINVAL.
+template <class F>
+int guarded(const char* who, F&& body) {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(BF_ENOMEM, std::string(who) + ": host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(BF_EINVAL, std::string(who) + ": " + e.what());
+    } catch (...) {
+        return fail(BF_EINVAL, std::string(who) + ": internal error");
+    }
 }
 
 bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -117,22 +133,26 @@ extern "C" {
 const char* bf_last_error(void) { return g_last_error.c_str(); }
 
 int bf_points(int box_size, int q, int* out, int cap, int* count) {
-    if (box_size < 1 || q < 2 || q > bfi::kMaxQ || !out || !count)
-        return fail(BF_EINVAL, "bf_points: bad argument");
-    int tmp[bfi::kMaxQ];
-    int c = bfi::mock_chebyshev(box_size, q, tmp);
-    if (c > cap) return fail(BF_EINVAL, "bf_points: capacity too small");
-    std::memcpy(out, tmp, sizeof(int) * c);
-    *count = c;
-    return BF_OK;
+    return guarded("bf_points", [&]() -> int {
+        if (box_size < 1 || q < 2 || q > bfi::kMaxQ || !out || !count)
+            return fail(BF_EINVAL, "bf_points: bad argument");
+        int tmp[bfi::kMaxQ];
+        int c = bfi::mock_chebyshev(box_size, q, tmp);
+        if (c > cap) return fail(BF_EINVAL, "bf_points: capacity too small");
+        std::memcpy(out, tmp, sizeof(int) * c);
+        *count = c;
+        return BF_OK;
+    });
 }
 
 int bf_unwrap(const double* u, long long n, double tau, double* v,
               long long* disc, int cap, int* ndisc) {
-    if (!u || !v || !ndisc || n < 3 || !(tau > 0) || (cap > 0 && !disc) ||
-        cap < 0)
-        return fail(BF_EINVAL, "bf_unwrap: bad argument");
-    return bfi::unwrap_vector(u, n, tau, v, disc, cap, ndisc);
+    return guarded("bf_unwrap", [&]() -> int {
+        if (!u || !v || !ndisc || n < 3 || !(tau > 0) || (cap > 0 && !disc) ||
+            cap < 0)
+            return fail(BF_EINVAL, "bf_unwrap: bad argument");
+        return bfi::unwrap_vector(u, n, tau, v, disc, cap, ndisc);
+    });
 }
 
 static bool sorted_unique(const long long* a, int n, long long N) {
@@ -147,52 +167,58 @@ int bf_recover_phase(long long N, const long long* C, int nc,
                      const long long* R, int nr, int rank, double tau,
                      bf_phase_sampler sample, void* ctx, int cap_rank,
                      double* U, double* V, int* rank_out) {
-    if (N < 8 || !C || !R || nc < 1 || nr < 1 || rank < 1 || rank > 64 ||
-        cap_rank < 1 || cap_rank > 64 || !(tau > 0) || !sample || !U ||
-        !V || !rank_out)
-        return fail(BF_EINVAL, "bf_recover_phase: bad argument");
-    if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
-        return fail(BF_EINVAL,
-                    "bf_recover_phase: C and R must be sorted, distinct and "
-                    "in [0, N)");
-    const int rc = bfi::recover_phase(N, C, nc, R, nr, rank, tau, sample,
-                                      ctx, cap_rank, U, V, rank_out);
-    if (rc != BF_OK)
-        return fail(rc, std::string("bf_recover_phase: ") +
-                            bfi::recovery_error());
-    return BF_OK;
+    return guarded("bf_recover_phase", [&]() -> int {
+        if (N < 8 || !C || !R || nc < 1 || nr < 1 || rank < 1 || rank > 64 ||
+            cap_rank < 1 || cap_rank > 64 || !(tau > 0) || !sample || !U ||
+            !V || !rank_out)
+            return fail(BF_EINVAL, "bf_recover_phase: bad argument");
+        if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
+            return fail(BF_EINVAL,
+                        "bf_recover_phase: C and R must be sorted, distinct and "
+                        "in [0, N)");
+        const int rc = bfi::recover_phase(N, C, nc, R, nr, rank, tau, sample,
+                                          ctx, cap_rank, U, V, rank_out);
+        if (rc != BF_OK)
+            return fail(rc, std::string("bf_recover_phase: ") +
+                                bfi::recovery_error());
+        return BF_OK;
+    });
 }
 
 int bf_lowrank_samples(long long N, const double* cols, const long long* C,
                        int nc, const double* rows, const long long* R, int nr,
                        int rank, int cap_rank, double* U, double* V,
                        int* rank_out) {
-    if (N < 1 || !cols || !rows || !C || !R || nc < 1 || nr < 1 ||
-        rank < 1 || rank > 64 || cap_rank < 1 || cap_rank > 64 || !U || !V ||
-        !rank_out)
-        return fail(BF_EINVAL, "bf_lowrank_samples: bad argument");
-    if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
-        return fail(BF_EINVAL,
-                    "bf_lowrank_samples: C and R must be sorted, distinct "
-                    "and in [0, N)");
-    const int rc = bfi::lowrank_fit(N, cols, C, nc, rows, R, nr, rank,
-                                    cap_rank, U, V, rank_out);
-    if (rc != BF_OK)
-        return fail(rc, std::string("bf_lowrank_samples: ") +
-                            bfi::recovery_error());
-    return BF_OK;
+    return guarded("bf_lowrank_samples", [&]() -> int {
+        if (N < 1 || !cols || !rows || !C || !R || nc < 1 || nr < 1 ||
+            rank < 1 || rank > 64 || cap_rank < 1 || cap_rank > 64 || !U || !V ||
+            !rank_out)
+            return fail(BF_EINVAL, "bf_lowrank_samples: bad argument");
+        if (!sorted_unique(C, nc, N) || !sorted_unique(R, nr, N))
+            return fail(BF_EINVAL,
+                        "bf_lowrank_samples: C and R must be sorted, distinct "
+                        "and in [0, N)");
+        const int rc = bfi::lowrank_fit(N, cols, C, nc, rows, R, nr, rank,
+                                        cap_rank, U, V, rank_out);
+        if (rc != BF_OK)
+            return fail(rc, std::string("bf_lowrank_samples: ") +
+                                bfi::recovery_error());
+        return BF_OK;
+    });
 }
 
 int bf_lagrange(const int* nodes, int r, const double* y, int m,
                 double* out) {
-    if (!nodes || !y || !out || r < 1 || m < 0)
-        return fail(BF_EINVAL, "bf_lagrange: bad argument");
-    for (int i = 0; i < r; ++i)
-        for (int j = i + 1; j < r; ++j)
-            if (nodes[i] == nodes[j])
-                return fail(BF_EINVAL, "bf_lagrange: repeated node");
-    bfi::lagrange_1d(nodes, r, y, m, out);
-    return BF_OK;
+    return guarded("bf_lagrange", [&]() -> int {
+        if (!nodes || !y || !out || r < 1 || m < 0)
+            return fail(BF_EINVAL, "bf_lagrange: bad argument");
+        for (int i = 0; i < r; ++i)
+            for (int j = i + 1; j < r; ++j)
+                if (nodes[i] == nodes[j])
+                    return fail(BF_EINVAL, "bf_lagrange: repeated node");
+        bfi::lagrange_1d(nodes, r, y, m, out);
+        return BF_OK;
+    });
 }
 
 static int plan_impl(const bf_grid* grid, const bf_phase* phase,
@@ -362,13 +388,17 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
 int bf_plan(const bf_grid* grid, const bf_phase* phase,
             const bf_amplitude* amp, int q, int precision, int max_nvec,
             bf_plan_t* out) {
-    return plan_impl(grid, phase, amp, q, precision, max_nvec, BF_OP_N, out);
+    return guarded("bf_plan", [&]() -> int {
+        return plan_impl(grid, phase, amp, q, precision, max_nvec, BF_OP_N, out);
+    });
 }
 
 int bf_plan_op(const bf_grid* grid, const bf_phase* phase,
                const bf_amplitude* amp, int q, int precision, int max_nvec,
                int op, bf_plan_t* out) {
-    return plan_impl(grid, phase, amp, q, precision, max_nvec, op, out);
+    return guarded("bf_plan_op", [&]() -> int {
+        return plan_impl(grid, phase, amp, q, precision, max_nvec, op, out);
+    });
 }
 
 static int check_plan(bf_plan_t plan) {
@@ -393,29 +423,35 @@ static int check_apply(bf_plan_t plan, int nvec, const void* f,
 }
 
 int bf_workspace_bytes(bf_plan_t plan, int nvec, size_t* bytes) {
-    if (int e = check_plan(plan)) return e;
-    if (!bytes || nvec < 1) return fail(BF_EINVAL, "bad argument");
-    *bytes = bfi::workspace_bytes(plan->p, nvec);
-    return BF_OK;
+    return guarded("bf_workspace_bytes", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        if (!bytes || nvec < 1) return fail(BF_EINVAL, "bad argument");
+        *bytes = bfi::workspace_bytes(plan->p, nvec);
+        return BF_OK;
+    });
 }
 
 int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
                 size_t ws_bytes, void* stream) {
-    if (int e = check_apply(plan, nvec, f, g)) return e;
-    if (!ws) return fail(BF_EINVAL, "bf_apply_ws: NULL workspace");
-    bfi::Plan& p = plan->p;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
-        return fail(BF_EINVAL, "bf_apply: plan belongs to another device");
-    std::string err = bfi::launch_apply(p, nvec, f, g, ws, ws_bytes,
-                                        (hipStream_t)stream);
-    if (!err.empty()) return fail(BF_EHIP, "bf_apply: " + err);
-    return BF_OK;
+    return guarded("bf_apply_ws", [&]() -> int {
+        if (int e = check_apply(plan, nvec, f, g)) return e;
+        if (!ws) return fail(BF_EINVAL, "bf_apply_ws: NULL workspace");
+        bfi::Plan& p = plan->p;
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+            return fail(BF_EINVAL, "bf_apply: plan belongs to another device");
+        std::string err = bfi::launch_apply(p, nvec, f, g, ws, ws_bytes,
+                                            (hipStream_t)stream);
+        if (!err.empty()) return fail(BF_EHIP, "bf_apply: " + err);
+        return BF_OK;
+    });
 }
 
 int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream) {
-    if (int e = check_plan(plan)) return e;
-    return bf_apply_ws(plan, nvec, f, g, plan->p.ws, plan->p.ws_bytes, stream);
+    return guarded("bf_apply", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        return bf_apply_ws(plan, nvec, f, g, plan->p.ws, plan->p.ws_bytes, stream);
+    });
 }
 
 static bool overlap(const void* a, const void* b, size_t bytes) {
@@ -467,244 +503,260 @@ static std::string launch_chain(const bf_plan_t* plans, int count, int nvec,
 
 int bf_apply_chain(const bf_plan_t* plans, int count, int nvec,
                    const void* f, void* g, void* tmp, void* stream) {
-    if (int e = check_chain("bf_apply_chain", plans, count, nvec, f, g, tmp))
-        return e;
-    std::string err = launch_chain(plans, count, nvec, f, g, tmp,
-                                   (hipStream_t)stream);
-    if (!err.empty()) return fail(BF_EHIP, "bf_apply_chain: " + err);
-    return BF_OK;
+    return guarded("bf_apply_chain", [&]() -> int {
+        if (int e = check_chain("bf_apply_chain", plans, count, nvec, f, g, tmp))
+            return e;
+        std::string err = launch_chain(plans, count, nvec, f, g, tmp,
+                                       (hipStream_t)stream);
+        if (!err.empty()) return fail(BF_EHIP, "bf_apply_chain: " + err);
+        return BF_OK;
+    });
 }
 
 int bf_destroy(bf_plan_t plan) {
-    if (!plan) return BF_OK;
-    if (int e = check_plan(plan)) return e;
-    bfi::Plan& p = plan->p;
-    if (p.graphs > 0)
-        return fail(BF_EBUSY, "bf_destroy: captured graphs still use the plan");
-    int rc = BF_OK;
-    if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
-    if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
-    if (p.S_arena && hipFree(p.S_arena) != hipSuccess) rc = BF_EHIP;
-    if (p.phase_arena && hipFree(p.phase_arena) != hipSuccess) rc = BF_EHIP;
-    if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
-    for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
-    plan->magic = 0;
-    delete plan;
-    if (rc != BF_OK) return fail(rc, "bf_destroy: HIP error while freeing");
-    return BF_OK;
+    return guarded("bf_destroy", [&]() -> int {
+        if (!plan) return BF_OK;
+        if (int e = check_plan(plan)) return e;
+        bfi::Plan& p = plan->p;
+        if (p.graphs > 0)
+            return fail(BF_EBUSY, "bf_destroy: captured graphs still use the plan");
+        int rc = BF_OK;
+        if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
+        if (p.arena && hipFree(p.arena) != hipSuccess) rc = BF_EHIP;
+        if (p.S_arena && hipFree(p.S_arena) != hipSuccess) rc = BF_EHIP;
+        if (p.phase_arena && hipFree(p.phase_arena) != hipSuccess) rc = BF_EHIP;
+        if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
+        for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
+        plan->magic = 0;
+        delete plan;
+        if (rc != BF_OK) return fail(rc, "bf_destroy: HIP error while freeing");
+        return BF_OK;
+    });
 }
 
 int bf_profile(bf_plan_t plan, int enable) {
-    if (int e = check_plan(plan)) return e;
-    bfi::Profiler& pr = plan->p.prof;
-    if (enable && pr.pool.empty()) {
-        const int cap = 8192;
-        pr.pool.resize(cap);
-        for (int i = 0; i < cap; ++i) {
-            if (hipEventCreate(&pr.pool[i]) != hipSuccess) {
-                for (int j = 0; j < i; ++j) (void)hipEventDestroy(pr.pool[j]);
-                pr.pool.clear();
-                return fail(BF_EHIP, "bf_profile: hipEventCreate failed");
+    return guarded("bf_profile", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        bfi::Profiler& pr = plan->p.prof;
+        if (enable && pr.pool.empty()) {
+            const int cap = 8192;
+            pr.pool.resize(cap);
+            for (int i = 0; i < cap; ++i) {
+                if (hipEventCreate(&pr.pool[i]) != hipSuccess) {
+                    for (int j = 0; j < i; ++j) (void)hipEventDestroy(pr.pool[j]);
+                    pr.pool.clear();
+                    return fail(BF_EHIP, "bf_profile: hipEventCreate failed");
+                }
             }
         }
-    }
-    pr.on = enable != 0;
-    return BF_OK;
+        pr.on = enable != 0;
+        return BF_OK;
+    });
 }
 
 int bf_profile_read(bf_plan_t plan, bf_kernel_stat* stats, int cap,
                     int* count) {
-    if (int e = check_plan(plan)) return e;
-    if (!count || (cap > 0 && !stats))
-        return fail(BF_EINVAL, "bf_profile_read: bad argument");
-    bfi::Profiler& pr = plan->p.prof;
-    std::vector<bf_kernel_stat> acc(pr.names.size());
-    for (size_t i = 0; i < pr.names.size(); ++i) {
-        std::memset(&acc[i], 0, sizeof(bf_kernel_stat));
-        std::snprintf(acc[i].name, sizeof(acc[i].name), "%s",
-                      pr.names[i].c_str());
-    }
-    for (const auto& r : pr.recs) {
-        float ms = 0.f;
-        if (hipEventSynchronize(pr.pool[r.ev1]) != hipSuccess ||
-            hipEventElapsedTime(&ms, pr.pool[r.ev0], pr.pool[r.ev1]) !=
-                hipSuccess)
-            return fail(BF_EHIP, "bf_profile_read: event query failed");
-        bf_kernel_stat& k = acc[r.cls];
-        k.launches += 1;
-        k.total_ms += ms;
-        k.bytes += r.bytes;
-        k.flops += r.flops;
-    }
-    int n = 0;
-    for (const auto& k : acc) {
-        if (k.launches == 0) continue;
-        if (n < cap) stats[n] = k;
-        ++n;
-    }
-    *count = n;
-    pr.recs.clear();
-    pr.used = 0;
-    return BF_OK;
+    return guarded("bf_profile_read", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        if (!count || (cap > 0 && !stats))
+            return fail(BF_EINVAL, "bf_profile_read: bad argument");
+        bfi::Profiler& pr = plan->p.prof;
+        std::vector<bf_kernel_stat> acc(pr.names.size());
+        for (size_t i = 0; i < pr.names.size(); ++i) {
+            std::memset(&acc[i], 0, sizeof(bf_kernel_stat));
+            std::snprintf(acc[i].name, sizeof(acc[i].name), "%s",
+                          pr.names[i].c_str());
+        }
+        for (const auto& r : pr.recs) {
+            float ms = 0.f;
+            if (hipEventSynchronize(pr.pool[r.ev1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, pr.pool[r.ev0], pr.pool[r.ev1]) !=
+                    hipSuccess)
+                return fail(BF_EHIP, "bf_profile_read: event query failed");
+            bf_kernel_stat& k = acc[r.cls];
+            k.launches += 1;
+            k.total_ms += ms;
+            k.bytes += r.bytes;
+            k.flops += r.flops;
+        }
+        int n = 0;
+        for (const auto& k : acc) {
+            if (k.launches == 0) continue;
+            if (n < cap) stats[n] = k;
+            ++n;
+        }
+        *count = n;
+        pr.recs.clear();
+        pr.used = 0;
+        return BF_OK;
+    });
 }
 
 int bf_query(bf_plan_t plan, bf_plan_info* info) {
-    if (int e = check_plan(plan)) return e;
-    if (!info) return fail(BF_EINVAL, "bf_query: NULL info");
-    const bfi::Plan& p = plan->p;
-    std::memset(info, 0, sizeof(*info));
-    info->dim = p.dim;
-    info->n = p.n;
-    info->L = p.L;
-    info->h = p.h;
-    info->q = p.q;
-    info->r = p.r_amp;
-    info->op = p.op;
-    info->precision = p.precision;
-    info->N = p.N;
-    info->first_xi_level = p.l0;
-    info->last_x_level = p.l1;
-    info->n_steps = (int)p.steps.size();
-    info->n_passes = p.fused ? bfi::fused_pass_count(p, p.chunk_nvec * p.r_amp)
-                             : (int)p.steps.size() + 1;
-    info->max_rank = p.max_rank;
-    info->chunk_nvec = p.chunk_nvec;
-    info->factor_bytes = p.arena_bytes + p.S_bytes +
-                         (p.phase_arena ? 2 * (size_t)p.phase.rank * p.N * 8
-                                        : 0);
-    info->workspace_bytes = p.ws_bytes;
-    info->flops_per_column = p.flops_per_column;
-    info->factor_stream_bytes = p.factor_stream_bytes;
-    return BF_OK;
+    return guarded("bf_query", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        if (!info) return fail(BF_EINVAL, "bf_query: NULL info");
+        const bfi::Plan& p = plan->p;
+        std::memset(info, 0, sizeof(*info));
+        info->dim = p.dim;
+        info->n = p.n;
+        info->L = p.L;
+        info->h = p.h;
+        info->q = p.q;
+        info->r = p.r_amp;
+        info->op = p.op;
+        info->precision = p.precision;
+        info->N = p.N;
+        info->first_xi_level = p.l0;
+        info->last_x_level = p.l1;
+        info->n_steps = (int)p.steps.size();
+        info->n_passes = p.fused ? bfi::fused_pass_count(p, p.chunk_nvec * p.r_amp)
+                                 : (int)p.steps.size() + 1;
+        info->max_rank = p.max_rank;
+        info->chunk_nvec = p.chunk_nvec;
+        info->factor_bytes = p.arena_bytes + p.S_bytes +
+                             (p.phase_arena ? 2 * (size_t)p.phase.rank * p.N * 8
+                                            : 0);
+        info->workspace_bytes = p.ws_bytes;
+        info->flops_per_column = p.flops_per_column;
+        info->factor_stream_bytes = p.factor_stream_bytes;
+        return BF_OK;
+    });
 }
 
 int bf_get_config(bf_plan_t plan, bf_config* cfg) {
-    if (int e = check_plan(plan)) return e;
-    if (!cfg) return fail(BF_EINVAL, "bf_get_config: NULL cfg");
-    const bfi::Plan& p = plan->p;
-    cfg->path = path_of(p);
-    cfg->tile_cols = p.tile_cols;
-    cfg->tile_cols_used =
-        p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
-    cfg->switch_otf = p.switch_otf ? 1 : 0;
-    return BF_OK;
+    return guarded("bf_get_config", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        if (!cfg) return fail(BF_EINVAL, "bf_get_config: NULL cfg");
+        const bfi::Plan& p = plan->p;
+        cfg->path = path_of(p);
+        cfg->tile_cols = p.tile_cols;
+        cfg->tile_cols_used =
+            p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
+        cfg->switch_otf = p.switch_otf ? 1 : 0;
+        return BF_OK;
+    });
 }
 
 int bf_set_config(bf_plan_t plan, const bf_config* cfg) {
-    if (int e = check_plan(plan)) return e;
-    if (!cfg) return fail(BF_EINVAL, "bf_set_config: NULL cfg");
-    if (plan->p.graphs > 0)
-        return fail(BF_EBUSY, "bf_set_config: captured graphs use the plan");
-    return apply_config(plan->p, *cfg);
+    return guarded("bf_set_config", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        if (!cfg) return fail(BF_EINVAL, "bf_set_config: NULL cfg");
+        if (plan->p.graphs > 0)
+            return fail(BF_EBUSY, "bf_set_config: captured graphs use the plan");
+        return apply_config(plan->p, *cfg);
+    });
 }
 
 int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
                 void* stream, bf_tune_entry* out, int cap, int* count) {
-    if (int e = check_apply(plan, nvec, f, g)) return e;
-    if (reps < 1 || !count || (cap > 0 && !out))
-        return fail(BF_EINVAL, "bf_autotune: bad argument");
-    bfi::Plan& p = plan->p;
-    if (p.graphs > 0)
-        return fail(BF_EBUSY, "bf_autotune: captured graphs use the plan");
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
-        return fail(BF_EINVAL, "bf_autotune: plan belongs to another device");
-    hipStream_t st = (hipStream_t)stream;
-    // candidates: both fused forms at tile widths r * 2^j <= 16, and the
-    // per-step launches; forms that resolve to the same kernels are timed once
-    std::vector<bf_config> cand;
-    for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
-        for (int tc = p.r_amp; tc <= 16; tc *= 2)
-            cand.push_back({path, tc, 0, 0});
-    cand.push_back({BF_PATH_PER_STEP, 0, 0, 0});
-    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0});
-    cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1});
-    // the stored switch blocks are read by every candidate but one
-    if (!p.S_arena && !bfi::build_switch_blocks(p).empty()) {
-        (void)hipGetLastError();
-        return fail(BF_ENOMEM, "bf_autotune: switch block storage");
-    }
-    const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
-    const int t0 = p.tile_cols;
-    std::vector<bf_tune_entry> res;
-    std::vector<std::pair<int, int>> seen;   // (path, tile width) timed
-    size_t ws_need = 0;
-    for (auto& c : cand) {
-        put_path(p, c.path, c.tile_cols, c.switch_otf);
-        bf_tune_entry e{};
-        e.config = c;
-        e.ms = -1.0;
-        if (bfi::check_config(p).empty()) {
-            e.config.tile_cols_used =
-                p.fused ? bfi::fused_tile_cols(p, std::min(nvec, p.chunk_nvec) *
-                                                      p.r_amp)
-                        : 0;
-            // 2D plans (and r not a power of two) have no MFMA passes: the
-            // fused form is then the vector-ALU one
-            const bool mf = p.fused && p.mfma && p.dim == 1 &&
-                            (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
-            const int key = !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) : 2)
-                                     : (mf ? 0 : 1);
-            std::pair<int, int> k{key, e.config.tile_cols_used};
-            bool dup = false;
-            for (auto& s2 : seen) dup |= s2 == k;
-            if (!dup) {
-                seen.push_back(k);
-                e.ms = 0.0;   // to be timed
-                ws_need = std::max(ws_need, bfi::workspace_bytes(p, nvec));
-            } else {
-                e.ms = -2.0;
-            }
+    return guarded("bf_autotune", [&]() -> int {
+        if (int e = check_apply(plan, nvec, f, g)) return e;
+        if (reps < 1 || !count || (cap > 0 && !out))
+            return fail(BF_EINVAL, "bf_autotune: bad argument");
+        bfi::Plan& p = plan->p;
+        if (p.graphs > 0)
+            return fail(BF_EBUSY, "bf_autotune: captured graphs use the plan");
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+            return fail(BF_EINVAL, "bf_autotune: plan belongs to another device");
+        hipStream_t st = (hipStream_t)stream;
+        // candidates: both fused forms at tile widths r * 2^j <= 16, and the
+        // per-step launches; forms that resolve to the same kernels are timed once
+        std::vector<bf_config> cand;
+        for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
+            for (int tc = p.r_amp; tc <= 16; tc *= 2)
+                cand.push_back({path, tc, 0, 0});
+        cand.push_back({BF_PATH_PER_STEP, 0, 0, 0});
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0});
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1});
+        // the stored switch blocks are read by every candidate but one
+        if (!p.S_arena && !bfi::build_switch_blocks(p).empty()) {
+            (void)hipGetLastError();
+            return fail(BF_ENOMEM, "bf_autotune: switch block storage");
         }
-        res.push_back(e);
-    }
-    void* ws = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::string err;
-    if (hipMalloc(&ws, std::max<size_t>(ws_need, 256)) != hipSuccess)
-        err = "workspace allocation";
-    if (err.empty() && (hipEventCreate(&e0) != hipSuccess ||
-                        hipEventCreate(&e1) != hipSuccess))
-        err = "event creation";
-    const bool prof0 = p.prof.on;
-    p.prof.on = false;
-    int best = -1;
-    for (size_t i = 0; i < res.size() && err.empty(); ++i) {
-        if (res[i].ms != 0.0) continue;
-        put_path(p, res[i].config.path, res[i].config.tile_cols,
-                 res[i].config.switch_otf);
-        err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);   // warm-up
-        if (!err.empty()) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { err = "event record"; break; }
-        for (int k = 0; k < reps && err.empty(); ++k)
-            err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);
-        float ms = 0.f;
-        if (err.empty() && (hipEventRecord(e1, st) != hipSuccess ||
-                            hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            err = "event timing";
-        if (!err.empty()) break;
-        res[i].ms = ms / reps;
-        if (best < 0 || res[i].ms < res[best].ms) best = (int)i;
-    }
-    p.prof.on = prof0;
-    if (ws) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(ws);
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
-    if (!err.empty()) {
-        (void)hipGetLastError();
-        return fail(BF_EHIP, "bf_autotune: " + err);
-    }
-    *count = (int)res.size();
-    for (int i = 0; i < (int)res.size() && i < cap; ++i) out[i] = res[i];
-    if (best < 0) return fail(BF_EUNSUPPORTED, "bf_autotune: no candidate ran");
-    bf_config chosen = res[best].config;
-    chosen.tile_cols_used = 0;
-    return apply_config(p, chosen);
+        const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
+        const int t0 = p.tile_cols;
+        std::vector<bf_tune_entry> res;
+        std::vector<std::pair<int, int>> seen;   // (path, tile width) timed
+        size_t ws_need = 0;
+        for (auto& c : cand) {
+            put_path(p, c.path, c.tile_cols, c.switch_otf);
+            bf_tune_entry e{};
+            e.config = c;
+            e.ms = -1.0;
+            if (bfi::check_config(p).empty()) {
+                e.config.tile_cols_used =
+                    p.fused ? bfi::fused_tile_cols(p, std::min(nvec, p.chunk_nvec) *
+                                                          p.r_amp)
+                            : 0;
+                // 2D plans (and r not a power of two) have no MFMA passes: the
+                // fused form is then the vector-ALU one
+                const bool mf = p.fused && p.mfma && p.dim == 1 &&
+                                (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
+                const int key = !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) : 2)
+                                         : (mf ? 0 : 1);
+                std::pair<int, int> k{key, e.config.tile_cols_used};
+                bool dup = false;
+                for (auto& s2 : seen) dup |= s2 == k;
+                if (!dup) {
+                    seen.push_back(k);
+                    e.ms = 0.0;   // to be timed
+                    ws_need = std::max(ws_need, bfi::workspace_bytes(p, nvec));
+                } else {
+                    e.ms = -2.0;
+                }
+            }
+            res.push_back(e);
+        }
+        void* ws = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        std::string err;
+        if (hipMalloc(&ws, std::max<size_t>(ws_need, 256)) != hipSuccess)
+            err = "workspace allocation";
+        if (err.empty() && (hipEventCreate(&e0) != hipSuccess ||
+                            hipEventCreate(&e1) != hipSuccess))
+            err = "event creation";
+        const bool prof0 = p.prof.on;
+        p.prof.on = false;
+        int best = -1;
+        for (size_t i = 0; i < res.size() && err.empty(); ++i) {
+            if (res[i].ms != 0.0) continue;
+            put_path(p, res[i].config.path, res[i].config.tile_cols,
+                     res[i].config.switch_otf);
+            err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);   // warm-up
+            if (!err.empty()) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { err = "event record"; break; }
+            for (int k = 0; k < reps && err.empty(); ++k)
+                err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);
+            float ms = 0.f;
+            if (err.empty() && (hipEventRecord(e1, st) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                err = "event timing";
+            if (!err.empty()) break;
+            res[i].ms = ms / reps;
+            if (best < 0 || res[i].ms < res[best].ms) best = (int)i;
+        }
+        p.prof.on = prof0;
+        if (ws) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(ws);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
+        if (!err.empty()) {
+            (void)hipGetLastError();
+            return fail(BF_EHIP, "bf_autotune: " + err);
+        }
+        *count = (int)res.size();
+        for (int i = 0; i < (int)res.size() && i < cap; ++i) out[i] = res[i];
+        if (best < 0) return fail(BF_EUNSUPPORTED, "bf_autotune: no candidate ran");
+        bf_config chosen = res[best].config;
+        chosen.tile_cols_used = 0;
+        return apply_config(p, chosen);
+    });
 }
 
 // Captures the chain plans[0..count) (one plan: a plain apply) into an
@@ -750,50 +802,58 @@ static int capture_chain(const char* who, const bf_plan_t* plans, int count,
 
 int bf_graph_create(bf_plan_t plan, int nvec, const void* f, void* g,
                     bf_graph_t* out) {
-    if (!out) return fail(BF_EINVAL, "bf_graph_create: out is NULL");
-    *out = nullptr;
-    if (int e = check_apply(plan, nvec, f, g)) return e;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != plan->p.device)
-        return fail(BF_EINVAL, "bf_graph_create: plan belongs to another device");
-    return capture_chain("bf_graph_create", &plan, 1, nvec, f, g, nullptr,
-                         out);
+    return guarded("bf_graph_create", [&]() -> int {
+        if (!out) return fail(BF_EINVAL, "bf_graph_create: out is NULL");
+        *out = nullptr;
+        if (int e = check_apply(plan, nvec, f, g)) return e;
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != plan->p.device)
+            return fail(BF_EINVAL, "bf_graph_create: plan belongs to another device");
+        return capture_chain("bf_graph_create", &plan, 1, nvec, f, g, nullptr,
+                             out);
+    });
 }
 
 int bf_graph_create_chain(const bf_plan_t* plans, int count, int nvec,
                           const void* f, void* g, void* tmp,
                           bf_graph_t* out) {
-    if (!out) return fail(BF_EINVAL, "bf_graph_create_chain: out is NULL");
-    *out = nullptr;
-    if (int e = check_chain("bf_graph_create_chain", plans, count, nvec, f, g,
-                            tmp))
-        return e;
-    return capture_chain("bf_graph_create_chain", plans, count, nvec, f, g,
-                         tmp, out);
+    return guarded("bf_graph_create_chain", [&]() -> int {
+        if (!out) return fail(BF_EINVAL, "bf_graph_create_chain: out is NULL");
+        *out = nullptr;
+        if (int e = check_chain("bf_graph_create_chain", plans, count, nvec, f, g,
+                                tmp))
+            return e;
+        return capture_chain("bf_graph_create_chain", plans, count, nvec, f, g,
+                             tmp, out);
+    });
 }
 
 int bf_graph_launch(bf_graph_t graph, void* stream) {
-    if (!graph || graph->magic != 0xbf09bf09u)
-        return fail(BF_EINVAL, "invalid graph handle");
-    if (hipGraphLaunch(graph->exec, (hipStream_t)stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(BF_EHIP, "bf_graph_launch: hipGraphLaunch failed");
-    }
-    return BF_OK;
+    return guarded("bf_graph_launch", [&]() -> int {
+        if (!graph || graph->magic != 0xbf09bf09u)
+            return fail(BF_EINVAL, "invalid graph handle");
+        if (hipGraphLaunch(graph->exec, (hipStream_t)stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BF_EHIP, "bf_graph_launch: hipGraphLaunch failed");
+        }
+        return BF_OK;
+    });
 }
 
 int bf_graph_destroy(bf_graph_t graph) {
-    if (!graph) return BF_OK;
-    if (graph->magic != 0xbf09bf09u)
-        return fail(BF_EINVAL, "invalid graph handle");
-    int rc = BF_OK;
-    if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
-    if (hipGraphExecDestroy(graph->exec) != hipSuccess) rc = BF_EHIP;
-    for (bf_plan_s* pl : graph->plans) --pl->p.graphs;
-    graph->magic = 0;
-    delete graph;
-    if (rc != BF_OK) return fail(rc, "bf_graph_destroy: HIP error");
-    return BF_OK;
+    return guarded("bf_graph_destroy", [&]() -> int {
+        if (!graph) return BF_OK;
+        if (graph->magic != 0xbf09bf09u)
+            return fail(BF_EINVAL, "invalid graph handle");
+        int rc = BF_OK;
+        if (hipDeviceSynchronize() != hipSuccess) rc = BF_EHIP;
+        if (hipGraphExecDestroy(graph->exec) != hipSuccess) rc = BF_EHIP;
+        for (bf_plan_s* pl : graph->plans) --pl->p.graphs;
+        graph->magic = 0;
+        delete graph;
+        if (rc != BF_OK) return fail(rc, "bf_graph_destroy: HIP error");
+        return BF_OK;
+    });
 }
 
 }  // extern "C"

@@ -136,3 +136,23 @@ def test_lowrank_samples_argument_errors():
     with pytest.raises(ValueError):
         bfm.lowrank_from_samples(16, A[:, [1, 3]], [1, 3, 5], A[[1, 2], :],
                                  [1, 2])
+
+
+def test_host_exceptions_do_not_cross_the_abi():
+    # a length the host vectors cannot hold (std::length_error, thrown
+    # before anything is allocated) comes back as an error code
+    import ctypes as C
+    from paper_1803_04128_amd import _lib
+    lib = _lib.load()
+    N = 1 << 62
+    idx = (C.c_longlong * 3)(0, 1, 2)
+    U = (C.c_double * 1)()
+    k = C.c_int()
+
+    def sampler(ctx, is_row, count, ids, out):
+        return 1
+    cb = _lib.SAMPLER(sampler)
+    rc = lib.bf_recover_phase(N, idx, 3, idx, 3, 4, 1.5, cb, None, 4, U, U,
+                              C.byref(k))
+    assert rc == _lib.BF_EINVAL
+    assert b"bf_recover_phase" in lib.bf_last_error()
