@@ -1008,9 +1008,17 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st) {
     set_attrs<VT, PREC>();
     const long long nblocks = a.nspatial * a.nchunk;
+    // A xi pass whose LDS fits twice in a CU runs as workgroups of 512
+    // threads when the grid still has two of them per CU (256 CUs): the
+    // same 16 waves per CU, in two groups with their own barriers, so one
+    // group's reads of the next level's factors overlap the other's MFMA
+    // work (with few columns per group the pass mostly waits on them).
+    // The x pass keeps 1024: its tail accumulators assume 16 waves.
+    const int xt = (2 * lds <= 160 * 1024 && nblocks >= 512)
+                       ? kMfmaThreads / 2 : kMfmaThreads;
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(kMfmaThreads), lds, st, a);
+                           dim3(xt), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
                            dim3(kMfmaThreads), lds, st, a);

@@ -9,6 +9,8 @@ oracle values `tests/golden/make_fullsize.py` computed with oracle/ alone:
 * vector 0 and the last vector against the dense FP64 matvec at those rows:
   relative l2 <= eps_BF + 1e-5, eps_BF the oracle butterfly's own error
   there (vector 0);
+* the batched workload's plan built for a single vector, vector 0 against
+  the same butterfly rows (<= 1e-5);
 * the split precisions at the precision-sweep size (N = 2^20, 256 vectors)
   against the stored butterfly rows: BF16x3 <= 1e-4, FP16x3 <= 1e-5."""
 
@@ -38,17 +40,18 @@ def _unpack(pairs):
     return a[:, 0] + 1j * a[:, 1]
 
 
-def _gpu_rows(name, precision, rows, picks):
+def _gpu_rows(name, precision, rows, picks, nvec=None):
     import torch
     import paper_1803_04128_amd as bfm
     w = CONFIGS[name]
-    f32 = gaussian_vectors(w.N, w.nvec, w.seed).astype(np.complex64)
+    nvec = nvec or w.nvec
+    f32 = gaussian_vectors(w.N, w.nvec, w.seed).astype(np.complex64)[:nvec]
     ab = None
     if w.amplitude != "one":
         ab = amplitude_factors(w.amplitude, w.dim, w.n, w.r, w.amp_seed)
         ab = tuple(x.astype(np.complex64).astype(np.complex128) for x in ab)
     with bfm.Plan(w.dim, w.n, w.phase_kind, w.phase_params, q=w.q,
-                  amplitude=ab, precision=precision, max_nvec=w.nvec) as pl:
+                  amplitude=ab, precision=precision, max_nvec=nvec) as pl:
         f = torch.from_numpy(f32).to("cuda")
         del f32
         g = pl.apply(f)
@@ -90,3 +93,16 @@ def test_split_precision_at_sweep_size(precision, tol):
     e = rel(g[0], _unpack(ref["bf"]["0"]))[0]
     log(f"  {precision} vs oracle butterfly (vector 0) {e:.3e}")
     assert e < tol
+
+
+def test_single_vector_at_full_size():
+    # the batched workload's plan built for one vector (four amplitude
+    # columns): a narrower tile and smaller xi workgroups than the batch
+    name = "fio1d_n262144_batched"
+    ref = _golden()[name]
+    rows = np.asarray(ref["rows"], np.int64)
+    log(f"case full size {name}, one vector")
+    g = _gpu_rows(name, "fp32", rows, [0], nvec=1)
+    e = rel(g[0], _unpack(ref["bf"]["0"]))[0]
+    log(f"  vector 0 alone: GPU vs oracle butterfly {e:.3e}")
+    assert e < TOL
