@@ -1003,25 +1003,34 @@ void init_mfma_attrs() {
     set_attrs_prec<BF_FP16X3>();
 }
 
+// Threads of an MFMA pass workgroup.  A pass whose LDS fits twice in a CU
+// runs as workgroups of 512 threads when the grid still has two of them per
+// CU (256 CUs): the same 16 waves per CU, in two groups with their own
+// barriers, so one group's reads of the next level's factors overlap the
+// other's MFMA work (with few columns per group a level mostly waits on
+// them).  The xi pass loops over its tiles with any number of waves; the x
+// pass gives each wave at most one tile per level, which 8 waves cover only
+// for groups of at most half the largest tile (Gk Vt <= 256).
+static int pass_threads(const PassArgs& a, bool is_xi, int vt, size_t lds,
+                        long long nblocks) {
+    const bool two = 2 * lds <= 160 * 1024 && nblocks >= 512;
+    const bool covered =
+        is_xi || (long long)a.Gk * vt <= (long long)kMfmaTileCap * 8 / 2;
+    return two && covered ? kMfmaThreads / 2 : kMfmaThreads;
+}
+
 template <int VT, int PREC>
 static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
                              hipStream_t st) {
     set_attrs<VT, PREC>();
     const long long nblocks = a.nspatial * a.nchunk;
-    // A xi pass whose LDS fits twice in a CU runs as workgroups of 512
-    // threads when the grid still has two of them per CU (256 CUs): the
-    // same 16 waves per CU, in two groups with their own barriers, so one
-    // group's reads of the next level's factors overlap the other's MFMA
-    // work (with few columns per group the pass mostly waits on them).
-    // The x pass keeps 1024: its tail accumulators assume 16 waves.
-    const int xt = (2 * lds <= 160 * 1024 && nblocks >= 512)
-                       ? kMfmaThreads / 2 : kMfmaThreads;
+    const int threads = pass_threads(a, is_xi, VT, lds, nblocks);
     if (is_xi)
         hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(xt), lds, st, a);
+                           dim3(threads), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(kMfmaThreads), lds, st, a);
+                           dim3(threads), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("MFMA pass launch: ") + hipGetErrorString(e);
