@@ -1,5 +1,6 @@
 // C ABI entry points (include/bf.h): argument checks, plan construction,
 // workspace, apply, query, destroy and error reporting.
+#include <mutex>
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -338,7 +339,12 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
         }
         p.fused = false;
     }
-    bfi::init_kernel_attrs();
+    {
+        // once per process: plans built on several host threads at once do
+        // not race on the kernels' attribute flags (launches only read them)
+        static std::once_flag attrs_once;
+        std::call_once(attrs_once, [] { bfi::init_kernel_attrs(); });
+    }
     if (phase->kind == BF_PHASE_LOWRANK) {
         const size_t fb = (size_t)p.N * phase->rank * sizeof(double);
         if (hipMalloc(&p.phase_arena, 2 * fb) != hipSuccess) {
