@@ -687,6 +687,19 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         if (p.precision != BF_FP32 && !use_mfma)
             return "split precision needs the 1D MFMA passes (power-of-two "
                    "tile width, r in {1, 2, 4, 8}, a level in every pass)";
+        // a head xi pass whose own f tile keeps it at one workgroup per CU
+        // gathers the head into the state tile at every sub-iteration when
+        // that lets two workgroups share a CU (then of 512 threads each):
+        // the gather is repeated per sub-iteration, from L2, but the two
+        // groups overlap each other's factor reads and barriers
+        a.head_inplace = 0;
+        if (use_mfma && is_xi && a.has_head && a.head_r <= a.rmax) {
+            const size_t keep = mfma_pass_lds(a, true);
+            a.head_inplace = 1;
+            const size_t in = mfma_pass_lds(a, true);
+            a.head_inplace = (2 * keep > 160 * 1024 && 2 * in <= 160 * 1024 &&
+                              nblocks >= 512) ? 1 : 0;
+        }
         if (use_mfma) {
             lds = mfma_pass_lds(a, is_xi);
             if (lds > 160 * 1024) return "MFMA pass does not fit in LDS";

@@ -752,7 +752,9 @@ __device__ __forceinline__ void zero_pass_lds(float2* lds, int n_front,
 // place: a unit reads its two slots and writes the same two slots, and all
 // of a unit's columns sit in one wave, so no other wave touches them within
 // the level.
-template <int VT, int PREC>
+//
+// HIN (a.head_inplace): the head is gathered into T at every sub-iteration.
+template <int VT, int PREC, bool HIN>
 __global__ void __launch_bounds__((kMfmaThreads))
 xi_pass_mfma(PassArgs a) {
     extern __shared__ float2 lds[];
@@ -764,13 +766,17 @@ xi_pass_mfma(PassArgs a) {
     float2* const W0 = lds + tsz;
     float2* const W1 = lds + tsz + wsz;
     float2* const ftile = lds + tsz + 2 * wsz;
+    // the head in a tile of its own (kept for all sub-iterations), or
+    // gathered into T at the tile's slot stride for each sub-iteration, so
+    // that level 1 runs in place like the others
+    const bool fsep = !HIN && a.has_head;
     long long spatial;
     int chunk;
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
     // zeroed pad after the tiles: reads past a level's rank land here, and
     // stores of rows past r_out and of padding columns go here (finite)
-    float2* const pad = a.has_head ? ftile + a.Gk * a.head_r * VT : ftile;
+    float2* const pad = fsep ? ftile + a.Gk * a.head_r * VT : ftile;
     zero_pass_lds(lds, tsz + 2 * wsz, pad);
     const int part = (int)(spatial % a.sub_split);
     spatial /= a.sub_split;
@@ -778,13 +784,15 @@ xi_pass_mfma(PassArgs a) {
     const long long ap_base = spatial / a.nbg;
     // the f tile is shared by the sub-iterations of the workgroup (the T_X
     // boxes at level l0 - 1 all see the same input)
-    if (a.has_head) load_head(a, ftile, bg * a.Gk, chunk);
+    if (fsep) load_head(a, ftile, bg * a.Gk, chunk);
     for (int si = 0; si < a.n_sub; ++si) {
         const int sub = part * a.n_sub + si;
         const long long ap_grp = a.has_head ? sub : ap_base;
         if (!a.has_head) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
             load_tile(a, T, p0, a.lv[0].r_in, chunk);
+        } else if constexpr (HIN) {
+            load_head(a, T, bg * a.Gk, chunk, a.rmax);
         }
         stage_twiddles(a, 1, W0, ap_grp, bg, true);
         float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -800,7 +808,7 @@ xi_pass_mfma(PassArgs a) {
             TwStage<tw_regs<VT>()> next;
             if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
             next.load(a, j + 1, ap_grp, bg, true);
-            const bool from_f = j == 1 && a.has_head;
+            const bool from_f = j == 1 && fsep;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     odd ? W0 : W1, j, aM, pad);
@@ -815,7 +823,7 @@ xi_pass_mfma(PassArgs a) {
             SwRound<sw_pairs<PREC>()> sw0;
             if constexpr (sw_ahead<PREC>())
                 if (a.has_switch) sw_load(a, ap_grp * a.Gk, bg, 0, sw0);
-            const bool from_f = j == 1 && a.has_head;
+            const bool from_f = j == 1 && fsep;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     (j & 1) ? W0 : W1, j, aM, pad);
@@ -972,7 +980,8 @@ std::string launch_sum_parts(const PassArgs& a, int nv, hipStream_t st) {
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     const size_t tsz = (size_t)a.Gk * a.rmax * a.Vt, wsz = (size_t)2 * a.Gk * a.rmax;
     size_t e = tsz + 2 * wsz + kMfmaLdsPad;
-    if (is_xi && a.has_head) e += (size_t)a.Gk * a.head_r * a.Vt;
+    if (is_xi && a.has_head && !a.head_inplace)
+        e += (size_t)a.Gk * a.head_r * a.Vt;
     return e * sizeof(float2);
 }
 
@@ -980,7 +989,10 @@ template <int VT, int PREC>
 static void set_attrs() {
     static bool attr = false;
     if (attr) return;
-    (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC>,
+    (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)xi_pass_mfma<VT, PREC, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     (void)hipFuncSetAttribute((const void*)x_pass_mfma<VT, PREC>,
@@ -1025,9 +1037,12 @@ static std::string launch_vt(const PassArgs& a, bool is_xi, size_t lds,
     set_attrs<VT, PREC>();
     const long long nblocks = a.nspatial * a.nchunk;
     const int threads = pass_threads(a, is_xi, VT, lds, nblocks);
-    if (is_xi)
-        hipLaunchKernelGGL((xi_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
-                           dim3(threads), lds, st, a);
+    if (is_xi && a.head_inplace)
+        hipLaunchKernelGGL((xi_pass_mfma<VT, PREC, true>),
+                           dim3((unsigned)nblocks), dim3(threads), lds, st, a);
+    else if (is_xi)
+        hipLaunchKernelGGL((xi_pass_mfma<VT, PREC, false>),
+                           dim3((unsigned)nblocks), dim3(threads), lds, st, a);
     else
         hipLaunchKernelGGL((x_pass_mfma<VT, PREC>), dim3((unsigned)nblocks),
                            dim3(threads), lds, st, a);

@@ -51,6 +51,10 @@ struct PassArgs {
     const float2* f;
     const float2* bamp;
     int head_side, head_r;
+    int head_inplace;         // xi MFMA passes: 1 = the head is gathered
+                              // into the state tile (slot stride rmax) at
+                              // every sub-iteration instead of being kept
+                              // in a tile of its own for all of them
     int n_sub;                // sub-iterations per workgroup
     int x_split;              // tail x passes: workgroups sharing the
                               // sub-iterations (B groups) of one A group;
@@ -120,11 +124,15 @@ struct Walk2 {
     }
 };
 
-// Gather of the head into dst[(m * head_r + s) * Vt + col]: input box
-// box0 + m (side head_side, all of its indices) and column col of the chunk,
-// value b_k(xi) f_v(xi).
+// Gather of the head into dst[(m * rs + s) * Vt + col], rs = head_r unless
+// given: input box box0 + m (side head_side, all of its indices) and column
+// col of the chunk, value b_k(xi) f_v(xi).
 __device__ __forceinline__ void load_head(const PassArgs& a, float2* dst,
-                                          long long box0, int chunk) {
+                                          long long box0, int chunk,
+                                          int rs = 0) {
+    // rows head_r..rs-1 of each box are skipped: element e lands at
+    // e + m (rs - head_r) Vt
+    const int gap = rs > a.head_r ? (rs - a.head_r) * a.Vt : 0;
     const int total = a.Gk * a.head_r * a.Vt;
     const int e0 = threadIdx.x;
     Walk2 rc(e0, a.Vt);                  // (row, col), row = m * head_r + s
@@ -151,7 +159,7 @@ __device__ __forceinline__ void load_head(const PassArgs& a, float2* dst,
             const float2 fv = a.f[(size_t)vl * a.N + j];
             v = a.bamp ? cmul(a.bamp[(size_t)kk * a.N + j], fv) : fv;
         }
-        dst[e] = v;
+        dst[e + m * gap] = v;
         const int old_row = rc.hi;
         rc.next();
         const bool plus = (rc.hi - old_row) != rc.dhi;
