@@ -11,8 +11,9 @@ oracle values `tests/golden/make_fullsize.py` computed with oracle/ alone:
   there (vector 0);
 * the batched workload's plan built for a single vector, vector 0 against
   the same butterfly rows (FP32 <= 1e-5, BF16x3 <= 1e-4, FP16x3 <= 1e-5);
-* the split precisions at the precision-sweep size (N = 2^20, 256 vectors)
-  against the stored butterfly rows: BF16x3 <= 1e-4, FP16x3 <= 1e-5."""
+* the split precisions at the batched size and at the precision-sweep size
+  (N = 2^20, 256 vectors) against the stored butterfly rows: BF16x3 <= 1e-4,
+  FP16x3 <= 1e-5."""
 
 import json
 import os
@@ -80,6 +81,24 @@ def test_full_size_against_oracle(name):
         e = rel(g[v], _unpack(ref["dense"][str(v)]))[0]
         log(f"  vector {v}: GPU vs dense {e:.3e}")
         assert e < eps + TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4),
+                                           ("fp16x3", 1e-5)])
+def test_split_precision_at_batched_size(precision, tol):
+    # the batched workload in the launch configuration the benchmark times
+    # (head gathered into the state tile, two workgroups per CU)
+    name = "fio1d_n262144_batched"
+    ref = _golden()[name]
+    rows = np.asarray(ref["rows"], np.int64)
+    picks = ref["vectors"]
+    log(f"case batched size {precision}, vectors {picks}")
+    g = _gpu_rows(name, precision, rows, picks)
+    for v in picks:
+        if str(v) in ref["bf"]:
+            e = rel(g[v], _unpack(ref["bf"][str(v)]))[0]
+            log(f"  {precision} vector {v} vs oracle butterfly {e:.3e}")
+            assert e < tol
 
 
 @pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4),
