@@ -409,10 +409,13 @@ static bool pass_fits(const Plan& p, int s0, int s1, int Vt, bool head,
     if (k > kMaxPassLevels) return false;
     if (mfma_mode(p, Vt) && p.steps[s0].kind != STEP_SWITCH) {
         const int hr1 = p.head_step_side;
-        // the tile (updated in place), two twiddle buffers, and the f tile
-        // of the head pass
+        // the tile (updated in place), two twiddle buffers, the f tile of
+        // the head pass and, in an FP32 x pass, every level's A operand
+        const bool x_amat =
+            p.steps[s0].kind == STEP_X && p.precision == BF_FP32;
         const size_t lds = (size_t)Gk * rmax * Vt * 8 + (size_t)4 * Gk * rmax * 8 +
-                           (head ? (size_t)Gk * hr1 * Vt * 8 : 0) + kMfmaLdsPad * 8;
+                           (head ? (size_t)Gk * hr1 * Vt * 8 : 0) + kMfmaLdsPad * 8 +
+                           (x_amat ? (size_t)k * 256 * 8 : 0);
         return lds <= kMfmaLdsBudget && Gk * Vt <= (long long)kMfmaTileCap * 8;
     }
     size_t lds = (size_t)Gk * rmax * Vt * 8;

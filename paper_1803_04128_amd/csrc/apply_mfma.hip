@@ -837,6 +837,11 @@ xi_pass_mfma(PassArgs a) {
     }
 }
 
+// The FP32 A operands of all levels are staged in LDS once per workgroup
+// (AX[(j - 1) 512 + q 64 + lane] = aM[q] of level j, the order of
+// load_amat): they are shared by every unit of a level, and reading them
+// from LDS per level keeps them (and the next level's) out of the
+// registers.
 template <int VT, int PREC>
 __global__ void __launch_bounds__((kMfmaThreads))
 x_pass_mfma(PassArgs a) {
@@ -850,6 +855,15 @@ x_pass_mfma(PassArgs a) {
     block_coords(a, spatial, chunk);
     if (spatial >= a.nspatial) return;
     float2* const pad = lds + tsz + 2 * wsz;
+    float* const AX = (float*)(pad + kMfmaLdsPad);
+    if constexpr (PREC == BF_FP32) {
+        for (int e = threadIdx.x; e < a.k * 512; e += blockDim.x) {
+            const int j = e >> 9, q = (e >> 6) & 7, ln = e & 63;
+            const PassLevel& lv = a.lv[j];
+            const int nks = (lv.r_in + 3) >> 2, i = q >> 2, kk = q & 3;
+            AX[e] = kk < nks ? lv.amat[(i * nks + kk) * 64 + ln] : 0.f;
+        }
+    }
     zero_pass_lds(lds, tsz + 2 * wsz, pad);
     // with x_split > 1 the workgroup takes part `part` of the B groups
     const int part = (int)(spatial % a.x_split);
@@ -865,23 +879,21 @@ x_pass_mfma(PassArgs a) {
         const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
         load_tile(a, T, p0, a.lv[0].r_in, chunk);
         stage_twiddles(a, 1, W0, ap_grp, bg, false);
-        float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if constexpr (PREC == BF_FP32) load_amat(a.lv[0], false, aM);
         __syncthreads();
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
-            float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             TwStage<tw_regs<VT>()> next;
-            if (j < a.k) {
-                if constexpr (PREC == BF_FP32) load_amat(a.lv[j], false, aMn);
-                next.load(a, j + 1, ap_grp, bg, false);
+            if (j < a.k) next.load(a, j + 1, ap_grp, bg, false);
+            if constexpr (PREC == BF_FP32) {
+                const int ln = threadIdx.x & 63;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) aM[q] = AX[(j - 1) * 512 + q * 64 + ln];
             }
             mfma_x_level<VT, PREC>(a, T, T, odd ? W0 : W1, j,
                                    a.has_tail && j == a.k, tacc, aM, pad);
             if (j < a.k) next.store(odd ? W1 : W0);
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
         }
         if (!a.has_tail) {
             store_tile(a, T, ap_grp * a.Gk, bg, chunk);
@@ -982,6 +994,7 @@ size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     size_t e = tsz + 2 * wsz + kMfmaLdsPad;
     if (is_xi && a.has_head && !a.head_inplace)
         e += (size_t)a.Gk * a.head_r * a.Vt;
+    if (!is_xi && a.prec == BF_FP32) e += (size_t)a.k * 256;   // A operands
     return e * sizeof(float2);
 }
 
