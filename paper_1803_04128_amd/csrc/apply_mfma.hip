@@ -873,18 +873,36 @@ x_pass_mfma(PassArgs a) {
     floatx4 tacc[2 * wave_tiles<VT>()];
 #pragma unroll
     for (int m = 0; m < 2 * wave_tiles<VT>(); ++m) tacc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the next sub-iteration's tile and level-1 twiddles are read during
+    // the current one's last level and written at the next one's start
+    // (not in FP16x3, whose x levels leave no registers for them)
+    constexpr bool kPre = PREC != BF_FP16X3;
+    TileLoad<5> pre;
+    TwStage<tw_regs<VT>()> pre_tw;
     for (int si = 0; si < a.n_sub; ++si) {
         const int sub = part * a.n_sub + si;
         const long long bg = a.has_tail ? sub : bg0;
-        const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
-        load_tile(a, T, p0, a.lv[0].r_in, chunk);
-        stage_twiddles(a, 1, W0, ap_grp, bg, false);
+        if (si == 0 || !kPre) {
+            const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
+            load_tile(a, T, p0, a.lv[0].r_in, chunk);
+            stage_twiddles(a, 1, W0, ap_grp, bg, false);
+        } else {
+            pre.store(a, T, a.lv[0].r_in);
+            pre_tw.store(W0);
+        }
         __syncthreads();
         for (int j = 1; j <= a.k; ++j) {
             const bool odd = (j & 1) != 0;
             float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             TwStage<tw_regs<VT>()> next;
-            if (j < a.k) next.load(a, j + 1, ap_grp, bg, false);
+            if (j < a.k) {
+                next.load(a, j + 1, ap_grp, bg, false);
+            } else if (kPre && si + 1 < a.n_sub) {
+                const long long bgn = a.has_tail ? sub + 1 : bg0;
+                pre.load(a, (ap_grp << (a.L - a.la + 1)) + bgn * a.Gk,
+                         a.lv[0].r_in, chunk);
+                pre_tw.load(a, 1, ap_grp, bgn, false);
+            }
             if constexpr (PREC == BF_FP32) {
                 const int ln = threadIdx.x & 63;
 #pragma unroll

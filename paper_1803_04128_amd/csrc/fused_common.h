@@ -194,6 +194,45 @@ __device__ __forceinline__ void store_tile(const PassArgs& a,
 }
 
 // Load the Gk consecutive pairs p0 .. p0+Gk-1 of the input state into slots.
+// load_tile in two halves: load() issues the global reads of the tile into
+// registers (up to NR per thread), store() writes them to LDS and copies
+// any entries past NR per thread directly, so that the reads overlap the
+// work in between.
+template <int NR>
+struct TileLoad {
+    float2 v[NR];
+    const float2* base;
+    int total;
+
+    __device__ __forceinline__ void load(const PassArgs& a, long long p0,
+                                         int r_in, int chunk) {
+        const int per_pair = r_in * a.Vt;
+        total = a.Gk * per_pair;
+        base = a.in + (size_t)chunk * a.N * per_pair + (size_t)p0 * per_pair;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int e = threadIdx.x + m * (int)blockDim.x;
+            if (e < total) v[m] = base[e];
+        }
+    }
+
+    __device__ __forceinline__ void store(const PassArgs& a, float2* tile,
+                                          int r_in) const {
+        const int per_pair = r_in * a.Vt;
+        const int lds_pair = a.rmax * a.Vt;
+        Walk2 w(threadIdx.x, per_pair);
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int e = threadIdx.x + m * (int)blockDim.x;
+            if (e < total) tile[w.hi * lds_pair + w.lo] = v[m];
+            w.next();
+        }
+        for (int e = threadIdx.x + NR * (int)blockDim.x; e < total;
+             e += blockDim.x, w.next())
+            tile[w.hi * lds_pair + w.lo] = base[e];
+    }
+};
+
 __device__ __forceinline__ void load_tile(const PassArgs& a, float2* tile,
                                           long long p0, int r_in, int chunk) {
     const int per_pair = r_in * a.Vt;
