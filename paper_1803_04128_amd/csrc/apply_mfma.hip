@@ -734,6 +734,14 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
     __syncthreads();
 }
 
+// A operand of level j from a pass's per-workgroup LDS copy.
+__device__ __forceinline__ void read_amat(const float* AX, int j,
+                                          float (&aM)[8]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) aM[q] = AX[(j - 1) * 512 + q * 64 + lane];
+}
+
 // Zero the tiles, the twiddle buffers and the trailing pad of a pass (the
 // f tile is written whole before use), so that K steps past a level's rank
 // and rows past r_out read finite values, which then meet zero A entries or
@@ -777,14 +785,30 @@ xi_pass_mfma(PassArgs a) {
     // zeroed pad after the tiles: reads past a level's rank land here, and
     // stores of rows past r_out and of padding columns go here (finite)
     float2* const pad = fsep ? ftile + a.Gk * a.head_r * VT : ftile;
+    // in-place head (FP32): the A operands of every level are staged in LDS
+    // once (AX[(j - 1) 512 + q 64 + lane] = aM[q] of level j, the order of
+    // load_amat), which leaves the registers to hold the gathered head
+    constexpr bool kAX = HIN && PREC == BF_FP32;
+    float* const AX = (float*)(pad + kMfmaLdsPad);
+    if constexpr (kAX) {
+        for (int e = threadIdx.x; e < a.k * 512; e += blockDim.x) {
+            const int j = e >> 9, q = (e >> 6) & 7, ln = e & 63;
+            const PassLevel& lv = a.lv[j];
+            AX[e] = q < ((lv.r_in + 1) >> 1) ? lv.amat[q * 64 + ln] : 0.f;
+        }
+    }
     zero_pass_lds(lds, tsz + 2 * wsz, pad);
     const int part = (int)(spatial % a.sub_split);
     spatial /= a.sub_split;
     const long long bg = spatial % a.nbg;
     const long long ap_base = spatial / a.nbg;
     // the f tile is shared by the sub-iterations of the workgroup (the T_X
-    // boxes at level l0 - 1 all see the same input)
+    // boxes at level l0 - 1 all see the same input): kept in LDS, or (in
+    // place, FP32) in registers and written into T at every sub-iteration
     if (fsep) load_head(a, ftile, bg * a.Gk, chunk);
+    HeadRegs<8> hreg;
+    const bool hkeep = kAX && hreg.fits(a);
+    if (hkeep) hreg.load(a, bg * a.Gk, chunk);
     for (int si = 0; si < a.n_sub; ++si) {
         const int sub = part * a.n_sub + si;
         const long long ap_grp = a.has_head ? sub : ap_base;
@@ -792,11 +816,14 @@ xi_pass_mfma(PassArgs a) {
             const long long p0 = (ap_grp << (a.L - a.la + 1)) + bg * a.Gk;
             load_tile(a, T, p0, a.lv[0].r_in, chunk);
         } else if constexpr (HIN) {
-            load_head(a, T, bg * a.Gk, chunk, a.rmax);
+            if (hkeep)
+                hreg.store(a, T, a.rmax);
+            else
+                load_head(a, T, bg * a.Gk, chunk, a.rmax);
         }
         stage_twiddles(a, 1, W0, ap_grp, bg, true);
         float aM[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if constexpr (PREC == BF_FP32) load_amat(a.lv[0], true, aM);
+        if constexpr (PREC == BF_FP32 && !kAX) load_amat(a.lv[0], true, aM);
         __syncthreads();
         // level j uses W0 (j odd) or W1; the next level's A operand and
         // twiddles are read from global memory before the level's MFMA work
@@ -806,20 +833,24 @@ xi_pass_mfma(PassArgs a) {
             const bool odd = (j & 1) != 0;
             float aMn[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             TwStage<tw_regs<VT>()> next;
-            if constexpr (PREC == BF_FP32) load_amat(a.lv[j], true, aMn);
+            if constexpr (PREC == BF_FP32 && !kAX) load_amat(a.lv[j], true, aMn);
             next.load(a, j + 1, ap_grp, bg, true);
+            if constexpr (kAX) read_amat(AX, j, aM);
             const bool from_f = j == 1 && fsep;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     odd ? W0 : W1, j, aM, pad);
             next.store(odd ? W1 : W0);
             __syncthreads();
+            if constexpr (!kAX) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
+                for (int q = 0; q < 8; ++q) aM[q] = aMn[q];
+            }
         }
         {
             // the last level reads the switch's first blocks ahead
             const int j = a.k;
+            if constexpr (kAX) read_amat(AX, j, aM);
             SwRound<sw_pairs<PREC>()> sw0;
             if constexpr (sw_ahead<PREC>())
                 if (a.has_switch) sw_load(a, ap_grp * a.Gk, bg, 0, sw0);
@@ -903,11 +934,7 @@ x_pass_mfma(PassArgs a) {
                          a.lv[0].r_in, chunk);
                 pre_tw.load(a, 1, ap_grp, bgn, false);
             }
-            if constexpr (PREC == BF_FP32) {
-                const int ln = threadIdx.x & 63;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) aM[q] = AX[(j - 1) * 512 + q * 64 + ln];
-            }
+            if constexpr (PREC == BF_FP32) read_amat(AX, j, aM);
             mfma_x_level<VT, PREC>(a, T, T, odd ? W0 : W1, j,
                                    a.has_tail && j == a.k, tacc, aM, pad);
             if (j < a.k) next.store(odd ? W1 : W0);
@@ -1012,7 +1039,8 @@ size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     size_t e = tsz + 2 * wsz + kMfmaLdsPad;
     if (is_xi && a.has_head && !a.head_inplace)
         e += (size_t)a.Gk * a.head_r * a.Vt;
-    if (!is_xi && a.prec == BF_FP32) e += (size_t)a.k * 256;   // A operands
+    // A operands of the FP32 x passes and in-place head xi passes
+    if (a.prec == BF_FP32 && (!is_xi || a.head_inplace)) e += (size_t)a.k * 256;
     return e * sizeof(float2);
 }
 

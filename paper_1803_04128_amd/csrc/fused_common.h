@@ -124,9 +124,32 @@ struct Walk2 {
     }
 };
 
+// Head value of input box `box` (side head_side, all of its indices),
+// index s within it, panel column gc: b_k(xi) f_v(xi), zero past the
+// panel's columns.
+__device__ __forceinline__ float2 head_entry(const PassArgs& a, long long box,
+                                             int s, int gc) {
+    float2 v = make_float2(0.f, 0.f);
+    if (gc < a.Vs) {
+        int bc[2], gi[2];
+        box_coords(box, a.dim, bc);
+        if (a.dim == 1) {
+            gi[0] = bc[0] * a.head_side + s;
+        } else {
+            const int s1 = s / a.head_side;
+            gi[0] = bc[0] * a.head_side + s1;
+            gi[1] = bc[1] * a.head_side + (s - s1 * a.head_side);
+        }
+        const long long j = user_index(gi, a.dim, a.n);
+        const int vl = gc / a.r_amp, kk = gc - vl * a.r_amp;
+        const float2 fv = a.f[(size_t)vl * a.N + j];
+        v = a.bamp ? cmul(a.bamp[(size_t)kk * a.N + j], fv) : fv;
+    }
+    return v;
+}
+
 // Gather of the head into dst[(m * rs + s) * Vt + col], rs = head_r unless
-// given: input box box0 + m (side head_side, all of its indices) and column
-// col of the chunk, value b_k(xi) f_v(xi).
+// given: input box box0 + m and column col of the chunk.
 __device__ __forceinline__ void load_head(const PassArgs& a, float2* dst,
                                           long long box0, int chunk,
                                           int rs = 0) {
@@ -142,24 +165,7 @@ __device__ __forceinline__ void load_head(const PassArgs& a, float2* dst,
     const int q1 = (rc.dhi + 1) / a.head_r, r1 = rc.dhi + 1 - q1 * a.head_r;
     for (int e = e0; e < total; e += blockDim.x) {
         const int col = rc.lo, m = ms.hi, s = ms.lo;
-        const int gc = chunk * a.Vt + col;
-        float2 v = make_float2(0.f, 0.f);
-        if (gc < a.Vs) {
-            int bc[2], gi[2];
-            box_coords(box0 + m, a.dim, bc);
-            if (a.dim == 1) {
-                gi[0] = bc[0] * a.head_side + s;
-            } else {
-                const int s1 = s / a.head_side;
-                gi[0] = bc[0] * a.head_side + s1;
-                gi[1] = bc[1] * a.head_side + (s - s1 * a.head_side);
-            }
-            const long long j = user_index(gi, a.dim, a.n);
-            const int vl = gc / a.r_amp, kk = gc - vl * a.r_amp;
-            const float2 fv = a.f[(size_t)vl * a.N + j];
-            v = a.bamp ? cmul(a.bamp[(size_t)kk * a.N + j], fv) : fv;
-        }
-        dst[e + m * gap] = v;
+        dst[e + m * gap] = head_entry(a, box0 + m, s, chunk * a.Vt + col);
         const int old_row = rc.hi;
         rc.next();
         const bool plus = (rc.hi - old_row) != rc.dhi;
@@ -171,6 +177,44 @@ __device__ __forceinline__ void load_head(const PassArgs& a, float2* dst,
         }
     }
 }
+
+// The head gathered once into registers (NR entries per thread, in the
+// order of load_head) and written to LDS as often as needed; covers heads
+// of at most NR * blockDim entries (fits()).
+template <int NR>
+struct HeadRegs {
+    float2 v[NR];
+
+    __device__ __forceinline__ bool fits(const PassArgs& a) const {
+        return a.Gk * a.head_r * a.Vt <= NR * (int)blockDim.x;
+    }
+    __device__ __forceinline__ void load(const PassArgs& a, long long box0,
+                                         int chunk) {
+        const int per_box = a.head_r * a.Vt;
+        const int total = a.Gk * per_box;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int e = threadIdx.x + m * (int)blockDim.x;
+            v[m] = make_float2(0.f, 0.f);
+            if (e < total) {
+                const int box = e / per_box, rem = e - box * per_box;
+                const int s = rem / a.Vt, col = rem - s * a.Vt;
+                v[m] = head_entry(a, box0 + box, s, chunk * a.Vt + col);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(const PassArgs& a, float2* dst,
+                                          int rs) const {
+        const int per_box = a.head_r * a.Vt;
+        const int total = a.Gk * per_box;
+        const int gap = (rs - a.head_r) * a.Vt;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int e = threadIdx.x + m * (int)blockDim.x;
+            if (e < total) dst[e + (e / per_box) * gap] = v[m];
+        }
+    }
+};
 
 // Copy the tile's Gk pairs (slot = digit-reversed logical a_loc) to the
 // state at the pass's last level lb: pair (a0 + a_loc) R^(L-lb) + bfix.
