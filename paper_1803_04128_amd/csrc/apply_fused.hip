@@ -691,10 +691,10 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             return "split precision needs the 1D MFMA passes (power-of-two "
                    "tile width, r in {1, 2, 4, 8}, a level in every pass)";
         // a head xi pass whose own f tile keeps it at one workgroup per CU
-        // gathers the head into the state tile at every sub-iteration when
-        // that lets two workgroups share a CU (then of 512 threads each):
-        // the gather is repeated per sub-iteration, from L2, but the two
-        // groups overlap each other's factor reads and barriers
+        // writes the head into the state tile at every sub-iteration
+        // instead (from registers in FP32, else gathered again) when that
+        // lets two workgroups of 512 threads share a CU; they then overlap
+        // each other's factor reads and barriers
         a.head_inplace = 0;
         if (use_mfma && is_xi && a.has_head && a.head_r <= a.rmax) {
             const size_t keep = mfma_pass_lds(a, true);
