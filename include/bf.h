@@ -160,6 +160,18 @@ int bf_plan_op(const bf_grid* grid, const bf_phase* phase,
                const bf_amplitude* amp, int q, int precision, int max_nvec,
                int op, bf_plan_t* out);
 
+/* Device bytes bf_plan_op with the same arguments would allocate: the
+ * factor arena (twiddles, Lagrange matrices, amplitude factors), the stored
+ * switch blocks when the initial execution form reads them, the low-rank
+ * phase factors and the default workspace.  Host only: no device is
+ * touched, so a caller that admits plans under a memory budget can decide
+ * before anything is allocated.  Returns the status bf_plan_op would return
+ * for the arguments' checks (BF_EINVAL, BF_EUNSUPPORTED, BF_ENOMEM for the
+ * BF_MEM_CAP_BYTES cap); *bytes is 0 on failure.                         */
+int bf_plan_footprint(const bf_grid* grid, const bf_phase* phase,
+                      const bf_amplitude* amp, int q, int precision,
+                      int max_nvec, int op, size_t* bytes);
+
 /* Apply: g[v] = sum_k a_k * BF(b_k * f[v]) for v < nvec (eq. (eqn:tg) with
  * Algorithm 4.1).
  * f, g: device complex64 interleaved, layout [nvec][N], contiguous, owned

@@ -16,6 +16,7 @@ from . import _lib
 from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
+           "plan_footprint",
            "apply_chain", "graph_chain", "fourier_coefficients_plan",
            "unwrap",
            "recover_phase", "kernel_phase_sampler", "lowrank_from_samples",
@@ -48,6 +49,56 @@ def lagrange(nodes, y):
     return out
 
 
+def _plan_structs(dim, n, phase, params, amplitude, op):
+    """The bf_grid, bf_phase and bf_amplitude of a plan, and the arrays
+    their pointers refer to (keep them alive while the structs are used)."""
+    if op not in OPS:
+        raise ValueError(f"op must be one of {sorted(OPS)}")
+    grid = _lib.BfGrid(int(dim), int(n))
+    if phase == "lowrank":
+        # params = (U, V): real factors [N][rank], Phi = U V^T
+        U, V = (np.ascontiguousarray(m, dtype=np.float64) for m in params)
+        if U.ndim != 2 or U.shape != V.shape or U.shape[0] != n ** dim:
+            raise ValueError("low-rank phase factors must both be "
+                             "[N][rank]")
+        pa = (C.c_double * 1)()
+        ph = _lib.BfPhase(PHASES[phase], 0, pa, U.shape[1],
+                          U.ctypes.data_as(C.POINTER(C.c_double)),
+                          V.ctypes.data_as(C.POINTER(C.c_double)))
+        keep = [pa, U, V]
+    else:
+        pa = (C.c_double * max(1, len(params)))(*params)
+        ph = _lib.BfPhase(PHASES[phase], len(params), pa)
+        keep = [pa]
+    amp = None
+    if amplitude is not None:
+        a, b = amplitude
+        a = np.ascontiguousarray(a, dtype=np.complex128)
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        if a.shape != b.shape or a.ndim != 2 or a.shape[1] != n ** dim:
+            raise ValueError("amplitude factors must both be [r][N]")
+        amp = _lib.BfAmplitude(
+            a.shape[0], a.ctypes.data_as(C.POINTER(C.c_double)),
+            b.ctypes.data_as(C.POINTER(C.c_double)))
+        keep += [a, b]
+    return grid, ph, amp, keep
+
+
+def plan_footprint(dim, n, phase, params=(), q=8, amplitude=None,
+                   precision="fp32", max_nvec=1, op="N"):
+    """Device bytes Plan(...) with these arguments would allocate (factors,
+    stored switch blocks, low-rank phase factors, workspace), computed on
+    the host without touching a device (bf_plan_footprint)."""
+    lib = _lib.load()
+    grid, ph, amp, keep = _plan_structs(dim, n, phase, params, amplitude, op)
+    out = C.c_size_t()
+    _lib.check(lib.bf_plan_footprint(
+        C.byref(grid), C.byref(ph), C.byref(amp) if amp else None, int(q),
+        PRECISIONS[precision], int(max_nvec), OPS[op], C.byref(out)))
+    del keep
+    return out.value
+
+
 class Plan:
     """A device-resident butterfly plan (bf_plan ... bf_destroy).
 
@@ -65,40 +116,18 @@ class Plan:
 
     def __init__(self, dim, n, phase, params=(), q=8, amplitude=None,
                  precision="fp32", max_nvec=1, op="N"):
-        if op not in OPS:
-            raise ValueError(f"op must be one of {sorted(OPS)}")
         self._lib = _lib.load()
         self._h = C.c_void_p()
-        grid = _lib.BfGrid(int(dim), int(n))
-        if phase == "lowrank":
-            # params = (U, V): real factors [N][rank], Phi = U V^T
-            U, V = (np.ascontiguousarray(m, dtype=np.float64) for m in params)
-            if U.ndim != 2 or U.shape != V.shape or U.shape[0] != n ** dim:
-                raise ValueError("low-rank phase factors must both be "
-                                 "[N][rank]")
-            self._params = (C.c_double * 1)()
-            ph = _lib.BfPhase(PHASES[phase], 0, self._params, U.shape[1],
-                              U.ctypes.data_as(C.POINTER(C.c_double)),
-                              V.ctypes.data_as(C.POINTER(C.c_double)))
-        else:
-            self._params = (C.c_double * max(1, len(params)))(*params)
-            ph = _lib.BfPhase(PHASES[phase], len(params), self._params)
-        amp = None
-        self.r = 1
-        if amplitude is not None:
-            a, b = amplitude
-            a = np.ascontiguousarray(a, dtype=np.complex128)
-            b = np.ascontiguousarray(b, dtype=np.complex128)
-            if a.shape != b.shape or a.ndim != 2:
-                raise ValueError("amplitude factors must both be [r][N]")
-            self.r = a.shape[0]
-            amp = _lib.BfAmplitude(
-                self.r, a.ctypes.data_as(C.POINTER(C.c_double)),
-                b.ctypes.data_as(C.POINTER(C.c_double)))
+        grid, ph, amp, self._keep = _plan_structs(dim, n, phase, params,
+                                                  amplitude, op)
+        self.r = amp.r if amp is not None else 1
         _lib.check(self._lib.bf_plan_op(
             C.byref(grid), C.byref(ph), C.byref(amp) if amp else None,
             int(q), PRECISIONS[precision], int(max_nvec), OPS[op],
             C.byref(self._h)))
+        import torch
+        # bf_plan builds on the current device; applies must stay there
+        self.device = torch.cuda.current_device()
         self.op = op
         self.dim, self.n, self.q = dim, n, q
         self.N = n ** dim
@@ -122,20 +151,36 @@ class Plan:
         s = stream if stream is not None else torch.cuda.current_stream()
         return C.c_void_p(s.cuda_stream)
 
+    def _device_tensor(self, t, name, complex64=True):
+        """Reject what the kernels must not see: host tensors (whose host
+        pointer would reach the GPU), tensors on another device, other
+        dtypes and non-contiguous views."""
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on cuda:{t.device.index}, the plan "
+                             f"on cuda:{self.device}")
+        if complex64 and t.dtype != torch.complex64:
+            raise TypeError(f"{name} must be complex64")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
     def _args(self, f, out):
         import torch
-        if not (f.is_cuda and f.dtype == torch.complex64):
-            raise TypeError("f must be a complex64 CUDA tensor")
+        self._device_tensor(f, "f")
         f2 = f.reshape(1, -1) if f.dim() == 1 else f
-        if f2.shape[-1] != self.N or not f2.is_contiguous():
-            raise ValueError("f must be contiguous with N entries per vector")
+        if f2.dim() != 2 or f2.shape[-1] != self.N:
+            raise ValueError("f must be [nvec][N] (or [N])")
         if out is None:
             out = torch.empty_like(f2)
-        elif out.dim() == 1:
-            out = out.reshape(1, -1)
-        if out.shape != f2.shape or out.dtype != f2.dtype or \
-                not out.is_contiguous():
-            raise ValueError("out must be a contiguous complex64 like f")
+        else:
+            self._device_tensor(out, "out")
+            if out.dim() == 1:
+                out = out.reshape(1, -1)
+        if out.shape != f2.shape:
+            raise ValueError("out must have the shape of f")
         return f2, out, f2.shape[0]
 
     def apply(self, f, out=None, stream=None, workspace=None):
@@ -143,6 +188,8 @@ class Plan:
         Asynchronous on ``stream`` (default: torch's current stream)."""
         squeeze = f.dim() == 1
         f2, out, nvec = self._args(f, out)
+        if workspace is not None:
+            self._device_tensor(workspace, "workspace", complex64=False)
         st = self._stream(stream)
         if workspace is None:
             _lib.check(self._lib.bf_apply(self._h, nvec, C.c_void_p(
@@ -244,6 +291,10 @@ class Graph:
                 C.c_void_p(self.out.data_ptr()), C.byref(self._h)))
             return
         import torch
+        if tmp is not None:
+            plan._device_tensor(tmp, "tmp")
+            if tmp.numel() != self.f.numel():
+                raise ValueError("tmp must have the shape of f")
         self.tmp = tmp if tmp is not None or len(chain) == 1 else \
             torch.empty_like(self.f)
         arr = (C.c_void_p * len(chain))(*[p._h.value for p in chain])
@@ -289,9 +340,10 @@ def apply_chain(plans, f, out=None, tmp=None, stream=None):
     if tmp is None and len(plans) > 1:
         import torch
         tmp = torch.empty_like(f2)
-    if tmp is not None and (tmp.shape != f2.shape or tmp.dtype != f2.dtype
-                            or not tmp.is_contiguous()):
-        raise ValueError("tmp must be a contiguous complex64 like f")
+    if tmp is not None:
+        plans[0]._device_tensor(tmp, "tmp")
+        if tmp.numel() != f2.numel():
+            raise ValueError("tmp must have the shape of f")
     arr = (C.c_void_p * len(plans))(*[p._h.value for p in plans])
     _lib.check(plans[0]._lib.bf_apply_chain(
         arr, len(plans), nvec, C.c_void_p(f2.data_ptr()),

@@ -63,7 +63,7 @@ class BfTuneEntry(C.Structure):
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
-EXPORTS = ["bf_plan", "bf_plan_op", "bf_apply_chain",
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_plan_footprint", "bf_apply_chain",
            "bf_graph_create_chain", "bf_unwrap",
            "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
@@ -103,6 +103,9 @@ def load():
     lib.bf_plan_op.argtypes = [P(BfGrid), P(BfPhase), P(BfAmplitude),
                                C.c_int, C.c_int, C.c_int, C.c_int,
                                P(C.c_void_p)]
+    lib.bf_plan_footprint.argtypes = [P(BfGrid), P(BfPhase),
+                                      P(BfAmplitude), C.c_int, C.c_int,
+                                      C.c_int, C.c_int, P(C.c_size_t)]
     lib.bf_unwrap.argtypes = [P(C.c_double), C.c_longlong, C.c_double,
                               P(C.c_double), P(C.c_longlong), C.c_int,
                               P(C.c_int)]

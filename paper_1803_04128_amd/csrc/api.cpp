@@ -222,11 +222,11 @@ int bf_lagrange(const int* nodes, int r, const double* y, int m,
     });
 }
 
-static int plan_impl(const bf_grid* grid, const bf_phase* phase,
-                     const bf_amplitude* amp, int q, int precision,
-                     int max_nvec, int op, bf_plan_t* out) {
-    if (!out) return fail(BF_EINVAL, "bf_plan: out is NULL");
-    *out = nullptr;
+// Host part of plan construction: argument checks, trees, level schedule,
+// execution form, vector chunking and the memory cap.  No device call.
+static int configure_plan(const bf_grid* grid, const bf_phase* phase,
+                          const bf_amplitude* amp, int q, int precision,
+                          int max_nvec, int op, bfi::Plan& p) {
     if (!grid || !phase) return fail(BF_EINVAL, "bf_plan: NULL grid/phase");
     const int dim = grid->dim, n = grid->n;
     if (dim != 1 && dim != 2) return fail(BF_EINVAL, "bf_plan: dim must be 1 or 2");
@@ -275,9 +275,6 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
             return fail(BF_EINVAL, "bf_plan: alpha = 1 needs r = 1");
     }
 
-    bf_plan_s* h = new (std::nothrow) bf_plan_s();
-    if (!h) return fail(BF_ENOMEM, "bf_plan: host allocation");
-    bfi::Plan& p = h->p;
     p.dim = dim;
     p.n = n;
     p.q = q;
@@ -305,15 +302,9 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     p.tile_cols = tenv ? std::max(0, std::atoi(tenv)) : 0;
     const char* oenv = std::getenv("BF_SWITCH_OTF");
     p.switch_otf = oenv && std::atoi(oenv) != 0 && !p.fused && p.mfma;
-    if (hipGetDevice(&p.device) != hipSuccess) {
-        delete h;
-        return fail(BF_EHIP, "bf_plan: no HIP device");
-    }
+    if (phase->kind == BF_PHASE_LOWRANK) p.phase.rank = phase->rank;
     std::string err = bfi::build_schedule(p);
-    if (!err.empty()) {
-        delete h;
-        return fail(BF_EUNSUPPORTED, "bf_plan: " + err);
-    }
+    if (!err.empty()) return fail(BF_EUNSUPPORTED, "bf_plan: " + err);
     // memory: factors + workspace under the cap
     const size_t cap = env_bytes("BF_MEM_CAP_BYTES", (size_t)-1);
     const size_t ws_cap = env_bytes("BF_WS_CAP_BYTES", 16 * kGiB);
@@ -326,18 +317,47 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
                         (phase->kind == BF_PHASE_LOWRANK
                              ? 2 * (size_t)phase->rank * p.N * 8
                              : 0);
-    if (factor_est + per_vec * chunk > cap) {
-        delete h;
+    if (factor_est + per_vec * chunk > cap)
         return fail(BF_ENOMEM, "bf_plan: plan exceeds BF_MEM_CAP_BYTES");
-    }
     if (bfi::check_config(p) != "") {
         // the configured fused passes do not fit this plan
-        if (precision != BF_FP32) {
-            std::string why = bfi::check_config(p);
-            delete h;
-            return fail(BF_EUNSUPPORTED, "bf_plan: " + why);
-        }
+        if (precision != BF_FP32)
+            return fail(BF_EUNSUPPORTED, "bf_plan: " + bfi::check_config(p));
         p.fused = false;
+    }
+    return BF_OK;
+}
+
+// Device bytes a configured plan allocates: factor arena, stored switch
+// blocks (when its form reads them), low-rank phase factors, workspace.
+static size_t plan_device_bytes(bfi::Plan& p) {
+    return bfi::factor_arena_bytes(p) +
+           (bfi::reads_stored_switch(p) ? bfi::switch_block_bytes(p) : 0) +
+           (p.phase.kind == BF_PHASE_LOWRANK
+                ? 2 * (size_t)p.phase.rank * p.N * sizeof(double)
+                : 0) +
+           bfi::workspace_bytes(p, p.max_nvec);
+}
+
+static int plan_impl(const bf_grid* grid, const bf_phase* phase,
+                     const bf_amplitude* amp, int q, int precision,
+                     int max_nvec, int op, bf_plan_t* out) {
+    if (!out) return fail(BF_EINVAL, "bf_plan: out is NULL");
+    *out = nullptr;
+    bf_plan_s* h = new (std::nothrow) bf_plan_s();
+    if (!h) return fail(BF_ENOMEM, "bf_plan: host allocation");
+    bfi::Plan& p = h->p;
+    if (int e = configure_plan(grid, phase, amp, q, precision, max_nvec, op,
+                               p)) {
+        delete h;
+        return e;
+    }
+    const double* a = amp ? amp->a : nullptr;
+    const double* b = amp ? amp->b : nullptr;
+    std::string err;
+    if (hipGetDevice(&p.device) != hipSuccess) {
+        delete h;
+        return fail(BF_EHIP, "bf_plan: no HIP device");
     }
     {
         // once per process: plans built on several host threads at once do
@@ -389,6 +409,21 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     }
     *out = h;
     return BF_OK;
+}
+
+int bf_plan_footprint(const bf_grid* grid, const bf_phase* phase,
+                      const bf_amplitude* amp, int q, int precision,
+                      int max_nvec, int op, size_t* bytes) {
+    return guarded("bf_plan_footprint", [&]() -> int {
+        if (!bytes) return fail(BF_EINVAL, "bf_plan_footprint: NULL bytes");
+        *bytes = 0;
+        bfi::Plan p;
+        if (int e = configure_plan(grid, phase, amp, q, precision, max_nvec,
+                                   op, p))
+            return e;
+        *bytes = plan_device_bytes(p);
+        return BF_OK;
+    });
 }
 
 int bf_plan(const bf_grid* grid, const bf_phase* phase,

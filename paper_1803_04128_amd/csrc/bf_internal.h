@@ -183,6 +183,9 @@ std::string build_schedule(Plan& p);   // "" on success, else a message
 std::string build_factors(Plan& p);
 std::string upload_amplitude(Plan& p, const double* a, const double* b);
 std::string build_switch_blocks(Plan& p);
+// device bytes build_factors / build_switch_blocks allocate (host only)
+size_t factor_arena_bytes(Plan& p);
+size_t switch_block_bytes(const Plan& p);
 // phase recovery (recovery.cpp); arguments checked by the C ABI
 int recover_phase(long long N, const long long* C, int nc, const long long* R,
                   int nr, int rank, double tau, bf_phase_sampler sample,

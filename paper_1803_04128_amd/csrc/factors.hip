@@ -160,11 +160,23 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
             return std::string(#x ": ") + hipGetErrorString(e_);        \
     } while (0)
 
-std::string build_factors(Plan& p) {
-    // arena layout
+// Offsets of every factor array inside the plan arena.
+struct ArenaLayout {
+    std::vector<size_t> off_tw, off_m, off_hi, off_lo, off_am, off_ax, off_af;
+    size_t off_a = 0, off_b = 0, bytes = 0;
+};
+
+static ArenaLayout arena_layout(Plan& p) {
+    ArenaLayout A;
     size_t bytes = 0;
     const bool split = p.precision != BF_FP32;
-    std::vector<size_t> off_tw, off_m, off_hi, off_lo, off_am, off_ax, off_af;
+    auto& off_tw = A.off_tw;
+    auto& off_m = A.off_m;
+    auto& off_hi = A.off_hi;
+    auto& off_lo = A.off_lo;
+    auto& off_am = A.off_am;
+    auto& off_ax = A.off_ax;
+    auto& off_af = A.off_af;
     for (auto& s : p.steps) {
         off_am.push_back(bytes);
         bytes = align_up(bytes + s.amat_elems * sizeof(float));
@@ -184,11 +196,27 @@ std::string build_factors(Plan& p) {
         off_lo.push_back(bytes);
         bytes = align_up(bytes + s.asplit_elems * 2);
     }
-    size_t off_a = bytes;
+    A.off_a = bytes;
+    if (p.has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
+    A.off_b = bytes;
+    if (p.has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
+    A.bytes = bytes;
+    return A;
+}
+
+size_t factor_arena_bytes(Plan& p) { return arena_layout(p).bytes; }
+
+std::string build_factors(Plan& p) {
+    const ArenaLayout A = arena_layout(p);
+    const auto& off_tw = A.off_tw;
+    const auto& off_m = A.off_m;
+    const auto& off_hi = A.off_hi;
+    const auto& off_lo = A.off_lo;
+    const auto& off_am = A.off_am;
+    const auto& off_ax = A.off_ax;
+    const auto& off_af = A.off_af;
+    const size_t off_a = A.off_a, off_b = A.off_b, bytes = A.bytes;
     const bool has_amp = p.has_amp;
-    if (has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
-    size_t off_b = bytes;
-    if (has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
     p.arena_bytes = bytes;
     HIPCHK(hipMalloc(&p.arena, bytes > 0 ? bytes : 256));
     char* base = (char*)p.arena;
@@ -312,14 +340,24 @@ std::string build_factors(Plan& p) {
 // The switch blocks S of every switch step in an allocation of their own:
 // built when the plan's execution form reads them (all forms but the
 // per-step MFMA form with on-the-fly blocks), kept until bf_destroy.
-std::string build_switch_blocks(Plan& p) {
-    if (p.S_arena) return "";
+static size_t switch_layout(const Plan& p, std::vector<size_t>& off) {
     size_t bytes = 0;
-    std::vector<size_t> off;
     for (auto& s : p.steps) {
         off.push_back(bytes);
         bytes = align_up(bytes + s.S_elems * sizeof(float2));
     }
+    return bytes;
+}
+
+size_t switch_block_bytes(const Plan& p) {
+    std::vector<size_t> off;
+    return switch_layout(p, off);
+}
+
+std::string build_switch_blocks(Plan& p) {
+    if (p.S_arena) return "";
+    std::vector<size_t> off;
+    const size_t bytes = switch_layout(p, off);
     if (bytes == 0) return "";
     void* mem = nullptr;
     HIPCHK(hipMalloc(&mem, bytes));

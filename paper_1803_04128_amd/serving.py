@@ -133,13 +133,20 @@ class Scheduler:
 class PlanCache:
     """Resident plans under an HBM budget, least recently used evicted first.
 
-    build(name) returns an object with ``footprint`` (device bytes) and
-    ``close()``.  A plan in ``pinned`` (in use by the caller) is never
-    evicted."""
+    footprint(name) gives the device bytes a plan will hold, computed on the
+    host before anything is allocated; build(name) returns an object with
+    ``footprint`` (the bytes it holds) and ``close()``.  Admission checks
+    the budget and evicts before building, so device memory never holds
+    more than the budget and each admission builds once.  A plan in
+    ``pinned`` (in use by the caller) is never evicted.  A build that fails
+    (a library error such as an allocation failure) is an admission failure
+    of that plan only."""
 
-    def __init__(self, budget_bytes, build: Callable[[str], Any]):
+    def __init__(self, budget_bytes, build: Callable[[str], Any],
+                 footprint: Callable[[str], int]):
         self.budget = int(budget_bytes)
         self._build = build
+        self._footprint = footprint
         self._res = collections.OrderedDict()
         self.builds = 0
         self.evictions = 0
@@ -155,23 +162,32 @@ class PlanCache:
         if name in self._res:
             self._res.move_to_end(name)
             return self._res[name]
-        obj = self._build(name)
-        self.builds += 1
-        need = obj.footprint
+        try:
+            need = int(self._footprint(name))
+        except Exception as e:        # a spec the library refuses
+            raise AdmissionError(f"plan {name}: {e}") from e
         if need > self.budget:
-            obj.close()
             raise AdmissionError(f"plan {name}: {need} bytes > budget "
                                  f"{self.budget}")
-        for victim in list(self._res):
+        idle = [v for v in self._res if v not in pinned]
+        if self.resident_bytes - sum(self._res[v].footprint for v in idle) \
+                + need > self.budget:
+            raise PinnedError(f"plan {name}: no room next to pinned plans")
+        for victim in idle:
             if self.resident_bytes + need <= self.budget:
                 break
-            if victim in pinned:
-                continue
             self._res.pop(victim).close()
             self.evictions += 1
-        if self.resident_bytes + need > self.budget:
+        try:
+            obj = self._build(name)
+        except Exception as e:
+            raise AdmissionError(f"plan {name}: build failed: {e}") from e
+        self.builds += 1
+        if self.resident_bytes + obj.footprint > self.budget:
+            # the estimate was short: never keep more than the budget
             obj.close()
-            raise PinnedError(f"plan {name}: no room next to pinned plans")
+            raise AdmissionError(f"plan {name}: holds {obj.footprint} bytes, "
+                                 f"estimated {need}")
         self._res[name] = obj
         return obj
 
@@ -199,6 +215,17 @@ class ResidentPlan:
         # amplitude, stored switch blocks, low-rank phase factors)
         self.footprint = (info["factor_bytes"] + info["workspace_bytes"] +
                           2 * self.fin.numel() * 8)
+
+    @staticmethod
+    def footprint_of(spec: PlanSpec, max_batch):
+        """Device bytes of ResidentPlan(spec, max_batch), from the host
+        (bf_plan_footprint plus the two staging buffers)."""
+        from . import plan_footprint
+        return (plan_footprint(spec.dim, spec.n, spec.phase, spec.params,
+                               q=spec.q, amplitude=spec.amplitude,
+                               precision=spec.precision, max_nvec=max_batch,
+                               op=spec.op) +
+                2 * max_batch * spec.N * 8)
 
     def run(self, reqs, stream):
         """Stage the requests' vectors, apply once, copy results out, all on
@@ -230,7 +257,8 @@ class Server:
         self.max_batch = max_batch
         self.max_inflight = max_inflight
         self.poll_s = poll_s
-        self.cache = PlanCache(hbm_budget_bytes, self._build)
+        self.cache = PlanCache(hbm_budget_bytes, self._build,
+                               self._footprint)
         self.batches: List[Tuple[str, int]] = []
         # device intervals of the batches: (start s, end s, plan, slot)
         self.intervals: List[Tuple[float, float, str, int]] = []
@@ -240,6 +268,9 @@ class Server:
 
     def _build(self, name):
         return ResidentPlan(self.specs[name], self.max_batch)
+
+    def _footprint(self, name):
+        return ResidentPlan.footprint_of(self.specs[name], self.max_batch)
 
     def run(self, requests: List[Request]):
         """Serve every request; fills done (seconds from the run's start),

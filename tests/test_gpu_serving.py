@@ -85,6 +85,8 @@ def test_batched_stream_matches_single_applies(budget_plans):
         for name in SPECS:
             rp = srv._build(name)
             sizes.append(rp.footprint)
+            # the host estimate admission uses is what the plan holds
+            assert srv._footprint(name) == rp.footprint, name
             rp.close()
         srv.cache.budget = max(sizes) + 1
     try:

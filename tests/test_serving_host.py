@@ -4,7 +4,8 @@ ordering, HBM-budget admission and LRU eviction, latency statistics."""
 import pytest
 import torch
 
-from paper_1803_04128_amd.serving import (AdmissionError, PlanCache, Request,
+from paper_1803_04128_amd.serving import (AdmissionError, PinnedError,
+                                          PlanCache, Request,
                                           Scheduler, summarize)
 from synthetic import serving_requests, SERVING_SHAPES
 
@@ -68,7 +69,8 @@ class _Fake:
 def test_cache_evicts_least_recently_used_and_refuses_oversized():
     closed = []
     sizes = {"a": 40, "b": 30, "c": 50, "huge": 101}
-    cache = PlanCache(100, lambda n: _Fake(n, sizes[n], closed))
+    cache = PlanCache(100, lambda n: _Fake(n, sizes[n], closed),
+                      lambda n: sizes[n])
     cache.get("a")
     cache.get("b")
     cache.get("a")                        # a is now the most recent
@@ -76,8 +78,9 @@ def test_cache_evicts_least_recently_used_and_refuses_oversized():
     assert closed == ["b"] and cache.names() == ["a", "c"]
     assert cache.resident_bytes == 90
     with pytest.raises(AdmissionError):
-        cache.get("huge")
-    assert closed[-1] == "huge" and cache.names() == ["a", "c"]
+        cache.get("huge")                 # refused before it is built
+    assert closed == ["b"] and cache.names() == ["a", "c"]
+    assert cache.builds == 3
     # pinned plans are never evicted
     with pytest.raises(AdmissionError):
         cache.get("b", pinned={"a", "c"})
@@ -135,3 +138,57 @@ def test_overlap_fraction():
     assert overlap_fraction([(0, 1, "a", 0), (2, 3, "b", 1)]) == 0.0
     # [0,2] and [1,3]: busy 3, two at once during [1,2]
     assert abs(overlap_fraction([(0, 2, "a", 0), (1, 3, "b", 1)]) - 1 / 3) < 1e-12
+
+
+class _Device:
+    """Counts the bytes fake plans hold, as device memory would."""
+
+    def __init__(self):
+        self.held = self.peak = 0
+        self.built = []
+
+    def build(self, name, size, fail=False):
+        if fail:
+            raise RuntimeError("[-2] hipMalloc failed")
+        self.built.append(name)
+        self.held += size
+        self.peak = max(self.peak, self.held)
+        dev = self
+
+        class _P:
+            footprint = size
+
+            def close(self):
+                dev.held -= size
+        return _P()
+
+
+def test_admission_never_exceeds_the_budget_and_builds_once():
+    dev = _Device()
+    sizes = {"a": 40, "b": 30, "c": 50, "d": 60, "e": 100}
+    cache = PlanCache(100, lambda n: dev.build(n, sizes[n]),
+                      lambda n: sizes[n])
+    for name in "abcadbeca":
+        cache.get(name)
+        assert dev.held == cache.resident_bytes <= 100
+    assert dev.peak <= 100
+    # one build per admission: a plan is rebuilt only after its eviction
+    assert dev.built.count("a") == 3 and cache.builds == len(dev.built)
+    # no room next to pinned plans: refused before building anything
+    n_built = len(dev.built)
+    cache.clear()
+    cache.get("c")
+    with pytest.raises(PinnedError):
+        cache.get("d", pinned={"c"})
+    assert len(dev.built) == n_built + 1 and dev.held == 50
+
+
+def test_failed_build_is_an_admission_error_of_that_plan():
+    dev = _Device()
+    sizes = {"a": 40, "bad": 30}
+    cache = PlanCache(100, lambda n: dev.build(n, sizes[n], fail=n == "bad"),
+                      lambda n: sizes[n])
+    cache.get("a")
+    with pytest.raises(AdmissionError, match="build failed"):
+        cache.get("bad")
+    assert cache.names() == ["a"] and dev.held == 40
