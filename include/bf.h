@@ -232,6 +232,54 @@ typedef struct bf_plan_info {
 
 int bf_query(bf_plan_t plan, bf_plan_info* info);
 
+/* ---- stored factors (diagnostics) ----------------------------------------
+ * The computed steps of a plan in apply order (bf_plan_info.n_steps of
+ * them): the xi levels, the switch, the x levels of Algorithm 4.1.  Each
+ * stored factor entry is exp(2 pi i [Phi(x_0, xi_0) - Phi(x_1, xi_1) -
+ * Phi(x_2, xi_2)]), rounded to complex64, over its phase terms (one to
+ * three), Phi the phase of the plan's operator (its arguments exchanged for
+ * BF_OP_T, negated for BF_OP_C).  Layouts, 0-based, R = 2^dim, pairs and
+ * boxes numbered as in Section 4 (2D box coordinates interleaved into
+ * Morton order, first coordinate on the odd bits):
+ *   xi step at level l: twiddles [u][i][c][s], u = a' R^(L-l) + b with a'
+ *     at level l-1 of the x tree, b at level L-l of the xi tree; the entry
+ *     W_{A,C}[s] (eq. (eqn:2) regrouped) for A = R a' + i, C = R b + c:
+ *     terms (c_A, xi_s^C) and, unless the step reads f, (c_P, xi_s^C);
+ *   switch at level h: blocks [p][t][s], p = a R^(L-h) + b:
+ *     S_{AB}[t][s] with terms (x_t^A, xi_s^B), then (c_A, xi_s^B) unless
+ *     the switch reads f, then (x_t^A, c_B) unless no x step follows;
+ *   x step at level l: twiddles [u][i][c][t] (u as above): T_{A,C}[t]
+ *     (eq. (eqn:3) regrouped), A = R a' + i, B = b, C = R b + c: terms
+ *     (x_t^A, c_C) and, unless the step writes lambda, (x_t^A, c_B).
+ * Points are the interpolation points of eqs. (eqn:gdA)/(eqn:gdB) (as
+ * bf_points gives them), centers the lower-middle index of a box.        */
+typedef struct bf_step_info {
+    int kind;             /* 0 xi level, 1 switch, 2 x level              */
+    int level;            /* tree level l of the step                     */
+    int r_in, r_out;      /* coefficients per input / output pair          */
+    int reads_f;          /* the step reads f (exact copy levels below)    */
+    int writes_lambda;    /* the step emits lambda (exact sums above)     */
+    int side_in, side_out;/* box side (per dimension) of the input-side
+                             and output-side point sets                   */
+    long long units;      /* units (xi, x) or pairs (switch)              */
+    long long tw_entries; /* stored twiddle entries (0: none)             */
+    long long S_entries;  /* stored switch block entries (0: none)        */
+} bf_step_info;
+
+int bf_step_query(bf_plan_t plan, int step, bf_step_info* info);
+
+/* Reads count stored entries of a step: which = 0 twiddles, 1 switch
+ * blocks; idx: host entry indices in the layout above.  Writes, per entry
+ * k, host arrays x[3 k + j], xi[3 k + j] (user indices of term j's x and xi
+ * arguments, -1 past the entry's terms) and values[2 k], values[2 k + 1]
+ * (the stored real and imaginary parts).  Synchronous; allocates a small
+ * device buffer.  For tests of the factor construction against an FP64
+ * evaluation of the same terms.  Returns BF_EINVAL for a bad step, an index
+ * out of range or factors the plan does not store.                       */
+int bf_factor_entries(bf_plan_t plan, int step, int which,
+                      const long long* idx, int count, long long* x,
+                      long long* xi, float* values);
+
 /* ---- execution form ------------------------------------------------------
  * How an apply is issued; every form computes the same Algorithm 4.1 and
  * agrees to FP32 rounding (the split precisions exist on BF_PATH_FUSED only).
@@ -338,16 +386,22 @@ int bf_graph_destroy(bf_graph_t graph);
  * 4096 launches are kept until the next bf_profile_read; later ones are not
  * timed, and launches inside a graph capture never are).  bf_profile(plan, 0)
  * stops recording.  bf_profile_read synchronises the recorded events and
- * returns one entry per kernel class: launches, total milliseconds, and the
+ * returns one entry per kernel class: launches, total milliseconds, the
  * algorithmic bytes (inputs, outputs and factors each counted once) and
- * flops of those launches; it then clears the records.  stats: caller
+ * flops of those launches, and the state bytes they spill through memory;
+ * it then clears the records.  stats: caller
  * array of cap entries; *count receives the number of classes.            */
 typedef struct bf_kernel_stat {
     char name[48];
     int launches;
     double total_ms;
-    double bytes;
-    double flops;
+    double bytes;        /* algorithmic: f, b_k, g, a_k and factors read
+                            or written by the launches, each once        */
+    double flops;        /* algorithmic (2D: one-dimension-at-a-time
+                            contraction of the Kronecker matrices)      */
+    double state_bytes;  /* the N r V state (and partial sums) read or
+                            written between launches: spills, not part
+                            of the algorithmic bytes                     */
 } bf_kernel_stat;
 
 int bf_profile(bf_plan_t plan, int enable);

@@ -139,6 +139,32 @@ class Plan:
         _lib.check(self._lib.bf_query(self._h, C.byref(inf)))
         return {k: getattr(inf, k) for k, _ in inf._fields_}
 
+    def steps(self):
+        """The computed steps (bf_step_query): kind, level, ranks, stored
+        entry counts."""
+        out = []
+        for k in range(self.info()["n_steps"]):
+            si = _lib.BfStepInfo()
+            _lib.check(self._lib.bf_step_query(self._h, k, C.byref(si)))
+            out.append({n: getattr(si, n) for n, _ in si._fields_})
+        return out
+
+    def factor_entries(self, step, which, idx):
+        """Stored factor entries of a step (bf_factor_entries): which is
+        "twiddle" or "switch"; returns (x [count][3], xi [count][3] user
+        indices of the phase terms, -1 past the last; complex64 values)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        n = idx.size
+        x = np.empty((n, 3), np.int64)
+        xi = np.empty((n, 3), np.int64)
+        v = np.empty(2 * n, np.float32)
+        lp = C.POINTER(C.c_longlong)
+        _lib.check(self._lib.bf_factor_entries(
+            self._h, int(step), {"twiddle": 0, "switch": 1}[which],
+            idx.ctypes.data_as(lp), n, x.ctypes.data_as(lp),
+            xi.ctypes.data_as(lp), v.ctypes.data_as(C.POINTER(C.c_float))))
+        return x, xi, v.view(np.complex64).copy()
+
     def workspace_bytes(self, nvec):
         v = C.c_size_t()
         _lib.check(self._lib.bf_workspace_bytes(self._h, int(nvec),
@@ -254,7 +280,8 @@ class Plan:
         for k in arr[:min(cnt.value, cap)]:
             out[k.name.decode()] = dict(launches=k.launches,
                                         total_ms=k.total_ms, bytes=k.bytes,
-                                        flops=k.flops)
+                                        flops=k.flops,
+                                        state_bytes=k.state_bytes)
         return out
 
     def close(self):

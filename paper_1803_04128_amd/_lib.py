@@ -42,10 +42,18 @@ class BfPlanInfo(C.Structure):
                 ("factor_stream_bytes", C.c_double), ("op", C.c_int)]
 
 
+class BfStepInfo(C.Structure):
+    _fields_ = [("kind", C.c_int), ("level", C.c_int), ("r_in", C.c_int),
+                ("r_out", C.c_int), ("reads_f", C.c_int),
+                ("writes_lambda", C.c_int), ("side_in", C.c_int),
+                ("side_out", C.c_int), ("units", C.c_longlong),
+                ("tw_entries", C.c_longlong), ("S_entries", C.c_longlong)]
+
+
 class BfKernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int),
                 ("total_ms", C.c_double), ("bytes", C.c_double),
-                ("flops", C.c_double)]
+                ("flops", C.c_double), ("state_bytes", C.c_double)]
 
 
 PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2, "per_step_mfma": 3}
@@ -63,7 +71,8 @@ class BfTuneEntry(C.Structure):
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
-EXPORTS = ["bf_plan", "bf_plan_op", "bf_plan_footprint", "bf_apply_chain",
+EXPORTS = ["bf_plan", "bf_plan_op", "bf_plan_footprint", "bf_step_query",
+           "bf_factor_entries", "bf_apply_chain",
            "bf_graph_create_chain", "bf_unwrap",
            "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
@@ -106,6 +115,11 @@ def load():
     lib.bf_plan_footprint.argtypes = [P(BfGrid), P(BfPhase),
                                       P(BfAmplitude), C.c_int, C.c_int,
                                       C.c_int, C.c_int, P(C.c_size_t)]
+    lib.bf_step_query.argtypes = [C.c_void_p, C.c_int, P(BfStepInfo)]
+    lib.bf_factor_entries.argtypes = [C.c_void_p, C.c_int, C.c_int,
+                                      P(C.c_longlong), C.c_int,
+                                      P(C.c_longlong), P(C.c_longlong),
+                                      P(C.c_float)]
     lib.bf_unwrap.argtypes = [P(C.c_double), C.c_longlong, C.c_double,
                               P(C.c_double), P(C.c_longlong), C.c_int,
                               P(C.c_int)]

@@ -478,6 +478,15 @@ int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
         if (int e = check_apply(plan, nvec, f, g)) return e;
         if (!ws) return fail(BF_EINVAL, "bf_apply_ws: NULL workspace");
         bfi::Plan& p = plan->p;
+        {
+            const size_t vb = (size_t)nvec * p.N * 8;
+            const char* w = (const char*)ws;
+            const char* fb = (const char*)f;
+            const char* gb = (const char*)g;
+            if ((w < fb + vb && fb < w + ws_bytes) ||
+                (w < gb + vb && gb < w + ws_bytes))
+                return fail(BF_EINVAL, "bf_apply_ws: workspace overlaps f or g");
+        }
         int cur = -1;
         if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
             return fail(BF_EINVAL, "bf_apply: plan belongs to another device");
@@ -619,6 +628,7 @@ int bf_profile_read(bf_plan_t plan, bf_kernel_stat* stats, int cap,
             k.total_ms += ms;
             k.bytes += r.bytes;
             k.flops += r.flops;
+            k.state_bytes += r.state_bytes;
         }
         int n = 0;
         for (const auto& k : acc) {
@@ -661,6 +671,55 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
         info->workspace_bytes = p.ws_bytes;
         info->flops_per_column = p.flops_per_column;
         info->factor_stream_bytes = p.factor_stream_bytes;
+        return BF_OK;
+    });
+}
+
+int bf_step_query(bf_plan_t plan, int step, bf_step_info* info) {
+    return guarded("bf_step_query", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        const bfi::Plan& p = plan->p;
+        if (!info || step < 0 || step >= (int)p.steps.size())
+            return fail(BF_EINVAL, "bf_step_query: bad step or NULL info");
+        const bfi::Step& s = p.steps[step];
+        std::memset(info, 0, sizeof(*info));
+        info->kind = s.kind;
+        info->level = s.level;
+        info->r_in = s.r_in;
+        info->r_out = s.r_out;
+        info->reads_f = s.reads_f ? 1 : 0;
+        info->writes_lambda = s.writes_lambda ? 1 : 0;
+        info->units = s.units;
+        info->tw_entries = s.tw ? (long long)s.tw_elems : 0;
+        info->S_entries = s.S ? (long long)s.S_elems : 0;
+        info->side_in = s.ax_in.side;
+        info->side_out = s.ax_out.side;
+        return BF_OK;
+    });
+}
+
+int bf_factor_entries(bf_plan_t plan, int step, int which,
+                      const long long* idx, int count, long long* x,
+                      long long* xi, float* values) {
+    return guarded("bf_factor_entries", [&]() -> int {
+        if (int e = check_plan(plan)) return e;
+        const bfi::Plan& p = plan->p;
+        if (step < 0 || step >= (int)p.steps.size() ||
+            (which != 0 && which != 1) || count < 1 || !idx || !x || !xi ||
+            !values)
+            return fail(BF_EINVAL, "bf_factor_entries: bad argument");
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+            return fail(BF_EINVAL,
+                        "bf_factor_entries: plan belongs to another device");
+        std::string err = bfi::read_factor_entries(p, step, which, idx,
+                                                   count, x, xi, values);
+        if (!err.empty())
+            return fail(err.find("range") != std::string::npos ||
+                                err.find("stores no") != std::string::npos
+                            ? BF_EINVAL
+                            : BF_EHIP,
+                        "bf_factor_entries: " + err);
         return BF_OK;
     });
 }

@@ -208,23 +208,14 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
     for (auto& s : p.steps) {
         StepArgs a = make_step_args(p, s, Vc, f, cur, bufs[which]);
         const bool otf = p.mfma && p.switch_otf && s.kind == STEP_SWITCH;
-        double bytes = (s.reads_f ? head_bytes : N * s.r_in * c8) +
-                       N * s.r_out * c8 + s.tw_elems * 8.0 +
-                       (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
-        double flops;
-        const char* name;
-        if (s.kind == STEP_XI) {
-            flops = (double)s.units * p.R * Vc *
-                    (p.R * s.r_in * 6.0 + (double)p.R * s.r_out * s.r_in * 4.0);
-            name = "xi_step_basic";
-        } else if (s.kind == STEP_X) {
-            flops = (double)s.units * p.R * Vc *
-                    ((double)p.R * s.r_out * s.r_in * 4.0 + p.R * s.r_out * 8.0);
-            name = "x_step_basic";
-        } else {
-            flops = N * Vc * s.r_out * (double)s.r_in * 8.0;
-            name = "switch_basic";
-        }
+        const double bytes = (s.reads_f ? head_bytes : 0.0) + s.tw_elems * 8.0 +
+                             (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
+        const double sbytes = (s.reads_f ? 0.0 : N * s.r_in * c8) +
+                              N * s.r_out * c8;
+        const double flops = step_alg_flops(p, s, Vc);
+        const char* name = s.kind == STEP_XI ? "xi_step_basic"
+                           : s.kind == STEP_X ? "x_step_basic"
+                                              : "switch_basic";
         ProfScope ps(p, st);
         if (p.mfma) {
             // contractions on MFMA (one launch per step)
@@ -245,7 +236,7 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return std::string("step launch: ") + hipGetErrorString(e);
-        ps.end(name, bytes, flops);
+        ps.end(name, bytes, flops, sbytes);
         cur = bufs[which];
         which ^= 1;
     }
@@ -256,9 +247,9 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return std::string("tail launch: ") + hipGetErrorString(e);
-    ps.end("tail_basic", N * t.r * c8 + N * nv * 8.0 +
-                             (p.has_amp ? N * p.r_amp * 8.0 : 0),
-           N * Vc * (double)t.nb * 2.0 + N * nv * p.r_amp * 8.0);
+    ps.end("tail_basic", N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0),
+           N * Vc * (double)t.nb * 2.0 + N * nv * p.r_amp * 8.0,
+           N * t.r * c8);
     return "";
 }
 

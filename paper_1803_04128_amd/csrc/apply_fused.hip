@@ -557,12 +557,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             a.lv[k].level = s.level;
             ++k;
             fbytes += s.tw_elems * 8.0 + s.mat_elems * 4.0;
-            if (s.kind == STEP_XI)
-                flops += (double)s.units * p.R * Vs *
-                         (p.R * s.r_in * 6.0 + (double)p.R * s.r_out * s.r_in * 4.0);
-            else
-                flops += (double)s.units * p.R * Vs *
-                         ((double)p.R * s.r_out * s.r_in * 4.0 + p.R * s.r_out * 8.0);
+            flops += step_alg_flops(p, s, Vs);
         }
         a.k = k;
         a.prec = p.precision;
@@ -588,7 +583,7 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         a.amp_a = p.has_amp ? p.a_dev : nullptr;
         a.tail_side = p.tail_side;
         a.tail_r = tr;
-        double in_bytes = 0, out_bytes = 0;
+        double in_bytes = 0, out_bytes = 0, state_bytes = 0;
         size_t lds = 0;
         if (is_xi) {
             a.la = p.steps[ps.first].level;
@@ -607,8 +602,9 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
             lds = (size_t)a.Gk * a.rmax * Vt * 8 +
                   (a.has_head ? (size_t)a.Gk * hr * Vt * 8 : 0);
             in_bytes = a.has_head ? N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0)
-                                  : N * a.lv[0].r_in * Vs * 8.0;
-            out_bytes = N * a.r_state_out * Vs * 8.0;
+                                  : 0.0;
+            state_bytes = (a.has_head ? 0.0 : N * a.lv[0].r_in * Vs * 8.0) +
+                          N * a.r_state_out * Vs * 8.0;
             if (a.has_switch) {
                 fbytes += swst.S_elems * 8.0;
                 flops += N * Vs * swst.r_out * (double)swst.r_in * 8.0;
@@ -633,9 +629,13 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
                   (a.has_tail ? (size_t)a.Gk * tr * Vt * 8 : 0) +
                   (head_sw ? (size_t)a.Gk * hr * Vt * 8 : 0);
             in_bytes = head_sw ? N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0)
-                               : N * (k > 0 ? a.lv[0].r_in : swst.r_out) * Vs * 8.0;
+                               : 0.0;
             out_bytes = a.has_tail ? N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0)
-                                   : N * a.r_state_out * Vs * 8.0;
+                                   : 0.0;
+            state_bytes = (head_sw ? 0.0
+                                   : N * (k > 0 ? a.lv[0].r_in : swst.r_out) *
+                                         Vs * 8.0) +
+                          (a.has_tail ? 0.0 : N * a.r_state_out * Vs * 8.0);
             if (head_sw) {
                 fbytes += swst.S_elems * 8.0;
                 flops += N * Vs * swst.r_out * (double)swst.r_in * 8.0;
@@ -736,13 +736,19 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return std::string("fused pass launch: ") + hipGetErrorString(e);
-        prof.end(name, in_bytes + out_bytes + fbytes, flops);
+        if (a.x_split > 1 && a.has_tail) {
+            // the tail pass writes x_split partial sums, summed into g below
+            out_bytes = 0.0;
+            state_bytes += a.x_split * (double)nv * N * 8.0;
+        }
+        prof.end(name, in_bytes + out_bytes + fbytes, flops, state_bytes);
         if (a.x_split > 1) {
             ProfScope ps2(p, st);
             std::string err = launch_sum_parts(a, nv, st);
             if (!err.empty()) return err;
-            ps2.end("sum_parts", (a.x_split + 1.0) * nv * N * 8.0,
-                    (double)(a.x_split - 1) * nv * N * 2.0);
+            ps2.end("sum_parts", nv * N * 8.0,
+                    (double)(a.x_split - 1) * nv * N * 2.0,
+                    a.x_split * (double)nv * N * 8.0);
         }
         cur = bufs[which];
         which ^= 1;

@@ -110,7 +110,7 @@ struct Pass {
 struct ProfRec {
     int cls;          // index into Profiler::names
     int ev0, ev1;     // indices into the event pool
-    double bytes, flops;
+    double bytes, flops, state_bytes;
 };
 
 struct Profiler {
@@ -170,7 +170,10 @@ struct ProfScope {
     hipStream_t st;
     int ev0 = -1;
     ProfScope(Plan& pl, hipStream_t s);
-    void end(const std::string& name, double bytes, double flops);
+    // bytes: algorithmic bytes (inputs f, b, outputs g, a and factors,
+    // each once); state_bytes: the state read or written between launches
+    void end(const std::string& name, double bytes, double flops,
+             double state_bytes = 0.0);
 };
 
 // geometry.cpp
@@ -186,6 +189,11 @@ std::string build_switch_blocks(Plan& p);
 // device bytes build_factors / build_switch_blocks allocate (host only)
 size_t factor_arena_bytes(Plan& p);
 size_t switch_block_bytes(const Plan& p);
+// diagnostic read-back of stored factor entries (which: 0 twiddles, 1 S)
+std::string read_factor_entries(const Plan& p, int step, int which,
+                                const long long* idx, int count,
+                                long long* x_out, long long* xi_out,
+                                float* val_out);
 // phase recovery (recovery.cpp); arguments checked by the C ABI
 int recover_phase(long long N, const long long* C, int nc, const long long* R,
                   int nr, int rank, double tau, bf_phase_sampler sample,
@@ -210,6 +218,37 @@ std::string check_config(Plan& p);   // "" when every pass fits
 int fused_tile_cols(const Plan& p, int Vs);
 int fused_pass_count(const Plan& p, int Vs);
 void init_kernel_attrs();
+
+// Algorithmic flops of one computed step for Vc columns: per unit and
+// column, the twiddle products (6 flops) and the real-matrix times complex
+// contractions (4 flops per multiply-add) of the regrouped eqs. (eqn:2) and
+// (eqn:3), the switch as a dense complex block (8 per multiply-add).  In 2D
+// the shared matrices are Kronecker products of 1D ones (a inputs, b
+// outputs per dimension), contracted one dimension at a time with the
+// first stage shared: a xi output child sums its two second-dimension
+// children before the first-dimension matrix (4 a^2 b + 2 a b^2 per child),
+// an x input child forms its second-dimension products once for both
+// first-dimension outputs (2 a^2 b + 4 a b^2 per child).
+inline double step_alg_flops(int dim, int kind, long long units, int r_in,
+                             int r_out, int a1, int b1, double Vc) {
+    const int R = 1 << dim;
+    const double U = (double)units * Vc;
+    if (kind == STEP_SWITCH) return U * r_out * (double)r_in * 8.0;
+    if (dim == 1) {
+        if (kind == STEP_XI)
+            return U * R * (R * r_in * 6.0 + (double)R * r_out * r_in * 4.0);
+        return U * R * ((double)R * r_out * r_in * 4.0 + R * r_out * 8.0);
+    }
+    const double a = a1, b = b1;
+    if (kind == STEP_XI)
+        return U * (R * R * r_in * 6.0 + R * (4 * a * a * b + 2 * a * b * b) * 4.0);
+    return U * (R * (2 * a * a * b + 4 * a * b * b) * 4.0 + R * R * r_out * 8.0);
+}
+
+inline double step_alg_flops(const Plan& p, const Step& s, double Vc) {
+    return step_alg_flops(p.dim, s.kind, s.units, s.r_in, s.r_out,
+                          s.ax_in.r1, s.ax_out.r1, Vc);
+}
 
 // tiny helpers
 inline int ilog2(long long v) {

@@ -14,11 +14,13 @@ ProfScope::ProfScope(Plan& pl, hipStream_t s) : p(pl), st(s) {
     if (hipEventRecord(p.prof.pool[ev0], st) != hipSuccess) ev0 = -1;
 }
 
-void ProfScope::end(const std::string& name, double bytes, double flops) {
+void ProfScope::end(const std::string& name, double bytes, double flops,
+                    double state_bytes) {
     if (ev0 < 0) return;
     const int ev1 = p.prof.used++;
     if (hipEventRecord(p.prof.pool[ev1], st) != hipSuccess) return;
-    p.prof.recs.push_back({p.prof.cls_of(name), ev0, ev1, bytes, flops});
+    p.prof.recs.push_back(
+        {p.prof.cls_of(name), ev0, ev1, bytes, flops, state_bytes});
 }
 
 std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
@@ -49,6 +51,17 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     if (reads_stored_switch(p) && !p.S_arena) {
         for (const auto& s : p.steps)
             if (s.S_elems) return "switch blocks are not stored";
+    }
+    if (p.fused) {
+        // every width this apply launches (the chunk and the tail) is
+        // planned before the first launch, so a failure leaves g untouched
+        const int widths[2] = {chunk, nvec % chunk};
+        for (int nv : widths) {
+            if (nv < 1) continue;
+            std::string err = run_fused(p, nv, nullptr, nullptr, nullptr,
+                                        nullptr, nullptr, true);
+            if (!err.empty()) return err;
+        }
     }
     const float2* f = (const float2*)fv;
     float2* g = (float2*)gv;

@@ -29,85 +29,202 @@ struct TwArgs {
 
 constexpr int kFactorBlock = 256;
 
+#define HIPCHK(x)                                                       \
+    do {                                                                \
+        hipError_t e_ = (x);                                            \
+        if (e_ != hipSuccess)                                           \
+            return std::string(#x ": ") + hipGetErrorString(e_);        \
+    } while (0)
+
+// The phase terms of one stored factor entry: the entry is
+// exp(2 pi i [Phi(ix_0, jx_0) - Phi(ix_1, jx_1) - Phi(ix_2, jx_2)]) over the
+// first `count` terms (grid coordinates; ix on the output tree, jx on the
+// input tree, as phase_value takes them).  The construction kernels and the
+// diagnostic read-back (factor_entries) decode entries with these functions.
+struct Terms {
+    int count;
+    int ix[3][2];
+    int jx[3][2];
+};
+
 // W (or D+ when the step reads f): [u][i][c][s]
-__global__ void xi_twiddles(TwArgs a) {
+__device__ __forceinline__ Terms xi_terms(const TwArgs& a, long long idx) {
     const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
     const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
     const int shiftB = dim * (a.L - a.level);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
-        int s = (int)(idx % r_in);
-        long long rest = idx / r_in;
-        int c = (int)(rest % R);
-        rest /= R;
-        int i = (int)(rest % R);
-        long long u = rest / R;
-        long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
-        int Ac[2], Pc[2], Cc[2], xi[2], cA[2], cP[2];
-        box_coords(ap * R + i, dim, Ac);
-        box_coords(ap, dim, Pc);
-        box_coords(b * R + c, dim, Cc);
-        point_grid(Cc, a.ax_in, s, dim, xi);
-        center_grid(Ac, n >> a.level, dim, cA);
-        center_grid(Pc, n >> (a.level - 1), dim, cP);
-        double v = phase_value(a.P, cA, xi);
-        if (!a.reads_f) v -= phase_value(a.P, cP, xi);
-        a.out[idx] = expi_frac(v);
+    int s = (int)(idx % r_in);
+    long long rest = idx / r_in;
+    int c = (int)(rest % R);
+    rest /= R;
+    int i = (int)(rest % R);
+    long long u = rest / R;
+    long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    int Ac[2], Pc[2], Cc[2];
+    Terms T;
+    box_coords(ap * R + i, dim, Ac);
+    box_coords(ap, dim, Pc);
+    box_coords(b * R + c, dim, Cc);
+    point_grid(Cc, a.ax_in, s, dim, T.jx[0]);
+    center_grid(Ac, n >> a.level, dim, T.ix[0]);
+    T.count = 1;
+    if (!a.reads_f) {
+        center_grid(Pc, n >> (a.level - 1), dim, T.ix[1]);
+        for (int d = 0; d < dim; ++d) T.jx[1][d] = T.jx[0][d];
+        T.count = 2;
     }
+    return T;
 }
 
 // T (or E+ on the last x step): [u][i][c][t]
-__global__ void x_twiddles(TwArgs a) {
+__device__ __forceinline__ Terms x_terms(const TwArgs& a, long long idx) {
     const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
     const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
     const int shiftB = dim * (a.L - a.level);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
-        int t = (int)(idx % r_out);
-        long long rest = idx / r_out;
-        int c = (int)(rest % R);
-        rest /= R;
-        int i = (int)(rest % R);
-        long long u = rest / R;
-        long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
-        int Ac[2], Bc[2], Cc[2], x[2], cB[2], cC[2];
-        box_coords(ap * R + i, dim, Ac);
-        box_coords(b, dim, Bc);
-        box_coords(b * R + c, dim, Cc);
-        point_grid(Ac, a.ax_out, t, dim, x);
-        center_grid(Cc, n >> (a.L - a.level + 1), dim, cC);
-        center_grid(Bc, n >> (a.L - a.level), dim, cB);
-        double v = phase_value(a.P, x, cC);
-        if (!a.writes_lambda) v -= phase_value(a.P, x, cB);
-        a.out[idx] = expi_frac(v);
+    int t = (int)(idx % r_out);
+    long long rest = idx / r_out;
+    int c = (int)(rest % R);
+    rest /= R;
+    int i = (int)(rest % R);
+    long long u = rest / R;
+    long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    int Ac[2], Bc[2], Cc[2];
+    Terms T;
+    box_coords(ap * R + i, dim, Ac);
+    box_coords(b, dim, Bc);
+    box_coords(b * R + c, dim, Cc);
+    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
+    center_grid(Cc, n >> (a.L - a.level + 1), dim, T.jx[0]);
+    T.count = 1;
+    if (!a.writes_lambda) {
+        for (int d = 0; d < dim; ++d) T.ix[1][d] = T.ix[0][d];
+        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[1]);
+        T.count = 2;
     }
+    return T;
 }
 
 // S: [p][t][s]
-__global__ void switch_blocks(TwArgs a) {
+__device__ __forceinline__ Terms switch_terms(const TwArgs& a,
+                                              long long idx) {
     const int dim = a.P.dim, n = a.P.n;
     const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
     const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
     const int shiftB = dim * (a.L - a.level);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-         idx < a.total; idx += (long long)gridDim.x * blockDim.x) {
-        int s = (int)(idx % r_in);
-        long long rest = idx / r_in;
-        int t = (int)(rest % r_out);
-        long long p = rest / r_out;
-        long long am = p >> shiftB, bm = p & ((1LL << shiftB) - 1);
-        int Ac[2], Bc[2], x[2], xi[2], cA[2], cB[2];
-        box_coords(am, dim, Ac);
-        box_coords(bm, dim, Bc);
-        point_grid(Ac, a.ax_out, t, dim, x);
-        point_grid(Bc, a.ax_in, s, dim, xi);
-        center_grid(Ac, n >> a.level, dim, cA);
-        center_grid(Bc, n >> (a.L - a.level), dim, cB);
-        double v = phase_value(a.P, x, xi);
-        if (!a.reads_f) v -= phase_value(a.P, cA, xi);
-        if (!a.writes_lambda) v -= phase_value(a.P, x, cB);
-        a.out[idx] = expi_frac(v);
+    int s = (int)(idx % r_in);
+    long long rest = idx / r_in;
+    int t = (int)(rest % r_out);
+    long long p = rest / r_out;
+    long long am = p >> shiftB, bm = p & ((1LL << shiftB) - 1);
+    int Ac[2], Bc[2];
+    Terms T;
+    box_coords(am, dim, Ac);
+    box_coords(bm, dim, Bc);
+    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
+    point_grid(Bc, a.ax_in, s, dim, T.jx[0]);
+    T.count = 1;
+    if (!a.reads_f) {
+        center_grid(Ac, n >> a.level, dim, T.ix[T.count]);
+        for (int d = 0; d < dim; ++d) T.jx[T.count][d] = T.jx[0][d];
+        ++T.count;
     }
+    if (!a.writes_lambda) {
+        for (int d = 0; d < dim; ++d) T.ix[T.count][d] = T.ix[0][d];
+        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[T.count]);
+        ++T.count;
+    }
+    return T;
+}
+
+// The entry's phase: FP64 terms, differences before the reduction modulo 1.
+__device__ __forceinline__ double terms_phase(const PhaseSpec& P,
+                                              const Terms& T) {
+    double v = phase_value(P, T.ix[0], T.jx[0]);
+    for (int k = 1; k < T.count; ++k) v -= phase_value(P, T.ix[k], T.jx[k]);
+    return v;
+}
+
+__global__ void xi_twiddles(TwArgs a) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x)
+        a.out[idx] = expi_frac(terms_phase(a.P, xi_terms(a, idx)));
+}
+
+__global__ void x_twiddles(TwArgs a) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x)
+        a.out[idx] = expi_frac(terms_phase(a.P, x_terms(a, idx)));
+}
+
+__global__ void switch_blocks(TwArgs a) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         idx < a.total; idx += (long long)gridDim.x * blockDim.x)
+        a.out[idx] = expi_frac(terms_phase(a.P, switch_terms(a, idx)));
+}
+
+// Diagnostic read-back of stored entries: for each requested entry index,
+// the user indices of its phase terms (-1 past the term count) and the
+// stored value.  kind: STEP_XI / STEP_X (twiddles) or STEP_SWITCH (blocks).
+__global__ void factor_entries(TwArgs a, int kind, const float2* src,
+                               const long long* idx, int count,
+                               long long* xo, long long* jo, float2* val) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const long long e = idx[k];
+    const Terms T = kind == STEP_XI ? xi_terms(a, e)
+                    : kind == STEP_X ? x_terms(a, e)
+                                     : switch_terms(a, e);
+    for (int t = 0; t < 3; ++t) {
+        xo[3 * k + t] = t < T.count ? user_index(T.ix[t], a.P.dim, a.P.n) : -1;
+        jo[3 * k + t] = t < T.count ? user_index(T.jx[t], a.P.dim, a.P.n) : -1;
+    }
+    val[k] = src[e];
+}
+
+std::string read_factor_entries(const Plan& p, int step, int which,
+                                const long long* idx, int count,
+                                long long* x_out, long long* xi_out,
+                                float* val_out) {
+    const Step& s = p.steps[step];
+    const float2* src = which == 0 ? s.tw : s.S;
+    const size_t total = which == 0 ? s.tw_elems : s.S_elems;
+    if (!src || total == 0)
+        return which == 0 ? "the step stores no twiddles"
+                          : "the step stores no switch blocks";
+    for (int k = 0; k < count; ++k)
+        if (idx[k] < 0 || (size_t)idx[k] >= total)
+            return "entry index out of range";
+    TwArgs t{};
+    t.P = p.phase;
+    t.L = p.L;
+    t.ax_in = s.ax_in;
+    t.ax_out = s.ax_out;
+    t.level = s.level;
+    t.reads_f = s.reads_f;
+    t.writes_lambda = s.writes_lambda;
+    void* mem = nullptr;
+    const size_t bi = (size_t)count * sizeof(long long);
+    HIPCHK(hipMalloc(&mem, bi * 7 + (size_t)count * sizeof(float2)));
+    long long* di = (long long*)mem;
+    long long* dx = di + count;
+    long long* dj = dx + 3 * (size_t)count;
+    float2* dv = (float2*)(dj + 3 * (size_t)count);
+    std::string err;
+    hipError_t e = hipMemcpy(di, idx, bi, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(factor_entries, dim3((count + 255) / 256),
+                           dim3(256), 0, 0, t, s.kind, src, di, count, dx, dj,
+                           dv);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(x_out, dx, 3 * bi, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(xi_out, dj, 3 * bi, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(val_out, dv, (size_t)count * sizeof(float2),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) err = std::string("factor read-back: ") + hipGetErrorString(e);
+    (void)hipFree(mem);
+    return err;
 }
 
 // complex128 host amplitude factors -> complex64 device (conjugated for
@@ -153,12 +270,6 @@ static int grid_for(long long total) {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-#define HIPCHK(x)                                                       \
-    do {                                                                \
-        hipError_t e_ = (x);                                            \
-        if (e_ != hipSuccess)                                           \
-            return std::string(#x ": ") + hipGetErrorString(e_);        \
-    } while (0)
 
 // Offsets of every factor array inside the plan arena.
 struct ArenaLayout {

@@ -199,18 +199,8 @@ std::string build_schedule(Plan& p) {
     // algorithmic work per apply column and factor bytes streamed per apply
     double fl = 0, by = 0;
     for (auto& s : p.steps) {
-        if (s.kind == STEP_XI) {
-            fl += (double)s.units * R *
-                  (R * s.r_in * 6.0 + (double)R * s.r_out * s.r_in * 4.0);
-            by += s.tw_elems * 8.0;
-        } else if (s.kind == STEP_X) {
-            fl += (double)s.units * R *
-                  ((double)R * s.r_out * s.r_in * 4.0 + R * s.r_out * 8.0);
-            by += s.tw_elems * 8.0;
-        } else {
-            fl += (double)s.units * s.r_out * s.r_in * 8.0;
-            by += s.S_elems * 8.0;
-        }
+        fl += step_alg_flops(p, s, 1.0);
+        by += s.kind == STEP_SWITCH ? s.S_elems * 8.0 : s.tw_elems * 8.0;
         by += s.mat_elems * 4.0;
     }
     const double nb = std::pow((double)R, p.L - p.lend);

@@ -73,6 +73,10 @@ CONFIGS = {
     # 2D generalized Radon FIO: n = 256 (N = 65536), q = 7, 16 vectors.
     "radon2d_n256": Workload("radon2d_n256", 2, 256, "radon2d", "one", 1, 7,
                              16, seed=2, rows=1024, row_seed=102),
+    # 2D generalized Radon FIO at n = 512 (N = 262144), the largest 2D grid
+    # of the serving mix: a parity case (16 vectors).
+    "radon2d_n512": Workload("radon2d_n512", 2, 512, "radon2d", "one", 1, 7,
+                             16, seed=5, rows=1024, row_seed=105),
     # precision sweep: N = 2^20, r = 4, q = 10, 256 vectors.
     "fio1d_n1048576_sweep": Workload("fio1d_n1048576_sweep", 1, 1 << 20,
                                      "fio1d", "sincos", 4, 10, 256, seed=3,
