@@ -183,6 +183,22 @@ int bf_plan_footprint(const bf_grid* grid, const bf_phase* phase,
  * pointers.                                                               */
 int bf_apply(bf_plan_t plan, int nvec, const void* f, void* g, void* stream);
 
+/* Allocation-free apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): as bf_apply, with the workspace taken from a static device
+ * buffer of BF_STATIC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends (its address is recorded once per device
+ * when the first plan is built there).  The call allocates nothing; vectors
+ * are processed in chunks that fit the buffer.  All calls on one GPU share
+ * the buffer and leave their intermediate state in it: calls that overlap
+ * in time on one GPU (other streams, other threads or plans) race and must
+ * be serialized by the caller.  Returns BF_EINVAL when one vector's
+ * workspace (bf_workspace_bytes(plan, 1)) exceeds the buffer, otherwise as
+ * bf_apply.                                                               */
+#define BF_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int bf_apply_static(bf_plan_t plan, int nvec, const void* f, void* g,
+                    void* stream);
+
 /* Chained applies: g = P_{count-1}( ... P_1(P_0 f)) for the plans
  * plans[0 .. count-1] (the same plan may appear more than once), e.g. the
  * composition of two FIOs of eq. (eq:example4): the FIO, then the Fourier

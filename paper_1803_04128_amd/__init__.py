@@ -227,6 +227,19 @@ class Plan:
                 workspace.numel() * workspace.element_size(), st))
         return out.reshape(-1) if squeeze else out
 
+    def apply_static(self, f, out=None, stream=None):
+        """As apply(), through the allocation-free entry point
+        (bf_apply_static): the workspace is the library's static device
+        buffer of each GPU, shared by every such call on that GPU, so calls
+        that overlap in time on one GPU race.  out is allocated by torch
+        when not given (pass it for an allocation-free call)."""
+        squeeze = f.dim() == 1
+        f2, out, nvec = self._args(f, out)
+        _lib.check(self._lib.bf_apply_static(
+            self._h, nvec, C.c_void_p(f2.data_ptr()),
+            C.c_void_p(out.data_ptr()), self._stream(stream)))
+        return out.reshape(-1) if squeeze else out
+
     def config(self):
         """Execution form: {"path", "tile_cols", "tile_cols_used",
         "switch_otf"}."""

@@ -56,6 +56,9 @@ class BfKernelStat(C.Structure):
                 ("flops", C.c_double), ("state_bytes", C.c_double)]
 
 
+# BF_STATIC_SCRATCH_BYTES of include/bf.h
+STATIC_SCRATCH_BYTES = 256 << 20
+
 PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2, "per_step_mfma": 3}
 
 
@@ -72,7 +75,7 @@ SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
 EXPORTS = ["bf_plan", "bf_plan_op", "bf_plan_footprint", "bf_step_query",
-           "bf_factor_entries", "bf_apply_chain",
+           "bf_factor_entries", "bf_apply_static", "bf_apply_chain",
            "bf_graph_create_chain", "bf_unwrap",
            "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
@@ -142,6 +145,8 @@ def load():
                                    C.c_void_p]
     lib.bf_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                              C.c_void_p]
+    lib.bf_apply_static.argtypes = [C.c_void_p, C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]
     lib.bf_workspace_bytes.argtypes = [C.c_void_p, C.c_int, P(C.c_size_t)]
     lib.bf_apply_ws.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_size_t, C.c_void_p]

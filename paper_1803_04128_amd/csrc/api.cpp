@@ -360,6 +360,13 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
         return fail(BF_EHIP, "bf_plan: no HIP device");
     }
     {
+        // set-up of bf_apply_static's scratch on this device (a failure is
+        // reported by bf_apply_static, which retries)
+        void* unused = nullptr;
+        (void)bfi::static_scratch(p.device, &unused);
+        (void)hipGetLastError();
+    }
+    {
         // once per process: plans built on several host threads at once do
         // not race on the kernels' attribute flags (launches only read them)
         static std::once_flag attrs_once;
@@ -493,6 +500,33 @@ int bf_apply_ws(bf_plan_t plan, int nvec, const void* f, void* g, void* ws,
         std::string err = bfi::launch_apply(p, nvec, f, g, ws, ws_bytes,
                                             (hipStream_t)stream);
         if (!err.empty()) return fail(BF_EHIP, "bf_apply: " + err);
+        return BF_OK;
+    });
+}
+
+int bf_apply_static(bf_plan_t plan, int nvec, const void* f, void* g,
+                    void* stream) {
+    return guarded("bf_apply_static", [&]() -> int {
+        if (int e = check_apply(plan, nvec, f, g)) return e;
+        bfi::Plan& p = plan->p;
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
+            return fail(BF_EINVAL,
+                        "bf_apply_static: plan belongs to another device");
+        const size_t need = bfi::workspace_bytes(p, 1);
+        if (need > bfi::kStaticScratchBytes)
+            return fail(BF_EINVAL,
+                        "bf_apply_static: the plan needs " +
+                            std::to_string(need) +
+                            " bytes of workspace per vector, the static "
+                            "scratch holds " +
+                            std::to_string(bfi::kStaticScratchBytes));
+        void* ws = nullptr;
+        std::string err = bfi::static_scratch(p.device, &ws);
+        if (!err.empty()) return fail(BF_EHIP, "bf_apply_static: " + err);
+        err = bfi::launch_apply(p, nvec, f, g, ws, bfi::kStaticScratchBytes,
+                                (hipStream_t)stream);
+        if (!err.empty()) return fail(BF_EHIP, "bf_apply_static: " + err);
         return BF_OK;
     });
 }

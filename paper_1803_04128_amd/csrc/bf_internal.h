@@ -209,6 +209,10 @@ const char* recovery_error();
 inline bool reads_stored_switch(const Plan& p) {
     return !(p.switch_otf && !p.fused && p.mfma);
 }
+// bytes of the static scratch workspace of bf_apply_static (per device)
+constexpr size_t kStaticScratchBytes = BF_STATIC_SCRATCH_BYTES;
+// its device address on `device` (current), recorded on first use
+std::string static_scratch(int device, void** out);
 // apply.hip
 std::string launch_apply(Plan& p, int nvec, const void* f, void* g, void* ws,
                          size_t ws_bytes, hipStream_t stream);

@@ -1,10 +1,45 @@
 // Apply dispatch: vector chunking over the workspace and the choice between
-// the per-step launches and the level-fused passes.
+// the per-step launches and the level-fused passes; the static scratch
+// workspace of the allocation-free apply.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "apply_common.h"
 
 namespace bfi {
+
+// Workspace of bf_apply_static: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in symbol):
+// it uses the device address hipGetSymbolAddress returns for the current
+// device, recorded once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address per device ordinal
+}  // namespace
+
+std::string static_scratch(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0) return "bad device";
+    if ((size_t)device >= g_scratch_ptr.size())
+        g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device)
+            return "the scratch's device is not current";
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return std::string("hipGetSymbolAddress(scratch): ") +
+                   hipGetErrorString(e);
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return "";
+}
 
 ProfScope::ProfScope(Plan& pl, hipStream_t s) : p(pl), st(s) {
     if (!p.prof.on || p.capturing ||

@@ -85,24 +85,29 @@ CONFIGS = {
 
 
 # Serving mix: plan shapes (dim, n, phase, amplitude, r, q) and their weights
-# in the request stream; smaller transforms are requested more often.
-SERVING_SHAPES = (
-    ((1, 1 << 12, "fio1d", "one", 1, 8), 6),
-    ((1, 1 << 12, "fio1d", "sincos", 4, 8), 4),
-    ((1, 1 << 14, "fio1d", "one", 1, 8), 5),
-    ((1, 1 << 14, "fio1d", "sincos", 2, 8), 4),
-    ((1, 1 << 16, "fio1d", "one", 1, 8), 4),
-    ((1, 1 << 16, "fio1d", "sincos", 4, 8), 3),
-    ((1, 1 << 18, "fio1d", "one", 1, 8), 2),
-    ((1, 1 << 18, "fio1d", "sincos", 2, 8), 2),
-    ((1, 1 << 20, "fio1d", "one", 1, 8), 1),
-    ((1, 1 << 20, "fio1d", "sincos", 2, 8), 1),
-    ((2, 64, "radon2d", "one", 1, 7), 3),
-    ((2, 128, "radon2d", "one", 1, 7), 2),
-    ((2, 256, "radon2d", "one", 1, 7), 1),
-)
-SERVING_NVEC = (1, 2, 4, 8, 16, 32)
-SERVING_NVEC_WEIGHTS = (8, 6, 4, 3, 2, 1)
+# in the request stream.  1D FIO plans at every N = 2^12 ... 2^20 (odd and
+# even depths) and 2D Radon plans at n = 64 ... 512, each with amplitude
+# rank r = 1, 2 or 4; smaller transforms are requested more often (weight
+# halving per doubling of N).
+def _serving_shapes():
+    shapes = []
+    for k in range(12, 21):
+        w = max(1, 2 ** (20 - k) // 16)
+        for r in (1, 2, 4):
+            shapes.append(((1, 1 << k, "fio1d", "one" if r == 1 else "sincos",
+                            r, 8), w))
+    for n in (64, 128, 256, 512):
+        w = {64: 8, 128: 4, 256: 2, 512: 1}[n]
+        for r in (1, 2, 4):
+            shapes.append(((2, n, "radon2d", "one" if r == 1 else "sincos",
+                            r, 7), w))
+    return tuple(shapes)
+
+
+SERVING_SHAPES = _serving_shapes()
+# vectors per request: 1 ... 32, weights proportional to 1 / nvec
+SERVING_NVEC = tuple(range(1, 33))
+SERVING_NVEC_WEIGHTS = tuple(1.0 / v for v in SERVING_NVEC)
 
 
 def serving_requests(count, seed, rate=None, shapes=SERVING_SHAPES):

@@ -53,7 +53,8 @@ def _gpu(name, precision, picks, nvec=None):
     import paper_1803_04128_amd as bfm
     w = CONFIGS[name]
     nvec = nvec or w.nvec
-    f32 = gaussian_vectors(w.N, nvec, w.seed).astype(np.complex64)
+    # the first nvec vectors of the workload's seeded batch
+    f32 = gaussian_vectors(w.N, w.nvec, w.seed)[:nvec].astype(np.complex64)
     ab = None
     if w.amplitude != "one":
         ab = amplitude_factors(w.amplitude, w.dim, w.n, w.r, w.amp_seed)

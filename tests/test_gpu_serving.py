@@ -19,6 +19,8 @@ SPECS = {
     "radon32": (2, 32, "radon2d", 7, None, "N"),
     "fio4096_adjoint": (1, 4096, "fio1d", 8, None, "H"),
     "lowrank2048": (1, 2048, "lowrank", 8, None, "N"),
+    "fio8192_odd_r2": (1, 8192, "fio1d", 8, ("sincos", 2), "N"),   # L = 13
+    "radon64_r2": (2, 64, "radon2d", 7, ("sincos", 2), "N"),
 }
 MAX_BATCH = 8
 
@@ -126,6 +128,18 @@ def test_batched_stream_matches_single_applies(budget_plans):
     f = r.f.cpu().numpy().astype(np.complex128)
     g = butterfly_apply(1, 2048, "lowrank", _spec("lowrank2048").params, 8, f)
     assert np.max(rel(r.out.cpu().numpy().astype(np.complex128), g)) < 1e-5
+    # an odd-depth 1D plan (h = floor(L / 2)) and a 2D plan with an r = 2
+    # amplitude against the oracle
+    for name in ("fio8192_odd_r2", "radon64_r2"):
+        r = next(x for x in done if x.plan == name)
+        dim, n, kind, q, _, _ = SPECS[name]
+        s = _spec(name)
+        f = r.f.cpu().numpy().astype(np.complex128)
+        g = butterfly_matvec(dim, n, kind, PHASE_PARAMS[kind], q,
+                             s.amplitude[0], s.amplitude[1], f)
+        e = np.max(rel(r.out.cpu().numpy().astype(np.complex128), g))
+        log(f"  {name}: served result vs oracle butterfly {e:.3e}")
+        assert e < 1e-5
 
 
 def test_plan_over_budget_fails_its_requests_only():

@@ -152,30 +152,24 @@ def test_otf_autotune_candidate_and_graph():
             gr.close()
 
 
+@pytest.mark.fullsize_oracle
+@pytest.mark.timeout(1800)
 def test_otf_at_full_size_2d():
-    # the 2D Radon workload (n = 256, 16 vectors) at full size: sampled rows
-    # against the stored oracle butterfly rows
+    # the 2D Radon workload (n = 256, 16 vectors) at full size: every entry
+    # of vectors 0 and 15 against the oracle's butterfly
+    import _fullsize_oracle as fo
     bfm = _bfm()
     name = "radon2d_n256"
     w = CONFIGS[name]
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        "golden", "fullsize_oracle.json")
-    with open(path) as fh:
-        ref = json.load(fh)[name]
-    rows = np.asarray(ref["rows"], np.int64)
     log(f"case otf full size {name}")
     f32 = gaussian_vectors(w.N, w.nvec, w.seed).astype(np.complex64)
     with bfm.Plan(w.dim, w.n, w.phase_kind, w.phase_params, q=w.q,
                   max_nvec=w.nvec) as pl:
         pl.set_config("per_step_mfma", switch_otf=True)
         g = pl.apply(_to_dev(f32))
-        import torch
-        idx = torch.as_tensor(rows, device="cuda")
-        for v in ref["vectors"]:
-            if str(v) not in ref["bf"]:
-                continue
-            bf = np.asarray(ref["bf"][str(v)], np.float64)
-            bf = bf[:, 0] + 1j * bf[:, 1]
-            e = rel(_host(g[v][idx]), bf)[0]
-            log(f"  vector {v}: vs oracle butterfly {e:.3e}")
+        for v in fo.JOBS[name]:
+            bf = fo.result(name, v, log)
+            e = rel(_host(g[v]), bf)[0]
+            log(f"  vector {v}: all {bf.size} entries vs oracle butterfly "
+                f"{e:.3e}")
             assert e < TOL

@@ -116,7 +116,16 @@ def test_request_stream_is_seeded_and_weighted():
     assert 15 < t[-1] < 25                 # about 2000 / 100 s
     kinds = [x[1] for x in a]
     assert set(kinds) == set(range(len(SERVING_SHAPES)))
-    assert kinds.count(0) > kinds.count(8)  # weights 6 vs 1
+    assert kinds.count(0) > kinds.count(26)  # N = 2^12 vs 2^20: 16 vs 1
+    # the mix: every 1D depth 12..20 (odd ones too), 2D n = 64..512, r in
+    # {1, 2, 4} for both, 1..32 vectors per request
+    shapes = [SERVING_SHAPES[k][0] for k in set(kinds)]
+    assert {n for d, n, *_ in shapes if d == 1} == {1 << k
+                                                     for k in range(12, 21)}
+    assert {n for d, n, *_ in shapes if d == 2} == {64, 128, 256, 512}
+    for dim in (1, 2):
+        assert {s[4] for s in shapes if s[0] == dim} == {1, 2, 4}
+    assert {x[2] for x in a} == set(range(1, 33))
 
 
 def test_busy_plans_are_skipped_without_losing_order():
