@@ -244,9 +244,76 @@ typedef struct bf_plan_info {
     double flops_per_column;  /* algorithmic flops per apply column       */
     double factor_stream_bytes; /* factor bytes read per apply            */
     int op;                /* BF_OP_* the plan applies                    */
+    int method;            /* 0 butterfly (Section 4), 1 NUFFT by
+                              dimension lifting (Section 3)              */
 } bf_plan_info;
 
 int bf_query(bf_plan_t plan, bf_plan_info* info);
+
+/* ---- NUFFT by dimension lifting (Section 3) ------------------------------
+ * For a kernel whose phase and amplitude are given by real low-rank factors
+ * on an N x N grid (1D x and xi), Phi(x_i, xi_j) ~ sum_c U1[i][c] V1[j][c]
+ * (rank r1) and alpha(x_i, xi_j) ~ sum_c U2[i][c] V2[j][c] (rank r2), the
+ * framework applies K either by the butterfly (bf_plan with
+ * BF_PHASE_LOWRANK) or, when the phase minus its leading rank-r part leaves
+ * a kernel of small numerical rank, as r_eps r-dimensional type-3 NUFFTs
+ * (eq. (eqn:tg3)):
+ *   g(x_i) ~ sum_k a_k(x_i) sum_j exp(2 pi i P_i . Q_j) b_k(xi_j) f(xi_j).
+ *
+ * bf_lift_decide: Algorithm 6 (host, FP64, synchronous, no device use).
+ *   1. P Q^T = the rank-r truncated SVD of U1 V1^T (P scaled by the
+ *      singular values), by a randomized range finder with the caller's
+ *      test matrix omega [N][omega_cols], r1 < omega_cols <= 64;
+ *   2. the residual Kres = (U2 V2^T) . exp(2 pi i (U1 V1^T - P Q^T)) at the
+ *      columns test_cols[0 .. n_test) (the method's random sample, r_eps q
+ *      of them for an oversampling q), and its numerical rank n: the
+ *      diagonal entries of R in its pivoted QR above |R(1,1)| eps;
+ *   3. y = 1 when n <= r_eps (the printed test compares n with r and
+ *      samples r q columns; it is read with r_eps, the rank of the sum in
+ *      eq. (eqn:tg3), since r = 1 could otherwise never pass), and then
+ *   4. Algorithm 1 factors Kres ~ sum_k a_k b_k^T with rank k <= r_eps:
+ *      `rounds` rounds of sampled rows rows_s[round][per_round] and columns
+ *      cols_s[round][per_round] (the important columns: pivots of a
+ *      pivoted QR of Kres(I, :); the important rows: pivots of a pivoted
+ *      LQ of Kres(:, J)), orthonormal bases from them, and the core matrix
+ *      on the important plus the extra rows and columns extra_rows,
+ *      extra_cols [n_extra].
+ * Inputs: U1, V1 [N][r1], U2, V2 [N][r2] real row-major host arrays; 1 <= r
+ * < r1, r <= 2; 1 <= r_eps <= 64; indices in [0, N).
+ * Outputs: *y, *n_rank; P, Q [N][r] (always); a, b host complex128
+ * interleaved [r_eps][N] of which the first *k_out rows are set when y = 1.
+ * Returns BF_EINVAL for bad arguments or a phase of numerical rank below r.
+ */
+int bf_lift_decide(long long N, int r1, const double* U1, const double* V1,
+                   int r2, const double* U2, const double* V2, int r,
+                   int r_eps, double eps, const double* omega, int omega_cols,
+                   const long long* test_cols, int n_test, int rounds,
+                   const long long* rows_s, const long long* cols_s,
+                   int per_round, const long long* extra_rows,
+                   const long long* extra_cols, int n_extra, int* y,
+                   int* n_rank, double* P, double* Q, double* a, double* b,
+                   int* k_out);
+
+/* bf_plan_lifted: a plan that applies eq. (eqn:tg3) on the current device:
+ * g_v(x_i) = sum_{c<k} a_c(x_i) sum_j exp(2 pi i P_i . Q_j) b_c(xi_j)
+ * f_v(xi_j), each term an r-dimensional type-3 NUFFT from the sources Q_j
+ * to the targets P_i (Gaussian gridding of the shifted sources onto a grid
+ * at twice the targets' Nyquist rate, a power-of-two FFT with the positive
+ * exponent on a twice-oversampled grid, Gaussian interpolation at the
+ * targets; about 1e-7 relative before FP32 rounding).  P, Q: host float64
+ * [N][r] (r = 1 or 2); a, b: host complex128 interleaved [k][N] (1 <= k <=
+ * 64); copied to the device.  The plan is used with bf_apply, bf_apply_ws,
+ * bf_apply_static, bf_apply_chain, the graph calls, bf_query (method = 1)
+ * and bf_destroy; it has one execution form (bf_set_config and
+ * bf_autotune return BF_EUNSUPPORTED) and no butterfly steps.  The
+ * workspace holds k FFT grids per vector chunk.  Returns BF_EINVAL for bad
+ * arguments, BF_EUNSUPPORTED when the grid the points need exceeds 2^24
+ * points (4096 per dimension for r = 2): the space-bandwidth product of the
+ * lifted phase is too large for this path, BF_ENOMEM when memory does not
+ * suffice.                                                               */
+int bf_plan_lifted(long long N, int r, const double* P, const double* Q,
+                   int k, const double* a, const double* b, int max_nvec,
+                   bf_plan_t* out);
 
 /* ---- stored factors (diagnostics) ----------------------------------------
  * The computed steps of a plan in apply order (bf_plan_info.n_steps of

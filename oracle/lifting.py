@@ -124,17 +124,20 @@ def decide(U1, V1, U2, V2, r, r_eps, eps, omega, test_cols, alg1_samples):
     return 1, P, Q, a, b, n
 
 
-def lifted_matvec(P, Q, a, b, f, block=256):
+def lifted_matvec(P, Q, a, b, f, rows=None, block=256):
     """Eq. (eqn:tg3) summed directly: g_v = sum_k a_k . E (b_k . f_v),
     E(i, j) = exp(2 pi i P_i . Q_j), FP64 (the exact result the r-dimensional
-    type-3 NUFFTs approximate).  f: [nvec][N]."""
+    type-3 NUFFTs approximate), at the given rows (default all).
+    f: [nvec][N]; returns [nvec][len(rows)]."""
     f = np.atleast_2d(np.asarray(f, np.complex128))
     N = P.shape[0]
-    g = np.zeros((f.shape[0], N), np.complex128)
-    for s in range(0, N, block):
-        E = np.exp(TWO_PI * 1j * (P[s:s + block] @ Q.T))   # rows s..s+block
+    rows = np.arange(N) if rows is None else np.asarray(rows, np.int64)
+    g = np.zeros((f.shape[0], rows.size), np.complex128)
+    for s in range(0, rows.size, block):
+        ri = rows[s:s + block]
+        E = np.exp(TWO_PI * 1j * (P[ri] @ Q.T))      # the block's rows of E
         for k in range(a.shape[0]):
-            g[:, s:s + block] += a[k, s:s + block] * ((f * b[k]) @ E.T)
+            g[:, s:s + block] += a[k, ri] * ((f * b[k]) @ E.T)
     return g
 
 

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import BfError, OPS, PATHS, PHASES, PRECISIONS  # noqa: F401
 
 __all__ = ["Plan", "Graph", "BfError", "points", "lagrange", "load",
-           "plan_footprint",
+           "plan_footprint", "lift_decide", "plan_lifted", "plan_for_kernel",
            "apply_chain", "graph_chain", "fourier_coefficients_plan",
            "unwrap",
            "recover_phase", "kernel_phase_sampler", "lowrank_from_samples",
@@ -99,6 +99,84 @@ def plan_footprint(dim, n, phase, params=(), q=8, amplitude=None,
     return out.value
 
 
+def lift_decide(U1, V1, U2, V2, r, r_eps, eps, omega, test_cols,
+                alg1_samples):
+    """Algorithm 6 (bf_lift_decide), host only: whether the kernel with
+    phase U1 V1^T and amplitude U2 V2^T (real [N][r1], [N][r2]) can be
+    applied as r_eps r-dimensional NUFFTs after lifting its phase to rank r.
+    omega [N][m] (m > r1), test_cols and alg1_samples = (row rounds [t][s],
+    column rounds [t][s], extra rows, extra columns) are the method's random
+    draws.  Returns (y, n, P, Q, a, b): a, b complex [k][N] when y = 1, else
+    None."""
+    lib = _lib.load()
+    f64 = lambda m: np.ascontiguousarray(m, dtype=np.float64)  # noqa: E731
+    i64 = lambda m: np.ascontiguousarray(m, dtype=np.int64)    # noqa: E731
+    U1, V1, U2, V2, omega = (f64(m) for m in (U1, V1, U2, V2, omega))
+    N, r1 = U1.shape
+    r2 = U2.shape[1]
+    if V1.shape != U1.shape or V2.shape != U2.shape or U2.shape[0] != N or \
+            omega.ndim != 2 or omega.shape[0] != N:
+        raise ValueError("factors must be [N][rank] and omega [N][m]")
+    tc = i64(test_cols)
+    rows, cols, xr, xc = alg1_samples
+    rows, cols = i64(rows), i64(cols)
+    xr, xc = i64(xr), i64(xc)
+    if rows.ndim != 2 or rows.shape != cols.shape or xr.shape != xc.shape:
+        raise ValueError("alg1_samples: rounds [t][s] of rows and columns, "
+                         "extra rows and columns of one length")
+    P = np.zeros((N, r))
+    Q = np.zeros((N, r))
+    a = np.zeros((r_eps, N), np.complex128)
+    b = np.zeros((r_eps, N), np.complex128)
+    y, n, k = C.c_int(), C.c_int(), C.c_int()
+    D, L = C.POINTER(C.c_double), C.POINTER(C.c_longlong)
+    _lib.check(lib.bf_lift_decide(
+        N, r1, U1.ctypes.data_as(D), V1.ctypes.data_as(D), r2,
+        U2.ctypes.data_as(D), V2.ctypes.data_as(D), int(r), int(r_eps),
+        float(eps), omega.ctypes.data_as(D), omega.shape[1],
+        tc.ctypes.data_as(L), tc.size, rows.shape[0], rows.ctypes.data_as(L),
+        cols.ctypes.data_as(L), rows.shape[1], xr.ctypes.data_as(L),
+        xc.ctypes.data_as(L), xr.size, C.byref(y), C.byref(n),
+        P.ctypes.data_as(D), Q.ctypes.data_as(D), a.ctypes.data_as(D),
+        b.ctypes.data_as(D), C.byref(k)))
+    if not y.value:
+        return 0, n.value, P, Q, None, None
+    return 1, n.value, P, Q, a[:k.value].copy(), b[:k.value].copy()
+
+
+def plan_lifted(P, Q, a, b, max_nvec=1):
+    """A device plan of eq. (eqn:tg3) (bf_plan_lifted): g = sum_k a_k .
+    NUFFT3(P, Q; b_k . f).  P, Q real [N][r], a, b complex [k][N]."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    if P.ndim != 2 or P.shape != Q.shape or a.shape != b.shape or \
+            a.ndim != 2 or a.shape[1] != P.shape[0]:
+        raise ValueError("P, Q must be [N][r] and a, b [k][N]")
+    return Plan._from_lifted(P, Q, a, b, max_nvec)
+
+
+def plan_for_kernel(U1, V1, U2, V2, r, r_eps, eps, omega, test_cols,
+                    alg1_samples, q=8, max_nvec=1):
+    """The unified framework (Figure (fig:flow), 1D): Algorithm 6 decides,
+    then the NUFFT path (plan_lifted) or the butterfly of the low-rank
+    phase with the amplitude factors (Plan with phase "lowrank").  Returns
+    (plan, decision) with decision = (y, n)."""
+    y, n, P, Q, a, b = lift_decide(U1, V1, U2, V2, r, r_eps, eps, omega,
+                                   test_cols, alg1_samples)
+    if y:
+        return plan_lifted(P, Q, a, b, max_nvec), (y, n)
+    U1 = np.asarray(U1, np.float64)
+    N = U1.shape[0]
+    amp = (np.asarray(U2, np.float64).T.astype(np.complex128),
+           np.asarray(V2, np.float64).T.astype(np.complex128))
+    if amp[0].shape[0] == 1 and np.all(amp[0] == 1) and np.all(amp[1] == 1):
+        amp = None
+    return Plan(1, N, "lowrank", (U1, V1), q=q, amplitude=amp,
+                max_nvec=max_nvec), (y, n)
+
+
 class Plan:
     """A device-resident butterfly plan (bf_plan ... bf_destroy).
 
@@ -133,6 +211,28 @@ class Plan:
         self.N = n ** dim
         self.max_nvec = max_nvec
         self.precision = precision
+
+    @classmethod
+    def _from_lifted(cls, P, Q, a, b, max_nvec):
+        import torch
+        self = cls.__new__(cls)
+        self._lib = _lib.load()
+        self._h = C.c_void_p()
+        D = C.POINTER(C.c_double)
+        N, r = P.shape
+        _lib.check(self._lib.bf_plan_lifted(
+            N, r, P.ctypes.data_as(D), Q.ctypes.data_as(D), a.shape[0],
+            a.ctypes.data_as(D), b.ctypes.data_as(D), int(max_nvec),
+            C.byref(self._h)))
+        self._keep = []
+        self.device = torch.cuda.current_device()
+        self.r = a.shape[0]
+        self.op = "N"
+        self.dim, self.n, self.q = 1, N, 0
+        self.N = N
+        self.max_nvec = max_nvec
+        self.precision = "fp32"
+        return self
 
     def info(self):
         inf = _lib.BfPlanInfo()

@@ -39,7 +39,8 @@ class BfPlanInfo(C.Structure):
                 ("factor_bytes", C.c_size_t),
                 ("workspace_bytes", C.c_size_t),
                 ("flops_per_column", C.c_double),
-                ("factor_stream_bytes", C.c_double), ("op", C.c_int)]
+                ("factor_stream_bytes", C.c_double), ("op", C.c_int),
+                ("method", C.c_int)]
 
 
 class BfStepInfo(C.Structure):
@@ -75,7 +76,8 @@ SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int,
                       C.POINTER(C.c_longlong), C.POINTER(C.c_double))
 
 EXPORTS = ["bf_plan", "bf_plan_op", "bf_plan_footprint", "bf_step_query",
-           "bf_factor_entries", "bf_apply_static", "bf_apply_chain",
+           "bf_factor_entries", "bf_apply_static", "bf_lift_decide",
+           "bf_plan_lifted", "bf_apply_chain",
            "bf_graph_create_chain", "bf_unwrap",
            "bf_recover_phase", "bf_lowrank_samples", "bf_apply", "bf_workspace_bytes", "bf_apply_ws",
            "bf_destroy", "bf_query", "bf_last_error", "bf_points",
@@ -118,6 +120,14 @@ def load():
     lib.bf_plan_footprint.argtypes = [P(BfGrid), P(BfPhase),
                                       P(BfAmplitude), C.c_int, C.c_int,
                                       C.c_int, C.c_int, P(C.c_size_t)]
+    D, L = P(C.c_double), P(C.c_longlong)
+    lib.bf_lift_decide.argtypes = [C.c_longlong, C.c_int, D, D, C.c_int, D,
+                                   D, C.c_int, C.c_int, C.c_double, D,
+                                   C.c_int, L, C.c_int, C.c_int, L, L,
+                                   C.c_int, L, L, C.c_int, P(C.c_int),
+                                   P(C.c_int), D, D, D, D, P(C.c_int)]
+    lib.bf_plan_lifted.argtypes = [C.c_longlong, C.c_int, D, D, C.c_int, D,
+                                   D, C.c_int, P(C.c_void_p)]
     lib.bf_step_query.argtypes = [C.c_void_p, C.c_int, P(BfStepInfo)]
     lib.bf_factor_entries.argtypes = [C.c_void_p, C.c_int, C.c_int,
                                       P(C.c_longlong), C.c_int,

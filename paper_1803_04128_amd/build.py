@@ -18,7 +18,8 @@ LIB = os.path.join(PKG, "libbf.so")
 
 SOURCES = ["geometry.cpp", "factors.hip", "apply_basic.hip",
            "apply_fused.hip", "apply_mfma.hip", "apply_step_mfma.hip",
-           "dispatch.cpp", "api.cpp", "recovery.cpp"]
+           "dispatch.cpp", "api.cpp", "recovery.cpp", "lifting.cpp",
+           "nufft.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

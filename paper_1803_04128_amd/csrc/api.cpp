@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -418,6 +419,95 @@ static int plan_impl(const bf_grid* grid, const bf_phase* phase,
     return BF_OK;
 }
 
+int bf_lift_decide(long long N, int r1, const double* U1, const double* V1,
+                   int r2, const double* U2, const double* V2, int r,
+                   int r_eps, double eps, const double* omega, int omega_cols,
+                   const long long* test_cols, int n_test, int rounds,
+                   const long long* rows_s, const long long* cols_s,
+                   int per_round, const long long* extra_rows,
+                   const long long* extra_cols, int n_extra, int* y,
+                   int* n_rank, double* P, double* Q, double* a, double* b,
+                   int* k_out) {
+    return guarded("bf_lift_decide", [&]() -> int {
+        if (N < 4 || r1 < 1 || r2 < 1 || r < 1 || r >= r1 || r > 2 ||
+            r_eps < 1 || !(eps > 0) || !U1 || !V1 || !U2 || !V2 || !omega ||
+            omega_cols <= r1 || omega_cols > 64 || !test_cols || n_test < 1 ||
+            rounds < 1 || per_round < 1 || !rows_s || !cols_s || n_extra < 0 ||
+            (n_extra > 0 && (!extra_rows || !extra_cols)) || !y || !n_rank ||
+            !P || !Q || !a || !b || !k_out || r_eps > 64 ||
+            (long long)n_test > N || (long long)per_round > N)
+            return fail(BF_EINVAL, "bf_lift_decide: bad argument");
+        auto in_range = [&](const long long* v, long long n) {
+            for (long long i = 0; i < n; ++i)
+                if (v[i] < 0 || v[i] >= N) return false;
+            return true;
+        };
+        if (!in_range(test_cols, n_test) ||
+            !in_range(rows_s, (long long)rounds * per_round) ||
+            !in_range(cols_s, (long long)rounds * per_round) ||
+            !in_range(extra_rows, n_extra) || !in_range(extra_cols, n_extra))
+            return fail(BF_EINVAL, "bf_lift_decide: index out of range");
+        std::string err;
+        int rc = bfi::lift_decide(N, r1, U1, V1, r2, U2, V2, r, r_eps, eps,
+                                  omega, omega_cols, test_cols, n_test,
+                                  rounds, rows_s, cols_s, per_round,
+                                  extra_rows, extra_cols, n_extra, y, n_rank,
+                                  P, Q, a, b, k_out, err);
+        if (rc != BF_OK) return fail(rc, "bf_lift_decide: " + err);
+        return BF_OK;
+    });
+}
+
+int bf_plan_lifted(long long N, int r, const double* P, const double* Q,
+                   int k, const double* a, const double* b, int max_nvec,
+                   bf_plan_t* out) {
+    return guarded("bf_plan_lifted", [&]() -> int {
+        if (!out) return fail(BF_EINVAL, "bf_plan_lifted: out is NULL");
+        *out = nullptr;
+        if (N < 2 || N > (1LL << 24) || (r != 1 && r != 2) || k < 1 ||
+            k > 64 || !P || !Q || !a || !b || max_nvec < 1)
+            return fail(BF_EINVAL, "bf_plan_lifted: bad argument");
+        for (long long i = 0; i < N * r; ++i)
+            if (!std::isfinite(P[i]) || !std::isfinite(Q[i]))
+                return fail(BF_EINVAL, "bf_plan_lifted: non-finite P or Q");
+        bf_plan_s* h = new (std::nothrow) bf_plan_s();
+        if (!h) return fail(BF_ENOMEM, "bf_plan_lifted: host allocation");
+        bfi::Plan& p = h->p;
+        p.dim = 1;
+        p.n = (int)N;
+        p.N = N;
+        p.r_amp = k;
+        p.max_nvec = max_nvec;
+        p.fused = false;
+        p.op = BF_OP_N;
+        if (hipGetDevice(&p.device) != hipSuccess) {
+            delete h;
+            return fail(BF_EHIP, "bf_plan_lifted: no HIP device");
+        }
+        std::string err = bfi::nufft_build(p, r, P, Q, k, a, b);
+        if (!err.empty()) {
+            delete h;
+            return fail(err.find("too large") != std::string::npos
+                            ? BF_EUNSUPPORTED
+                            : BF_EHIP,
+                        "bf_plan_lifted: " + err);
+        }
+        const size_t ws_cap = env_bytes("BF_WS_CAP_BYTES", 16 * kGiB);
+        const size_t per_vec = bfi::nufft_grid_bytes(*p.nufft, 1);
+        p.chunk_nvec = (int)std::max<size_t>(
+            1, std::min<size_t>(max_nvec, ws_cap / per_vec));
+        p.ws_bytes = bfi::workspace_bytes(p, max_nvec);
+        if (hipMalloc(&p.ws, p.ws_bytes) != hipSuccess) {
+            p.ws = nullptr;
+            bfi::nufft_free(p.nufft);
+            delete h;
+            return fail(BF_ENOMEM, "bf_plan_lifted: workspace allocation");
+        }
+        *out = h;
+        return BF_OK;
+    });
+}
+
 int bf_plan_footprint(const bf_grid* grid, const bf_phase* phase,
                       const bf_amplitude* amp, int q, int precision,
                       int max_nvec, int op, size_t* bytes) {
@@ -610,6 +700,8 @@ int bf_destroy(bf_plan_t plan) {
         if (p.S_arena && hipFree(p.S_arena) != hipSuccess) rc = BF_EHIP;
         if (p.phase_arena && hipFree(p.phase_arena) != hipSuccess) rc = BF_EHIP;
         if (p.ws && hipFree(p.ws) != hipSuccess) rc = BF_EHIP;
+        bfi::nufft_free(p.nufft);
+        p.nufft = nullptr;
         for (auto ev : p.prof.pool) (void)hipEventDestroy(ev);
         plan->magic = 0;
         delete plan;
@@ -701,7 +793,9 @@ int bf_query(bf_plan_t plan, bf_plan_info* info) {
         info->chunk_nvec = p.chunk_nvec;
         info->factor_bytes = p.arena_bytes + p.S_bytes +
                              (p.phase_arena ? 2 * (size_t)p.phase.rank * p.N * 8
-                                            : 0);
+                                            : 0) +
+                             (p.nufft ? bfi::nufft_factor_bytes(*p.nufft) : 0);
+        info->method = p.nufft ? 1 : 0;
         info->workspace_bytes = p.ws_bytes;
         info->flops_per_column = p.flops_per_column;
         info->factor_stream_bytes = p.factor_stream_bytes;
@@ -776,6 +870,9 @@ int bf_set_config(bf_plan_t plan, const bf_config* cfg) {
     return guarded("bf_set_config", [&]() -> int {
         if (int e = check_plan(plan)) return e;
         if (!cfg) return fail(BF_EINVAL, "bf_set_config: NULL cfg");
+        if (plan->p.nufft)
+            return fail(BF_EUNSUPPORTED,
+                        "bf_set_config: a NUFFT plan has one execution form");
         if (plan->p.graphs > 0)
             return fail(BF_EBUSY, "bf_set_config: captured graphs use the plan");
         return apply_config(plan->p, *cfg);
@@ -786,6 +883,9 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
                 void* stream, bf_tune_entry* out, int cap, int* count) {
     return guarded("bf_autotune", [&]() -> int {
         if (int e = check_apply(plan, nvec, f, g)) return e;
+        if (plan->p.nufft)
+            return fail(BF_EUNSUPPORTED,
+                        "bf_autotune: a NUFFT plan has one execution form");
         if (reps < 1 || !count || (cap > 0 && !out))
             return fail(BF_EINVAL, "bf_autotune: bad argument");
         bfi::Plan& p = plan->p;

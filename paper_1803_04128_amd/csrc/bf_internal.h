@@ -127,7 +127,12 @@ struct Profiler {
     }
 };
 
+struct NufftPlan;   // nufft.hip
+
 struct Plan {
+    // a plan of the NUFFT path of Section 3 (eq. (eqn:tg3)) instead of the
+    // butterfly: the fields below describe its grid (1D, N = n) only
+    NufftPlan* nufft = nullptr;
     int dim = 1, n = 0, L = 0, h = 0, R = 2, q = 0, r_amp = 1;
     int precision = BF_FP32, max_nvec = 1;
     long long N = 0;
@@ -253,6 +258,25 @@ inline double step_alg_flops(const Plan& p, const Step& s, double Vc) {
     return step_alg_flops(p.dim, s.kind, s.units, s.r_in, s.r_out,
                           s.ax_in.r1, s.ax_out.r1, Vc);
 }
+
+// nufft.hip: the NUFFT by dimension lifting (Section 3, eq. (eqn:tg3))
+std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
+                        int K, const double* a, const double* b);
+void nufft_free(NufftPlan* q);
+size_t nufft_grid_bytes(const NufftPlan& q, int nv);
+size_t nufft_factor_bytes(const NufftPlan& q);
+std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
+                         void* ws, size_t ws_bytes, hipStream_t st);
+// lifting.cpp: Algorithm 6 with Algorithm 1 (host, FP64)
+int lift_decide(long long N, int r1, const double* U1, const double* V1,
+                int r2, const double* U2, const double* V2, int r, int r_eps,
+                double eps, const double* omega, int omega_cols,
+                const long long* test_cols, int n_test, int rounds,
+                const long long* rows_s, const long long* cols_s,
+                int per_round, const long long* extra_rows,
+                const long long* extra_cols, int n_extra, int* y, int* n_rank,
+                double* P, double* Q, double* a, double* b, int* k_out,
+                std::string& err);
 
 // tiny helpers
 inline int ilog2(long long v) {

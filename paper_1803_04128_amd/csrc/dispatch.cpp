@@ -71,11 +71,15 @@ static size_t state_bytes(const Plan& p, int nv) {
 
 size_t workspace_bytes(const Plan& p, int nvec) {
     const int nv = std::min(nvec, p.chunk_nvec);
+    if (p.nufft) return nufft_grid_bytes(*p.nufft, nv);
     return 2 * state_bytes(p, nv);
 }
 
 std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
                          void* ws, size_t ws_bytes, hipStream_t st) {
+    if (p.nufft)
+        return launch_nufft(p, nvec, (const float2*)fv, (float2*)gv, ws,
+                            ws_bytes, st);
     // vectors per chunk: as many as the workspace holds, at most chunk_nvec
     int chunk = std::min(nvec, p.chunk_nvec);
     while (chunk > 1 && 2 * state_bytes(p, chunk) > ws_bytes) --chunk;
@@ -115,6 +119,7 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
 }
 
 std::string check_config(Plan& p) {
+    if (p.nufft) return "";
     if (p.precision != BF_FP32 && !p.fused)
         return "split precision needs the fused passes";
     if (!p.fused) return "";

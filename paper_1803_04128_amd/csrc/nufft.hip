@@ -1,0 +1,607 @@
+// NUFFT by dimension lifting on the device (Section 3, eq. (eqn:tg3)):
+//   g_v(x_i) = sum_k a_k(x_i) sum_j exp(2 pi i P_i . Q_j) b_k(xi_j) f_v(xi_j),
+// r_eps r-dimensional type-3 NUFFTs (r = 1 or 2) from the sources s_j = Q_j
+// to the targets t_i = P_i, for every vector and amplitude term.
+//
+// Type 3 through two Gaussian griddings, per dimension (centers sbar, tbar,
+// half-widths S, X of the shifted points s' = s - sbar, t' = t - tbar):
+//   sum_j c_j e^{2 pi i t.s_j} = e^{2 pi i t.sbar} sum_j [c_j e^{2 pi i tbar.s'_j}]
+//                                e^{2 pi i t'.s'_j};
+//   spreading the shifted sources with phi(u) = exp(-(u/h)^2 / (4 b)) onto
+//   the grid u = m h (h = 1 / (4 X): twice the Nyquist rate of the targets)
+//   turns the sum into (1 / phihat(t')) h sum_m F_m e^{2 pi i m theta},
+//   theta = t' h, |theta| <= 1/4; that Fourier series is evaluated by the
+//   second gridding: coefficients h F_m / psihat_m on an oversampled FFT
+//   grid of Mr >= 4 Mh points (modes |m| <= Mh), one FFT with the positive
+//   exponent, and the Gaussian psi(theta) = exp(-(theta Mr)^2 / (4 b)) at
+//   each target, divided by Mr.
+// Both Gaussians use b = W / (4 pi sqrt(1/2)) and 2 W grid points per
+// dimension, which balances the truncation error exp(-W^2 / (4 b)) against
+// the aliasing error at oversampling 2 (about 1e-7 relative at W = 7).
+// Point positions are split on the host (FP64) into an integer grid index
+// and a fraction in [0, 1), and the phase factors are computed in FP64, so
+// the device arithmetic (FP32) only forms Gaussian weights of fractions.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "apply_common.h"
+
+namespace bfi {
+
+namespace {
+
+constexpr int kW = 7;                 // stencil half-width (2 kW points)
+constexpr int kFftMax = 4096;         // longest FFT held in one workgroup
+constexpr int kNufftThreads = 256;
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+struct NuArgs {
+    int r, K, nv;                     // dims, amplitude terms, vectors
+    long long N;
+    int Mr[2], Mh[2];
+    long long cells;
+    float b4;                         // 4 b
+    int n1, n2;                       // 1D four-step split (n1 = 0: none)
+    const int* sbase;
+    const float* sfrac;
+    const float2* pre;
+    const int* tbase;
+    const float* tfrac;
+    const float2* post;
+    const float* dec0;
+    const float* dec1;
+    const float2* a;
+    const float2* b;
+    const float2* f;                  // [nv][N] chunk
+    float2* g;
+    float2* grid;                     // [nv * K][cells]
+};
+
+__global__ void __launch_bounds__(kNufftThreads)
+nufft_zero(float2* p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = make_float2(0.f, 0.f);
+}
+
+// Gaussian weights of the 2 kW grid points m0 - kW + 1 + e around a point at
+// grid position m0 + frac.
+__device__ __forceinline__ void gauss(float frac, float b4, float (&w)[2 * kW]) {
+#pragma unroll
+    for (int e = 0; e < 2 * kW; ++e) {
+        const float d = (float)(e - kW + 1) - frac;
+        w[e] = expf(-d * d / b4);
+    }
+}
+
+__device__ __forceinline__ int wrap(int m, int M) {
+    m %= M;
+    return m < 0 ? m + M : m;
+}
+
+// Sources to the grid: thread per source, every column of the chunk.
+// Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source phase;
+// each grid point gets phi times h / psihat of its mode.
+template <int R>
+__global__ void __launch_bounds__(kNufftThreads) nufft_spread(NuArgs a) {
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         j < a.N; j += (long long)gridDim.x * blockDim.x) {
+        float w0[2 * kW], w1[2 * kW];
+        int c0[2 * kW], c1[2 * kW];
+        {
+            const int m0 = a.sbase[j * R];
+            gauss(a.sfrac[j * R], a.b4, w0);
+#pragma unroll
+            for (int e = 0; e < 2 * kW; ++e) {
+                const int m = m0 - kW + 1 + e;
+                w0[e] *= a.dec0[m + a.Mh[0]];
+                c0[e] = wrap(m, a.Mr[0]);
+            }
+        }
+        if (R == 2) {
+            const int m0 = a.sbase[j * R + 1];
+            gauss(a.sfrac[j * R + 1], a.b4, w1);
+#pragma unroll
+            for (int e = 0; e < 2 * kW; ++e) {
+                const int m = m0 - kW + 1 + e;
+                w1[e] *= a.dec1[m + a.Mh[1]];
+                c1[e] = wrap(m, a.Mr[1]);
+            }
+        }
+        const float2 pj = a.pre[j];
+        for (int v = 0; v < a.nv; ++v) {
+            const float2 fv = cmul(a.f[(size_t)v * a.N + j], pj);
+            for (int k = 0; k < a.K; ++k) {
+                const float2 val = cmul(a.b[(size_t)k * a.N + j], fv);
+                float2* gc = a.grid + (size_t)(v * a.K + k) * a.cells;
+                if (R == 1) {
+#pragma unroll
+                    for (int e = 0; e < 2 * kW; ++e) {
+                        atomicAdd(&gc[c0[e]].x, w0[e] * val.x);
+                        atomicAdd(&gc[c0[e]].y, w0[e] * val.y);
+                    }
+                } else {
+                    for (int e = 0; e < 2 * kW; ++e) {
+                        float2* row = gc + (size_t)c0[e] * a.Mr[1];
+                        const float vx = w0[e] * val.x, vy = w0[e] * val.y;
+#pragma unroll
+                        for (int e1 = 0; e1 < 2 * kW; ++e1) {
+                            atomicAdd(&row[c1[e1]].x, w1[e1] * vx);
+                            atomicAdd(&row[c1[e1]].y, w1[e1] * vy);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Batched power-of-two FFT with the positive exponent, one sequence per
+// workgroup held in LDS: y_k = sum_t x_t exp(2 pi i t k / n).  Sequence s
+// of column col starts at col * col_dist + s * seq_dist, elements `stride`
+// apart.  Radix-2 decimation in time after a bit-reversed load.  With
+// total > 0 (first step of a four-step transform of length total), output
+// k of sequence s is multiplied by exp(2 pi i s k / total).
+struct FftArgs {
+    float2* data;
+    const float2* tw;       // exp(2 pi i k / n), k < n / 2
+    int logn;
+    long long stride, seq_dist, col_dist;
+    long long nseq;
+    long long total;
+};
+
+__global__ void __launch_bounds__(kNufftThreads) fft_lds(FftArgs a) {
+    __shared__ float2 x[kFftMax];
+    const int n = 1 << a.logn;
+    const long long sid = blockIdx.x;
+    const long long col = sid / a.nseq, s = sid - col * a.nseq;
+    float2* base = a.data + col * a.col_dist + s * a.seq_dist;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
+        x[rv] = base[(long long)t * a.stride];
+    }
+    __syncthreads();
+    for (int lh = 0; lh < a.logn; ++lh) {
+        const int half = 1 << lh;
+        const int tstep = n >> (lh + 1);        // twiddle index step
+        for (int q = threadIdx.x; q < n / 2; q += blockDim.x) {
+            const int grp = q >> lh, jj = q & (half - 1);
+            const int i0 = (grp << (lh + 1)) + jj, i1 = i0 + half;
+            const float2 w = a.tw[jj * tstep];
+            const float2 u = x[i0], v = cmul(x[i1], w);
+            x[i0] = make_float2(u.x + v.x, u.y + v.y);
+            x[i1] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        float2 y = x[t];
+        if (a.total > 0) {
+            // exp(2 pi i s t / total), the product reduced exactly first
+            const long long p = (s * t) & (a.total - 1);
+            float sn, cs;
+            sincospif(2.0f * (float)((double)p / (double)a.total), &sn, &cs);
+            y = cmul(y, make_float2(cs, sn));
+        }
+        base[(long long)t * a.stride] = y;
+    }
+}
+
+// Grid to targets: thread per (target, vector); the Gaussian psi over the
+// 2 kW points around theta Mr in each dimension, for every amplitude term,
+// recombined with a_k and the target factor (phase, 1 / (phihat Mr)).
+template <int R>
+__global__ void __launch_bounds__(kNufftThreads) nufft_interp(NuArgs a) {
+    const long long total = a.N * a.nv;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int v = (int)(e / a.N);
+        const long long i = e - (long long)v * a.N;
+        float w0[2 * kW], w1[2 * kW];
+        int p0[2 * kW], p1[2 * kW];
+        {
+            const int m0 = a.tbase[i * R];
+            gauss(a.tfrac[i * R], a.b4, w0);
+#pragma unroll
+            for (int q = 0; q < 2 * kW; ++q) {
+                const int k = wrap(m0 - kW + 1 + q, a.Mr[0]);
+                // four-step output order: frequency k at (k % n1) n2 + k / n1
+                p0[q] = a.n1 ? (k & (a.n1 - 1)) * a.n2 + k / a.n1 : k;
+            }
+        }
+        if (R == 2) {
+            const int m0 = a.tbase[i * R + 1];
+            gauss(a.tfrac[i * R + 1], a.b4, w1);
+#pragma unroll
+            for (int q = 0; q < 2 * kW; ++q) p1[q] = wrap(m0 - kW + 1 + q, a.Mr[1]);
+        }
+        float2 acc = make_float2(0.f, 0.f);
+        for (int k = 0; k < a.K; ++k) {
+            const float2* gc = a.grid + (size_t)(v * a.K + k) * a.cells;
+            float2 s = make_float2(0.f, 0.f);
+            if (R == 1) {
+#pragma unroll
+                for (int q = 0; q < 2 * kW; ++q) {
+                    const float2 h = gc[p0[q]];
+                    s.x += w0[q] * h.x;
+                    s.y += w0[q] * h.y;
+                }
+            } else {
+                for (int q = 0; q < 2 * kW; ++q) {
+                    const float2* row = gc + (size_t)p0[q] * a.Mr[1];
+                    float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int q1 = 0; q1 < 2 * kW; ++q1) {
+                        const float2 h = row[p1[q1]];
+                        t.x += w1[q1] * h.x;
+                        t.y += w1[q1] * h.y;
+                    }
+                    s.x += w0[q] * t.x;
+                    s.y += w0[q] * t.y;
+                }
+            }
+            const float2 z = cmul(a.a[(size_t)k * a.N + i], s);
+            acc.x += z.x;
+            acc.y += z.y;
+        }
+        a.g[(size_t)v * a.N + i] = cmul(acc, a.post[i]);
+    }
+}
+
+int blocks_for_n(long long n) {
+    long long b = (n + kNufftThreads - 1) / kNufftThreads;
+    return (int)std::max<long long>(1, std::min<long long>(b, 65536));
+}
+
+int ilog2i(long long v) {
+    int l = 0;
+    while ((1LL << l) < v) ++l;
+    return l;
+}
+
+long long next_pow2(long long v) {
+    long long p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct NufftPlan {
+    int r = 1, K = 1;
+    long long N = 0;
+    int Mr[2] = {1, 1}, Mh[2] = {0, 0};
+    long long cells = 1;
+    int n1 = 0, n2 = 0;
+    double b = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    int* sbase = nullptr;
+    float* sfrac = nullptr;
+    float2* pre = nullptr;
+    int* tbase = nullptr;
+    float* tfrac = nullptr;
+    float2* post = nullptr;
+    float* dec[2] = {nullptr, nullptr};
+    float2* a = nullptr;
+    float2* bb = nullptr;
+    // FFT twiddle tables by log2 length
+    std::vector<std::pair<int, float2*>> tw;
+    const float2* twiddles(int logn) const {
+        for (auto& t : tw)
+            if (t.first == logn) return t.second;
+        return nullptr;
+    }
+};
+
+void nufft_free(NufftPlan* q) {
+    if (!q) return;
+    if (q->arena) (void)hipFree(q->arena);
+    delete q;
+}
+
+size_t nufft_grid_bytes(const NufftPlan& q, int nv) {
+    return (size_t)nv * q.K * q.cells * sizeof(float2);
+}
+
+// FP64 host planning (see the head of this file).
+std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
+                        int K, const double* a, const double* b) {
+    NufftPlan* q = new (std::nothrow) NufftPlan();
+    if (!q) return "host allocation";
+    const long long N = p.N;
+    q->r = r;
+    q->K = K;
+    q->N = N;
+    q->b = kW / (4.0 * kPi * std::sqrt(0.5));
+    double sbar[2], tbar[2], h[2];
+    for (int d = 0; d < r; ++d) {
+        double smin = Q[d], smax = Q[d], tmin = P[d], tmax = P[d];
+        for (long long j = 0; j < N; ++j) {
+            smin = std::min(smin, Q[j * r + d]);
+            smax = std::max(smax, Q[j * r + d]);
+            tmin = std::min(tmin, P[j * r + d]);
+            tmax = std::max(tmax, P[j * r + d]);
+        }
+        sbar[d] = 0.5 * (smin + smax);
+        tbar[d] = 0.5 * (tmin + tmax);
+        const double S = 0.5 * (smax - smin), X = 0.5 * (tmax - tmin);
+        // twice the Nyquist rate of the targets; a dimension whose targets
+        // barely spread takes a grid of about the sources' width
+        h[d] = X > 0 ? std::min(1.0 / (4.0 * X), std::max(S, 1.0))
+                     : std::max(S, 1.0);
+        q->Mh[d] = (int)std::ceil(S / h[d]) + kW + 1;
+        const long long mr = std::max<long long>(16, next_pow2(4LL * q->Mh[d]));
+        if (mr > (r == 1 ? (1LL << 24) : (long long)kFftMax)) {
+            delete q;
+            return "the lifted grid is too large (space-bandwidth product)";
+        }
+        q->Mr[d] = (int)mr;
+    }
+    q->cells = (long long)q->Mr[0] * (r == 2 ? q->Mr[1] : 1);
+    if (q->cells > (1LL << 24)) {
+        delete q;
+        return "the lifted grid is too large (space-bandwidth product)";
+    }
+    if (r == 1 && q->Mr[0] > kFftMax) {
+        const int l = ilog2i(q->Mr[0]);
+        q->n1 = 1 << ((l + 1) / 2);
+        q->n2 = q->Mr[0] / q->n1;
+    }
+    // host arrays
+    std::vector<int> sbase((size_t)N * r), tbase((size_t)N * r);
+    std::vector<float> sfrac((size_t)N * r), tfrac((size_t)N * r);
+    std::vector<float2> pre(N), post(N), av((size_t)K * N), bv((size_t)K * N);
+    const double b4 = 4.0 * q->b;
+    for (long long j = 0; j < N; ++j) {
+        double ph = 0;
+        for (int d = 0; d < r; ++d) {
+            const double sp = Q[j * r + d] - sbar[d];
+            const double u = sp / h[d];
+            const double fl = std::floor(u);
+            sbase[j * r + d] = (int)fl;
+            sfrac[j * r + d] = (float)(u - fl);
+            ph += tbar[d] * sp;
+        }
+        ph -= std::nearbyint(ph);
+        pre[j] = make_float2((float)std::cos(2 * kPi * ph),
+                             (float)std::sin(2 * kPi * ph));
+    }
+    for (long long i = 0; i < N; ++i) {
+        double ph = 0, mag = 1;
+        for (int d = 0; d < r; ++d) {
+            const double tp = P[i * r + d] - tbar[d];
+            const double th = tp * h[d] * q->Mr[d];
+            const double fl = std::floor(th);
+            tbase[i * r + d] = (int)fl;
+            tfrac[i * r + d] = (float)(th - fl);
+            ph += P[i * r + d] * sbar[d];
+            // 1 / (phihat(t') Mr), phihat(t) = h sqrt(4 pi b) e^{-4 pi^2 b h^2 t^2}
+            const double phihat = h[d] * std::sqrt(4 * kPi * q->b) *
+                                  std::exp(-4 * kPi * kPi * q->b * h[d] * h[d] * tp * tp);
+            mag /= phihat * q->Mr[d];
+        }
+        ph -= std::nearbyint(ph);
+        post[i] = make_float2((float)(mag * std::cos(2 * kPi * ph)),
+                              (float)(mag * std::sin(2 * kPi * ph)));
+    }
+    for (long long e = 0; e < (long long)K * N; ++e) {
+        av[e] = make_float2((float)a[2 * e], (float)a[2 * e + 1]);
+        bv[e] = make_float2((float)b[2 * e], (float)b[2 * e + 1]);
+    }
+    std::vector<float> dec[2];
+    for (int d = 0; d < r; ++d) {
+        const int Mh = q->Mh[d];
+        dec[d].resize(2 * Mh);
+        for (int m = -Mh; m < Mh; ++m) {
+            // h / psihat_m, psihat_m = sqrt(4 pi b) / Mr e^{-4 pi^2 b m^2 / Mr^2}
+            const double x = (double)m / q->Mr[d];
+            dec[d][m + Mh] = (float)(h[d] * q->Mr[d] / std::sqrt(4 * kPi * q->b) *
+                                     std::exp(4 * kPi * kPi * q->b * x * x));
+        }
+    }
+    (void)b4;
+    // FFT twiddles for every length the transforms use
+    std::vector<int> lens;
+    if (r == 1) {
+        if (q->n1) {
+            lens.push_back(ilog2i(q->n1));
+            lens.push_back(ilog2i(q->n2));
+        } else {
+            lens.push_back(ilog2i(q->Mr[0]));
+        }
+    } else {
+        lens.push_back(ilog2i(q->Mr[0]));
+        lens.push_back(ilog2i(q->Mr[1]));
+    }
+    std::sort(lens.begin(), lens.end());
+    lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+    // arena layout
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_sb = off; off = al(off + sbase.size() * 4);
+    const size_t o_sf = off; off = al(off + sfrac.size() * 4);
+    const size_t o_pre = off; off = al(off + pre.size() * 8);
+    const size_t o_tb = off; off = al(off + tbase.size() * 4);
+    const size_t o_tf = off; off = al(off + tfrac.size() * 4);
+    const size_t o_post = off; off = al(off + post.size() * 8);
+    size_t o_dec[2] = {0, 0};
+    for (int d = 0; d < r; ++d) {
+        o_dec[d] = off;
+        off = al(off + dec[d].size() * 4);
+    }
+    const size_t o_a = off; off = al(off + av.size() * 8);
+    const size_t o_b = off; off = al(off + bv.size() * 8);
+    std::vector<size_t> o_tw;
+    for (int l : lens) {
+        o_tw.push_back(off);
+        off = al(off + (size_t)std::max(1, (1 << l) / 2) * 8);
+    }
+    if (hipMalloc(&q->arena, off) != hipSuccess) {
+        q->arena = nullptr;
+        delete q;
+        return "hipMalloc nufft arena";
+    }
+    q->arena_bytes = off;
+    char* base = (char*)q->arena;
+    q->sbase = (int*)(base + o_sb);
+    q->sfrac = (float*)(base + o_sf);
+    q->pre = (float2*)(base + o_pre);
+    q->tbase = (int*)(base + o_tb);
+    q->tfrac = (float*)(base + o_tf);
+    q->post = (float2*)(base + o_post);
+    for (int d = 0; d < r; ++d) q->dec[d] = (float*)(base + o_dec[d]);
+    q->a = (float2*)(base + o_a);
+    q->bb = (float2*)(base + o_b);
+    hipError_t e = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+    };
+    up(q->sbase, sbase.data(), sbase.size() * 4);
+    up(q->sfrac, sfrac.data(), sfrac.size() * 4);
+    up(q->pre, pre.data(), pre.size() * 8);
+    up(q->tbase, tbase.data(), tbase.size() * 4);
+    up(q->tfrac, tfrac.data(), tfrac.size() * 4);
+    up(q->post, post.data(), post.size() * 8);
+    for (int d = 0; d < r; ++d) up(q->dec[d], dec[d].data(), dec[d].size() * 4);
+    up(q->a, av.data(), av.size() * 8);
+    up(q->bb, bv.data(), bv.size() * 8);
+    for (size_t t = 0; t < lens.size(); ++t) {
+        const int n = 1 << lens[t];
+        std::vector<float2> w(std::max(1, n / 2));
+        for (int k = 0; k < n / 2; ++k)
+            w[k] = make_float2((float)std::cos(2 * kPi * k / n),
+                               (float)std::sin(2 * kPi * k / n));
+        float2* dst = (float2*)(base + o_tw[t]);
+        up(dst, w.data(), w.size() * 8);
+        q->tw.push_back({lens[t], dst});
+    }
+    if (e != hipSuccess) {
+        nufft_free(q);
+        return std::string("nufft upload: ") + hipGetErrorString(e);
+    }
+    p.nufft = q;
+    return "";
+}
+
+size_t nufft_factor_bytes(const NufftPlan& q) { return q.arena_bytes; }
+
+static std::string launch_fft(const NufftPlan& q, float2* data, int ncols,
+                              hipStream_t st) {
+    auto run = [&](int logn, long long stride, long long seq_dist,
+                   long long nseq, long long total) -> std::string {
+        FftArgs f{data, q.twiddles(logn), logn, stride, seq_dist, q.cells,
+                  nseq, total};
+        if (!f.tw) return "missing FFT twiddles";
+        const long long blocks = nseq * ncols;
+        if (blocks > 0x7fffffffLL) return "FFT grid too large";
+        hipLaunchKernelGGL(fft_lds, dim3((unsigned)blocks),
+                           dim3(kNufftThreads), 0, st, f);
+        return "";
+    };
+    std::string err;
+    if (q.r == 1) {
+        if (q.n1) {
+            // four-step: n1-point transforms over j1 (stride n2), twiddle,
+            // n2-point transforms over j2; frequency k1 + n1 k2 lands at
+            // k1 n2 + k2
+            err = run(ilog2i(q.n1), q.n2, 1, q.n2, q.Mr[0]);
+            if (err.empty()) err = run(ilog2i(q.n2), 1, q.n2, q.n1, 0);
+        } else {
+            err = run(ilog2i(q.Mr[0]), 1, 0, 1, 0);
+        }
+    } else {
+        err = run(ilog2i(q.Mr[1]), 1, q.Mr[1], q.Mr[0], 0);      // rows
+        if (err.empty()) err = run(ilog2i(q.Mr[0]), q.Mr[1], 1, q.Mr[1], 0);
+    }
+    return err;
+}
+
+std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
+                         void* ws, size_t ws_bytes, hipStream_t st) {
+    const NufftPlan& q = *p.nufft;
+    int chunk = std::min(nvec, p.chunk_nvec);
+    while (chunk > 1 && nufft_grid_bytes(q, chunk) > ws_bytes) --chunk;
+    if (nufft_grid_bytes(q, chunk) > ws_bytes)
+        return "workspace too small for one vector";
+    const double N = (double)q.N;
+    const double stencil = std::pow(2.0 * kW, q.r);
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+        const int nv = std::min(chunk, nvec - v0);
+        NuArgs a{};
+        a.r = q.r;
+        a.K = q.K;
+        a.nv = nv;
+        a.N = q.N;
+        for (int d = 0; d < 2; ++d) {
+            a.Mr[d] = q.Mr[d];
+            a.Mh[d] = q.Mh[d];
+        }
+        a.cells = q.cells;
+        a.b4 = (float)(4.0 * q.b);
+        a.n1 = q.n1;
+        a.n2 = q.n2;
+        a.sbase = q.sbase;
+        a.sfrac = q.sfrac;
+        a.pre = q.pre;
+        a.tbase = q.tbase;
+        a.tfrac = q.tfrac;
+        a.post = q.post;
+        a.dec0 = q.dec[0];
+        a.dec1 = q.dec[1];
+        a.a = q.a;
+        a.b = q.bb;
+        a.f = f + (size_t)v0 * q.N;
+        a.g = g + (size_t)v0 * q.N;
+        a.grid = (float2*)ws;
+        const long long ncols = (long long)nv * q.K;
+        const long long gcells = ncols * q.cells;
+        {
+            ProfScope ps(p, st);
+            hipLaunchKernelGGL(nufft_zero, dim3(blocks_for_n(gcells)),
+                               dim3(kNufftThreads), 0, st, a.grid, gcells);
+            ps.end("nufft_zero", 0.0, 0.0, gcells * 8.0);
+        }
+        {
+            ProfScope ps(p, st);
+            if (q.r == 1)
+                hipLaunchKernelGGL(nufft_spread<1>, dim3(blocks_for_n(q.N)),
+                                   dim3(kNufftThreads), 0, st, a);
+            else
+                hipLaunchKernelGGL(nufft_spread<2>, dim3(blocks_for_n(q.N)),
+                                   dim3(kNufftThreads), 0, st, a);
+            ps.end("nufft_spread", N * nv * 8.0 + N * q.K * 8.0 + N * 16.0,
+                   N * ncols * (stencil * 4.0 + 12.0), N * ncols * stencil * 8.0);
+        }
+        {
+            ProfScope ps(p, st);
+            std::string err = launch_fft(q, a.grid, (int)ncols, st);
+            if (!err.empty()) return err;
+            const double passes = q.r == 2 || q.n1 ? 2.0 : 1.0;
+            ps.end("nufft_fft", 0.0,
+                   5.0 * gcells * std::log2((double)q.cells),
+                   2.0 * passes * gcells * 8.0);
+        }
+        {
+            ProfScope ps(p, st);
+            const long long nt = q.N * nv;
+            if (q.r == 1)
+                hipLaunchKernelGGL(nufft_interp<1>, dim3(blocks_for_n(nt)),
+                                   dim3(kNufftThreads), 0, st, a);
+            else
+                hipLaunchKernelGGL(nufft_interp<2>, dim3(blocks_for_n(nt)),
+                                   dim3(kNufftThreads), 0, st, a);
+            ps.end("nufft_interp", N * nv * 8.0 + N * q.K * 8.0 + N * 16.0,
+                   N * ncols * (stencil * 4.0 + 8.0), N * ncols * stencil * 8.0);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return std::string("nufft launch: ") + hipGetErrorString(e);
+    }
+    return "";
+}
+
+}  // namespace bfi

@@ -1,0 +1,179 @@
+"""NUFFT by dimension lifting on the GPU (Section 3, eq. (eqn:tg3),
+Algorithm 6), through the C ABI.
+
+* the bare type-3 transform (one term, a = b = 1) at random points in one
+  and two dimensions, including a 1D grid past one workgroup's FFT (the
+  four-step transform), against the oracle's direct sum: relative l2 <=
+  1e-5;
+* the whole path on kernels whose phase is given by low-rank factors: the
+  library's Algorithm 6 decides, its factors P, Q, a, b feed the GPU plan,
+  and the apply matches the oracle's direct sum of eq. (eqn:tg3) with the
+  same factors (<= 1e-5) and the dense FP64 matvec of the kernel within the
+  factorization's own error (measured by the oracle) plus 1e-5:
+    - a wave-equation-like phase x xi + tau c(x)|xi| (small tau: the
+      residual after lifting to r = 1 has small numerical rank);
+    - the 1D FIO phase of the workloads, exactly rank 2, with the sincos
+      amplitude: lifting to r = 2 leaves the amplitude (rank 2);
+* a kernel the test refuses (the FIO phase lifted to r = 1) gets the
+  butterfly plan instead (plan_for_kernel), checked against the oracle's
+  butterfly of the same low-rank phase;
+* the allocation-free and chained entry points accept a NUFFT plan."""
+
+import numpy as np
+import pytest
+
+from _util import log, rel
+from oracle import lifting as ol
+from oracle.butterfly import butterfly_matvec
+from oracle.dense import dense_rows
+from synthetic import gaussian_vectors, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _grid(N):
+    return np.arange(N) / N, (np.arange(N) - N // 2).astype(float)
+
+
+def _draws(seed, N, r1, r_eps, q=3, rounds=2, extra=4):
+    rng = np.random.default_rng(seed)
+    omega = rng.standard_normal((N, r1 + 3))
+    test = rng.choice(N, min(N, r_eps * q), replace=False)
+    rows = np.stack([rng.choice(N, r_eps * q, replace=False)
+                     for _ in range(rounds)])
+    cols = np.stack([rng.choice(N, r_eps * q, replace=False)
+                     for _ in range(rounds)])
+    return omega, test, (rows, cols, rng.choice(N, extra, replace=False),
+                         rng.choice(N, extra, replace=False))
+
+
+def _gpu_apply(plan, f):
+    import torch
+    ft = torch.from_numpy(np.ascontiguousarray(f.astype(np.complex64)))
+    g = plan.apply(ft.to("cuda"))
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("r,N,ext", [(1, 3000, (40.0,)),
+                                     (1, 8192, (4096.0,)),
+                                     (2, 2500, (30.0, 12.0)),
+                                     (2, 2000, (3.0, 200.0))])
+def test_type3_transform_against_direct_sum(r, N, ext):
+    import paper_1803_04128_amd as bfm
+    log(f"case lifted type-3 r={r} N={N} extents={ext}")
+    rng = np.random.default_rng(N + r)
+    # space-bandwidth ext_d = X_d S_d per dimension, off-center points
+    t = rng.uniform(-0.5, 0.5, (N, r)) * np.sqrt(ext) + 0.37
+    s = rng.uniform(-0.5, 0.5, (N, r)) * np.sqrt(ext) - 1.3
+    one = np.ones((1, N), np.complex128)
+    f = gaussian_vectors(N, 2, 9)
+    f32 = f.astype(np.complex64).astype(np.complex128)
+    with bfm.plan_lifted(t, s, one, one, max_nvec=2) as pl:
+        assert pl.info()["method"] == 1
+        g = _gpu_apply(pl, f32)
+    ref = ol.nufft3_direct(t, s, f32)
+    e = np.max(rel(g, ref))
+    log(f"  GPU vs direct sum {e:.3e}")
+    assert e < TOL
+
+
+def _wave_factors(N, tau):
+    """Phi = x xi + tau c(x)|xi|, c = (2 + sin 2 pi x)/8, rank 2."""
+    x, xi = _grid(N)
+    c = (2 + np.sin(2 * np.pi * x)) / 8
+    return np.stack([x, tau * c], 1), np.stack([xi, np.abs(xi)], 1)
+
+
+def _fio_factors(N):
+    x, xi = _grid(N)
+    c = (2 + np.sin(2 * np.pi * x)) / 8
+    return (np.stack([x, c, np.zeros(N)], 1),
+            np.stack([xi, np.abs(xi), np.zeros(N)], 1))
+
+
+def _sincos(N):
+    x, xi = _grid(N)
+    return (np.stack([np.ones(N), 0.5 * np.sin(2 * np.pi * x)], 1),
+            np.stack([np.ones(N), np.cos(2 * np.pi * xi / N)], 1))
+
+
+@pytest.mark.parametrize("case", ["wave_r1", "fio_r2"])
+def test_unified_path_against_oracle(case):
+    import paper_1803_04128_amd as bfm
+    if case == "wave_r1":
+        N, r, r_eps, eps = 4096, 1, 24, 1e-9
+        U1, V1 = _wave_factors(N, 8.0 / N)
+        U2, V2 = np.ones((N, 1)), np.ones((N, 1))
+        amp_kind = "one"
+    else:
+        N, r, r_eps, eps = 512, 2, 4, 1e-10
+        U1, V1 = _fio_factors(N)
+        U2, V2 = _sincos(N)
+        amp_kind = "sincos"
+    log(f"case lifted path {case} N={N} r={r} r_eps={r_eps}")
+    omega, test, samples = _draws(21, N, U1.shape[1], r_eps)
+    y, n, P, Q, a, b = bfm.lift_decide(U1, V1, U2, V2, r, r_eps, eps, omega,
+                                       test, samples)
+    log(f"  Algorithm 6: y={y}, sampled rank {n}, terms {a.shape[0]}")
+    assert y == 1
+    f = gaussian_vectors(N, 3, 31)
+    f32 = f.astype(np.complex64).astype(np.complex128)
+    with bfm.plan_lifted(P, Q, a, b, max_nvec=3) as pl:
+        g = _gpu_apply(pl, f32)
+        # the allocation-free entry point on the same plan
+        import torch
+        ft = torch.from_numpy(f32.astype(np.complex64)).to("cuda")
+        gs = pl.apply_static(ft).cpu().numpy().astype(np.complex128)
+        assert np.max(rel(gs, g)) < TOL
+    rows = sample_rows(N, 256, 7)
+    ref = ol.lifted_matvec(P, Q, a, b, f32, rows=rows)
+    e = np.max(rel(g[:, rows], ref))
+    dense = dense_rows(1, N, "lowrank", (U1, V1), amp_kind, f32, rows)
+    eps_lr = np.max(rel(ref, dense))
+    ed = np.max(rel(g[:, rows], dense))
+    log(f"  GPU vs eq. (tg3) direct {e:.3e}; vs dense {ed:.3e} "
+        f"(factorization error {eps_lr:.3e})")
+    assert e < TOL
+    assert ed < eps_lr + TOL
+
+
+def test_refused_kernel_gets_the_butterfly():
+    import paper_1803_04128_amd as bfm
+    N = 1024
+    U1, V1 = _fio_factors(N)
+    U1, V1 = U1[:, :2].copy(), V1[:, :2].copy()
+    ones = np.ones((N, 1))
+    omega, test, samples = _draws(5, N, 2, 8)
+    log("case lifted path refused: FIO phase lifted to r = 1")
+    pl, (y, n) = bfm.plan_for_kernel(U1, V1, ones, ones, 1, 8, 1e-9, omega,
+                                     test, samples, q=8, max_nvec=2)
+    with pl:
+        assert y == 0 and n > 8 and pl.info()["method"] == 0
+        f = gaussian_vectors(N, 2, 3).astype(np.complex64).astype(
+            np.complex128)
+        g = _gpu_apply(pl, f)
+    ref = butterfly_matvec(1, N, "lowrank", (U1, V1), 8,
+                           np.ones((1, N), np.complex128),
+                           np.ones((1, N), np.complex128), f)
+    e = np.max(rel(g, ref))
+    log(f"  butterfly of the low-rank phase vs oracle {e:.3e}")
+    assert e < TOL
+
+
+def test_lifted_plan_refuses_what_it_cannot_hold():
+    import paper_1803_04128_amd as bfm
+    from paper_1803_04128_amd import BfError
+    N = 4096
+    rng = np.random.default_rng(2)
+    # 2D extents whose grid would exceed 4096 points per dimension
+    t = rng.uniform(-1, 1, (N, 2)) * 100
+    s = rng.uniform(-1, 1, (N, 2)) * 100
+    one = np.ones((1, N), np.complex128)
+    with pytest.raises(BfError, match="too large"):
+        bfm.plan_lifted(t, s, one, one)
+    with bfm.plan_lifted(t[:, :1] * 0.01, s[:, :1], one, one) as pl:
+        with pytest.raises(BfError):
+            pl.set_config("fused")
