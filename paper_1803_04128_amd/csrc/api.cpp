@@ -242,9 +242,6 @@ static int configure_plan(const bf_grid* grid, const bf_phase* phase,
     if (max_nvec < 1) return fail(BF_EINVAL, "bf_plan: max_nvec < 1");
     if (op < BF_OP_N || op > BF_OP_H)
         return fail(BF_EINVAL, "bf_plan_op: unknown op");
-    if (precision != BF_FP32 && dim != 1)
-        return fail(BF_EUNSUPPORTED,
-                    "bf_plan: split precisions are implemented for 1D grids");
     int need = -1;
     switch (phase->kind) {
         case BF_PHASE_DFT: need = 0; break;

@@ -197,6 +197,9 @@ static void launch_step_basic(const Step& s, const StepArgs& a,
 std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
                              hipStream_t st);
 
+std::string launch_step_split(const Plan& p, const Step& s,
+                              const StepArgs& a, hipStream_t st);
+
 std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
                       float2* buf0, float2* buf1, hipStream_t st) {
     const int Vc = nv * p.r_amp;
@@ -217,7 +220,14 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
                            : s.kind == STEP_X ? "x_step_basic"
                                               : "switch_basic";
         ProfScope ps(p, st);
-        if (p.mfma) {
+        if (p.mfma && p.precision != BF_FP32) {
+            // split-precision contractions on MFMA
+            std::string err = launch_step_split(p, s, a, st);
+            if (!err.empty()) return err;
+            name = s.kind == STEP_XI ? "xi_step_split"
+                   : s.kind == STEP_X ? "x_step_split"
+                                      : "switch_step_split";
+        } else if (p.mfma) {
             // contractions on MFMA (one launch per step)
             std::string err = launch_step_mfma(p, s, a, st);
             if (!err.empty()) return err;

@@ -11,6 +11,8 @@ struct StepArgs {
     const float2* tw;
     const float* mats;
     const float* amat;     // mats in MFMA A-operand order (Step::amat)
+    const uint16_t* a16_hi;  // split parts of mats (Step::a16_hi / a16_lo)
+    const uint16_t* a16_lo;
     const float2* S;
     const float2* f;       // vector chunk [nv][N] (when reads_f)
     const float2* bamp;    // b_k [r][N] or nullptr (alpha = 1)
@@ -60,6 +62,8 @@ inline StepArgs make_step_args(const Plan& p, const Step& s, int Vc,
     a.tw = s.tw;
     a.mats = s.mats;
     a.amat = s.amat;
+    a.a16_hi = s.a16_hi;
+    a.a16_lo = s.a16_lo;
     a.S = s.S;
     a.f = f;
     a.bamp = p.has_amp ? p.b_dev : nullptr;

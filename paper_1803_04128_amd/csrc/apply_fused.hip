@@ -514,6 +514,7 @@ void init_kernel_attrs() {
     set_lds_limit<2, 16, 2>();
     set_lds_limit<4, 32, 2>();
     init_mfma_attrs();
+    init_step_split_attrs();
 }
 
 // dry: check every pass of the configuration (LDS, tile caps, grid) and

@@ -23,6 +23,7 @@
 // end use A = 0 and read valid (finite) data, so the loads need no guards.
 // R = 2, r <= 16, VT (columns per tile) in {1, 2, 4, 8}.
 #include "fused_common.h"
+#include "split_common.h"
 
 namespace bfi {
 
@@ -46,62 +47,7 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// ---- split precision: x = hi + lo in bfloat16 or half, products
-// hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo term is dropped).
-// 16x16x32 layout: A lane l holds A[l%16][8(l/16)+e], B lane l holds
-// B[8(l/16)+e][l%16], e < 8; 16x16x16: 4(l/16)+e, e < 4 (checked by an
-// in-bounds probe).
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef short shortx4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-
-template <int PREC> struct Split;
-
-template <> struct Split<BF_BF16X3> {
-    typedef bf16x8 v8;
-    typedef shortx4 v4;
-    static constexpr bool kScaled = false;   // bfloat16 has the FP32 range
-    static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
-        const __bf16 hv = (__bf16)v;
-        h[e] = hv;
-        l[e] = (__bf16)(v - (float)hv);
-    }
-    static __device__ __forceinline__ void put4(v4& h, v4& l, int e, float v) {
-        const __bf16 hv = (__bf16)v;
-        const __bf16 lv = (__bf16)(v - (float)hv);
-        h[e] = __builtin_bit_cast(short, hv);
-        l[e] = __builtin_bit_cast(short, lv);
-    }
-    static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ floatx4 mma16(v4 a, v4 b, floatx4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-    }
-};
-
-template <> struct Split<BF_FP16X3> {
-    typedef f16x8 v8;
-    typedef f16x4 v4;
-    static constexpr bool kScaled = true;    // half: scale each column
-    static __device__ __forceinline__ void put8(v8& h, v8& l, int e, float v) {
-        const _Float16 hv = (_Float16)v;
-        h[e] = hv;
-        l[e] = (_Float16)(v - (float)hv);
-    }
-    static __device__ __forceinline__ void put4(v4& h, v4& l, int e, float v) {
-        const _Float16 hv = (_Float16)v;
-        h[e] = hv;
-        l[e] = (_Float16)(v - (float)hv);
-    }
-    static __device__ __forceinline__ floatx4 mma32(v8 a, v8 b, floatx4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ floatx4 mma16(v4 a, v4 b, floatx4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
-    }
-};
+// ---- split precision: the Split<PREC> parts and products (split_common.h)
 
 // Exponent e of a power-of-two column scale for the half-precision split:
 // m is this lane's largest magnitude; the lanes 16, 32 and 48 apart hold
@@ -734,6 +680,109 @@ __device__ __forceinline__ void mfma_switch(const PassArgs& a, float2* tile,
     __syncthreads();
 }
 
+// Split-precision switch (BF16x3 / FP16x3).  The stored blocks of a split
+// plan hold, per entry, the 16-bit parts (Re hi, Re lo, Im hi, Im lo) of
+// S_{AB}[t][s] (split once at plan time), so a block streams the same bytes
+// as in FP32.  One pair per wave and round, r_in <= 16: a single 16x16x16
+// product per part, lane l holding A[l % 16][4 (l / 16) + e] and
+// B[4 (l / 16) + e][l % 16], e < 4.  Re nu and Im nu come from A = Re S and
+// A = Im S, each as hi*hi + hi*lo + lo*hi on the split panel (FP16: each
+// column scaled by a power of two first), with the cross term from the
+// neighbouring lane as in FP32.
+template <int PREC>
+struct SwRoundSplit {
+    typename Split<PREC>::v4 rh, rl, ih, il;
+};
+
+template <int PREC>
+__device__ __forceinline__ void sw_load_split(const PassArgs& a, long long a0,
+                                              long long bfix, int r0,
+                                              SwRoundSplit<PREC>& R) {
+    using V = typename Split<PREC>::v4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r_in = a.sw_r_in, r_out = a.sw_r_out;
+    const int shiftB = a.L - (a.la - 1 + a.k);
+    const int g = lane >> 4, tA = lane & 15;
+    const int slot = r0 + wave;
+    R.rh = R.rl = R.ih = R.il = V{};
+    if (slot >= a.Gk || tA >= r_out) return;
+    const unsigned dA = (unsigned)digit_rev(slot, a.k, 1);
+    const ushort4* S = (const ushort4*)a.S +
+                       (size_t)((a0 << shiftB) + bfix) * r_out * r_in +
+                       (size_t)(dA << shiftB) * (unsigned)(r_out * r_in) +
+                       (size_t)tA * r_in;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int sx = 4 * g + e;
+        ushort4 q = make_ushort4(0, 0, 0, 0);
+        if (sx < r_in) q = S[sx];
+        using E = typename Split<PREC>::e4;
+        R.rh[e] = __builtin_bit_cast(E, q.x);
+        R.rl[e] = __builtin_bit_cast(E, q.y);
+        R.ih[e] = __builtin_bit_cast(E, q.z);
+        R.il[e] = __builtin_bit_cast(E, q.w);
+    }
+}
+
+template <int VT, int PREC>
+__device__ __forceinline__ void mfma_switch_split(
+    const PassArgs& a, float2* tile, long long a0, long long bfix,
+    const SwRoundSplit<PREC>& first) {
+    using SP = Split<PREC>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int r_in = a.sw_r_in, r_out = a.sw_r_out;
+    const int g = lane >> 4;
+    const int n = lane & 15;
+    const int col = n >> 1, reim = n & 1;
+    const int colc = col < VT ? col : 0;
+    float* tf = (float*)tile;
+    SwRoundSplit<PREC> cur = first;
+    for (int r0 = 0; r0 < a.Gk; r0 += nwaves) {   // rounds of pairs
+        SwRoundSplit<PREC> nxt;
+        if (r0 + nwaves < a.Gk) sw_load_split<PREC>(a, a0, bfix, r0 + nwaves, nxt);
+        const int slot = r0 + wave;
+        if (slot < a.Gk) {
+            const int base = slot * a.rmax * VT * 2;
+            float bv[4];
+            float m = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int sx = 4 * g + e;
+                // rows past r_in meet A = 0; zeroed so that they set no scale
+                bv[e] = (sx < r_in && col < VT)
+                            ? tf[base + (sx * VT + colc) * 2 + reim] : 0.f;
+                if constexpr (SP::kScaled) m = fmaxf(m, fabsf(bv[e]));
+            }
+            int ex = 0;
+            if constexpr (SP::kScaled) ex = column_exponent(m);
+            typename SP::v4 bh, bl;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                SP::put4(bh, bl, e, SP::kScaled ? ldexpf(bv[e], -ex) : bv[e]);
+            const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+            floatx4 ar = SP::mma16(cur.rh, bh, z), ai = SP::mma16(cur.ih, bh, z);
+            ar = SP::mma16(cur.rh, bl, ar);
+            ai = SP::mma16(cur.ih, bl, ai);
+            ar = SP::mma16(cur.rl, bh, ar);
+            ai = SP::mma16(cur.il, bh, ai);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if constexpr (SP::kScaled) {
+                    ar[jj] = ldexpf(ar[jj], ex);
+                    ai[jj] = ldexpf(ai[jj], ex);
+                }
+                const float p = lane_swap1(ai[jj]);
+                const float v = reim ? ar[jj] + p : ar[jj] - p;
+                const int t = 4 * g + jj;
+                if (col < VT && t < r_out) tf[base + (t * VT + col) * 2 + reim] = v;
+            }
+        }
+        cur = nxt;
+    }
+    __syncthreads();
+}
+
 // A operand of level j from a pass's per-workgroup LDS copy.
 __device__ __forceinline__ void read_amat(const float* AX, int j,
                                           float (&aM)[8]) {
@@ -852,16 +901,21 @@ xi_pass_mfma(PassArgs a) {
             const int j = a.k;
             if constexpr (kAX) read_amat(AX, j, aM);
             SwRound<sw_pairs<PREC>()> sw0;
-            if constexpr (sw_ahead<PREC>())
-                if (a.has_switch) sw_load(a, ap_grp * a.Gk, bg, 0, sw0);
+            SwRoundSplit<PREC == BF_FP32 ? BF_BF16X3 : PREC> sws0;
+            if constexpr (PREC != BF_FP32)
+                if (a.has_switch) sw_load_split<PREC>(a, ap_grp * a.Gk, bg, 0, sws0);
             const bool from_f = j == 1 && fsep;
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     (j & 1) ? W0 : W1, j, aM, pad);
             __syncthreads();
-            if (a.has_switch)
-                mfma_switch<VT, sw_pairs<PREC>(), sw_ahead<PREC>()>(
-                    a, T, ap_grp * a.Gk, bg, sw0);
+            if (a.has_switch) {
+                if constexpr (PREC == BF_FP32)
+                    mfma_switch<VT, sw_pairs<PREC>(), sw_ahead<PREC>()>(
+                        a, T, ap_grp * a.Gk, bg, sw0);
+                else
+                    mfma_switch_split<VT, PREC>(a, T, ap_grp * a.Gk, bg, sws0);
+            }
         }
         store_tile(a, T, ap_grp * a.Gk, bg, chunk);
         __syncthreads();

@@ -81,6 +81,12 @@ struct Step {
     size_t tw_elems = 0, mat_elems = 0, S_elems = 0, amat_elems = 0;
     size_t amat_xi_elems = 0;
     size_t asplit_elems = 0;  // 512 per step with a matrix (split plans)
+    // split plans of the per-step form (2D): hi and lo 16-bit parts of mats
+    // in the A order of 16x16x16 products, [R][ceil(r_out/16)][ceil(r_in/16)]
+    // [lane][4], lane l holding M[16 mt + l % 16][16 kb + 4 (l / 16) + e]
+    uint16_t* a16_hi = nullptr;
+    uint16_t* a16_lo = nullptr;
+    size_t a16_elems = 0;
     std::vector<double> mats_host;  // FP64 Lagrange matrices
 };
 
@@ -218,6 +224,10 @@ inline bool reads_stored_switch(const Plan& p) {
 constexpr size_t kStaticScratchBytes = BF_STATIC_SCRATCH_BYTES;
 // its device address on `device` (current), recorded on first use
 std::string static_scratch(int device, void** out);
+// apply_step_split.hip: split-precision per-step kernels
+void init_step_split_attrs();
+// "" when the plan's execution form can run its precision
+std::string split_form_error(const Plan& p);
 // apply.hip
 std::string launch_apply(Plan& p, int nvec, const void* f, void* g, void* ws,
                          size_t ws_bytes, hipStream_t stream);

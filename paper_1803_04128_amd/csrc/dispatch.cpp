@@ -85,8 +85,10 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     while (chunk > 1 && 2 * state_bytes(p, chunk) > ws_bytes) --chunk;
     if (2 * state_bytes(p, chunk) > ws_bytes)
         return "workspace too small for one vector";
-    if (!p.fused && p.precision != BF_FP32)
-        return "split precision needs the fused passes";
+    {
+        std::string why = split_form_error(p);
+        if (!why.empty()) return why;
+    }
     if (reads_stored_switch(p) && !p.S_arena) {
         for (const auto& s : p.steps)
             if (s.S_elems) return "switch blocks are not stored";
@@ -118,10 +120,22 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     return "";
 }
 
+std::string split_form_error(const Plan& p) {
+    if (p.precision == BF_FP32) return "";
+    if (p.dim == 1 && !p.fused)
+        return "split precision needs the fused passes in 1D";
+    if (p.dim == 2 && (p.fused || !p.mfma || p.switch_otf))
+        return "split precision needs the per-step MFMA form with stored "
+               "switch blocks in 2D";
+    return "";
+}
+
 std::string check_config(Plan& p) {
     if (p.nufft) return "";
-    if (p.precision != BF_FP32 && !p.fused)
-        return "split precision needs the fused passes";
+    {
+        std::string why = split_form_error(p);
+        if (!why.empty()) return why;
+    }
     if (!p.fused) return "";
     // every chunk width the applies can take: the full chunk and a tail
     const int widths[2] = {p.chunk_nvec, 1};

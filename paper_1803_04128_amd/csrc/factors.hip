@@ -36,6 +36,50 @@ constexpr int kFactorBlock = 256;
             return std::string(#x ": ") + hipGetErrorString(e_);        \
     } while (0)
 
+// Stored switch blocks of a split-precision plan: each complex64 entry is
+// replaced in place by its 16-bit parts (Re hi, Re lo, Im hi, Im lo), the
+// same 8 bytes, in bfloat16 (round to nearest even) or half.
+__global__ void split_switch_blocks(float2* S, long long count, int use_half) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         i < count; i += (long long)gridDim.x * blockDim.x) {
+        const float2 v = S[i];
+        unsigned short h[4];
+        const float parts[2] = {v.x, v.y};
+        for (int c = 0; c < 2; ++c) {
+            const float x = parts[c];
+            if (use_half) {
+                const __half hi = __float2half_rn(x);
+                const __half lo = __float2half_rn(x - __half2float(hi));
+                h[2 * c] = __half_as_ushort(hi);
+                h[2 * c + 1] = __half_as_ushort(lo);
+            } else {
+                const unsigned u = __float_as_uint(x);
+                const unsigned hb = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+                const float r = x - __uint_as_float(hb);
+                const unsigned ul = __float_as_uint(r);
+                const unsigned lb = (ul + 0x7fffu + ((ul >> 16) & 1u)) >> 16;
+                h[2 * c] = (unsigned short)(hb >> 16);
+                h[2 * c + 1] = (unsigned short)lb;
+            }
+        }
+        ((ushort4*)S)[i] = make_ushort4(h[0], h[1], h[2], h[3]);
+    }
+}
+
+// hi + lo of a split entry (read-back of split plans)
+__device__ __forceinline__ float2 join_split(float2 raw, int split) {
+    const ushort4 q = __builtin_bit_cast(ushort4, raw);
+    if (split == BF_FP16X3)
+        return make_float2(__half2float(__ushort_as_half(q.x)) +
+                               __half2float(__ushort_as_half(q.y)),
+                           __half2float(__ushort_as_half(q.z)) +
+                               __half2float(__ushort_as_half(q.w)));
+    return make_float2(__uint_as_float((unsigned)q.x << 16) +
+                           __uint_as_float((unsigned)q.y << 16),
+                       __uint_as_float((unsigned)q.z << 16) +
+                           __uint_as_float((unsigned)q.w << 16));
+}
+
 // The phase terms of one stored factor entry: the entry is
 // exp(2 pi i [Phi(ix_0, jx_0) - Phi(ix_1, jx_1) - Phi(ix_2, jx_2)]) over the
 // first `count` terms (grid coordinates; ix on the output tree, jx on the
@@ -166,7 +210,8 @@ __global__ void switch_blocks(TwArgs a) {
 // stored value.  kind: STEP_XI / STEP_X (twiddles) or STEP_SWITCH (blocks).
 __global__ void factor_entries(TwArgs a, int kind, const float2* src,
                                const long long* idx, int count,
-                               long long* xo, long long* jo, float2* val) {
+                               long long* xo, long long* jo, float2* val,
+                               int split) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
     const long long e = idx[k];
@@ -177,7 +222,7 @@ __global__ void factor_entries(TwArgs a, int kind, const float2* src,
         xo[3 * k + t] = t < T.count ? user_index(T.ix[t], a.P.dim, a.P.n) : -1;
         jo[3 * k + t] = t < T.count ? user_index(T.jx[t], a.P.dim, a.P.n) : -1;
     }
-    val[k] = src[e];
+    val[k] = split ? join_split(src[e], split) : src[e];
 }
 
 std::string read_factor_entries(const Plan& p, int step, int which,
@@ -213,7 +258,8 @@ std::string read_factor_entries(const Plan& p, int step, int which,
     if (e == hipSuccess) {
         hipLaunchKernelGGL(factor_entries, dim3((count + 255) / 256),
                            dim3(256), 0, 0, t, s.kind, src, di, count, dx, dj,
-                           dv);
+                           dv,
+                           which == 1 && p.precision != BF_FP32 ? p.precision : 0);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -274,6 +320,7 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Offsets of every factor array inside the plan arena.
 struct ArenaLayout {
     std::vector<size_t> off_tw, off_m, off_hi, off_lo, off_am, off_ax, off_af;
+    std::vector<size_t> off_2f, off_2h, off_2l;   // 2D split tables
     size_t off_a = 0, off_b = 0, bytes = 0;
 };
 
@@ -306,6 +353,17 @@ static ArenaLayout arena_layout(Plan& p) {
         bytes = align_up(bytes + s.asplit_elems * 2);
         off_lo.push_back(bytes);
         bytes = align_up(bytes + s.asplit_elems * 2);
+        // split plans of the per-step form: the 16x16x16 A tables
+        s.a16_elems = 0;
+        if (split && s.mat_elems && p.dim == 2)
+            s.a16_elems = (size_t)p.R * ((s.r_out + 15) / 16) *
+                          ((s.r_in + 15) / 16) * 256;
+        A.off_2f.push_back(bytes);
+        bytes = align_up(bytes + s.a16_elems * sizeof(float));
+        A.off_2h.push_back(bytes);
+        bytes = align_up(bytes + s.a16_elems * 2);
+        A.off_2l.push_back(bytes);
+        bytes = align_up(bytes + s.a16_elems * 2);
     }
     A.off_a = bytes;
     if (p.has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
@@ -402,6 +460,34 @@ std::string build_factors(Plan& p) {
                                  s.amat_xi_elems * sizeof(float),
                                  hipMemcpyHostToDevice));
             }
+            if (s.a16_elems) {
+                // 16x16x16 A tables of the per-step split kernels, arranged
+                // in FP32, then split into hi and lo parts on the device
+                const int MTs = (s.r_out + 15) / 16, KB = (s.r_in + 15) / 16;
+                std::vector<float> af(s.a16_elems, 0.f);
+                for (int c = 0; c < p.R; ++c)
+                    for (int mt = 0; mt < MTs; ++mt)
+                        for (int kb = 0; kb < KB; ++kb)
+                            for (int l = 0; l < 64; ++l)
+                                for (int e = 0; e < 4; ++e) {
+                                    const int t = 16 * mt + l % 16;
+                                    const int sx = 16 * kb + 4 * (l / 16) + e;
+                                    if (t < s.r_out && sx < s.r_in)
+                                        af[((((size_t)c * MTs + mt) * KB + kb) * 64 + l) * 4 + e] =
+                                            mf[((size_t)c * s.r_out + t) * s.r_in + sx];
+                                }
+                float* dev = (float*)(base + A.off_2f[k]);
+                s.a16_hi = (uint16_t*)(base + A.off_2h[k]);
+                s.a16_lo = (uint16_t*)(base + A.off_2l[k]);
+                HIPCHK(hipMemcpy(dev, af.data(), af.size() * sizeof(float),
+                                 hipMemcpyHostToDevice));
+                hipLaunchKernelGGL(split_matrices,
+                                   dim3(grid_for((long long)s.a16_elems)),
+                                   dim3(kFactorBlock), 0, 0, dev, s.a16_hi,
+                                   s.a16_lo, (long long)s.a16_elems,
+                                   p.precision == BF_FP16X3 ? 1 : 0);
+                HIPCHK(hipGetLastError());
+            }
             if (s.asplit_elems) {
                 // A operands of the split products, arranged per lane, then
                 // split into hi and lo parts on the device
@@ -489,6 +575,13 @@ std::string build_switch_blocks(Plan& p) {
         hipLaunchKernelGGL(switch_blocks, dim3(grid_for(t.total)),
                            dim3(kFactorBlock), 0, 0, t);
     }
+    // split-precision plans read the blocks only in the split MFMA switch
+    if (p.precision != BF_FP32)
+        hipLaunchKernelGGL(split_switch_blocks,
+                           dim3(grid_for((long long)(bytes / sizeof(float2)))),
+                           dim3(kFactorBlock), 0, 0, (float2*)mem,
+                           (long long)(bytes / sizeof(float2)),
+                           p.precision == BF_FP16X3 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {

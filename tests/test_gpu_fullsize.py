@@ -14,7 +14,8 @@ tests/golden/make_fullsize.py stored (oracle/ alone):
     at those rows, stated in the log.
 Workloads: the batched 1D FIO (N = 2^18, r = 4, 64 vectors), the 2D Radon
 FIO at n = 256 and n = 512 (16 vectors), the precision sweep (N = 2^20,
-r = 4, 256 vectors); the split precisions at both 1D sizes; the batched
+r = 4, 256 vectors); the split precisions at both 1D sizes and the 2D
+Radon size (per-step MFMA kernels); the batched
 plan built for a single vector (both passes in 512-thread workgroups)."""
 
 import json
@@ -95,7 +96,7 @@ def test_full_size_fp32_all_entries(name):
 
 
 @pytest.mark.parametrize("name", ["fio1d_n262144_batched",
-                                  "fio1d_n1048576_sweep"])
+                                  "fio1d_n1048576_sweep", "radon2d_n256"])
 @pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
 def test_split_precision_all_entries(name, precision):
     picks = list(fo.JOBS[name])

@@ -257,8 +257,64 @@ def test_split_precision_any_input_scale(apply_path, precision, scale):
     assert err < SPLIT_TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("n,q,amp,r,nvec", [(32, 7, "one", 1, 3),
+                                            (64, 7, "sincos", 2, 2),
+                                            (128, 6, "one", 1, 17)])
+def test_split_precision_2d(apply_path, precision, n, q, amp, r, nvec):
+    # 2D plans run the split products in the per-step MFMA kernels (the
+    # Lagrange matrices and the stored switch blocks split at plan time)
+    if apply_path != "per_step_mfma":
+        pytest.skip("2D split precisions run on the per-step MFMA kernels")
+    log(f"case split 2D {precision} n={n} q={q} r={r} nvec={nvec}")
+    f32, f, ab = inputs(2, n, nvec, 970 + n, amp=amp, r=r)
+    with _plan(2, n, "radon2d", q, ab=ab, nvec=nvec,
+               precision=precision) as pl:
+        g, _ = gpu_apply(pl, f32)
+    if ab is None:
+        ref = butterfly_apply(2, n, "radon2d", PHASE_PARAMS["radon2d"], q, f)
+    else:
+        ref = butterfly_matvec(2, n, "radon2d", PHASE_PARAMS["radon2d"], q,
+                               ab[0], ab[1], f)
+    err = np.max(rel(g, ref))
+    log(f"  {precision} 2D rel err vs FP64 butterfly = {err:.3e}")
+    assert err < SPLIT_TOL[precision]
+
+
+@pytest.mark.parametrize("scale", [1e6, 1e-6])
+def test_split_precision_2d_any_input_scale(apply_path, scale):
+    if apply_path != "per_step_mfma":
+        pytest.skip("2D split precisions run on the per-step MFMA kernels")
+    n, q = 64, 7
+    log(f"case split 2D scale fp16x3 {scale:g}")
+    f32, f, _ = inputs(2, n, 2, 990)
+    f32 = (f32 * np.float32(scale)).astype(np.complex64)
+    with _plan(2, n, "radon2d", q, nvec=2, precision="fp16x3") as pl:
+        g, _ = gpu_apply(pl, f32)
+    ref = butterfly_apply(2, n, "radon2d", PHASE_PARAMS["radon2d"], q,
+                          f32.astype(np.complex128))
+    assert np.all(np.isfinite(g))
+    err = np.max(rel(g, ref))
+    log(f"  rel err {err:.3e}")
+    assert err < SPLIT_TOL["fp16x3"]
+
+
 def test_split_precision_rejected_where_not_built(apply_path):
+    # split products exist in the 1D fused passes and the 2D per-step MFMA
+    # kernels; every other form refuses them instead of computing in FP32
     import paper_1803_04128_amd as bfm
-    with pytest.raises(bfm.BfError):
-        bfm.Plan(2, 64, "radon2d", PHASE_PARAMS["radon2d"], q=7,
-                 precision="bf16x3")
+    if apply_path != "per_step_mfma":
+        with pytest.raises(bfm.BfError):
+            bfm.Plan(2, 64, "radon2d", PHASE_PARAMS["radon2d"], q=7,
+                     precision="bf16x3")
+    if apply_path != "fused":
+        with pytest.raises(bfm.BfError):
+            bfm.Plan(1, 4096, "fio1d", PHASE_PARAMS["fio1d"], q=8,
+                     precision="fp16x3")
+    if apply_path == "per_step_mfma":
+        with bfm.Plan(2, 64, "radon2d", PHASE_PARAMS["radon2d"], q=7,
+                      precision="bf16x3") as pl:
+            with pytest.raises(bfm.BfError):
+                pl.set_config("per_step_mfma", switch_otf=True)
+            with pytest.raises(bfm.BfError):
+                pl.set_config("fused")
