@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libbf.so")
 
 SOURCES = ["geometry.cpp", "factors.hip", "apply_basic.hip",
            "apply_fused.hip", "apply_mfma.hip", "apply_step_mfma.hip",
-           "apply_step_split.hip",
+           "apply_step_split.hip", "apply_step_sep.hip",
            "dispatch.cpp", "api.cpp", "recovery.cpp", "lifting.cpp",
            "nufft.hip"]
 

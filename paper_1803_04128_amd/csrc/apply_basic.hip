@@ -231,10 +231,11 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
             // contractions on MFMA (one launch per step)
             std::string err = launch_step_mfma(p, s, a, st);
             if (!err.empty()) return err;
-            name = s.kind == STEP_XI ? "xi_step_mfma"
-                   : s.kind == STEP_X    ? "x_step_mfma"
-                   : otf                 ? "switch_otf_mfma"
-                                         : "switch_step_mfma";
+            const bool sep = step_sep_ok(p, s);
+            name = s.kind == STEP_XI ? (sep ? "xi_step_sep" : "xi_step_mfma")
+                   : s.kind == STEP_X ? (sep ? "x_step_sep" : "x_step_mfma")
+                   : otf              ? "switch_otf_mfma"
+                                      : "switch_step_mfma";
         } else if (p.dim == 1) {
             if (p.max_rank <= 16) launch_step_basic<2, 16>(s, a, st);
             else return "1D rank above 16";

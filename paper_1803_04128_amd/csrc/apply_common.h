@@ -13,6 +13,8 @@ struct StepArgs {
     const float* amat;     // mats in MFMA A-operand order (Step::amat)
     const uint16_t* a16_hi;  // split parts of mats (Step::a16_hi / a16_lo)
     const uint16_t* a16_lo;
+    const float* amat_sep;   // 2D: A tables of the 1D factors (Step)
+    int a1, b1;              // 2D: input / output points per dimension
     const float2* S;
     const float2* f;       // vector chunk [nv][N] (when reads_f)
     const float2* bamp;    // b_k [r][N] or nullptr (alpha = 1)
@@ -64,6 +66,9 @@ inline StepArgs make_step_args(const Plan& p, const Step& s, int Vc,
     a.amat = s.amat;
     a.a16_hi = s.a16_hi;
     a.a16_lo = s.a16_lo;
+    a.amat_sep = s.amat_sep;
+    a.a1 = s.ax_in.r1;
+    a.b1 = s.ax_out.r1;
     a.S = s.S;
     a.f = f;
     a.bamp = p.has_amp ? p.b_dev : nullptr;

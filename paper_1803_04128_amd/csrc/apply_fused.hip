@@ -515,6 +515,7 @@ void init_kernel_attrs() {
     set_lds_limit<4, 32, 2>();
     init_mfma_attrs();
     init_step_split_attrs();
+    init_step_sep_attrs();
 }
 
 // dry: check every pass of the configuration (LDS, tile caps, grid) and

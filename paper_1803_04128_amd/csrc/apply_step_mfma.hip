@@ -453,6 +453,9 @@ void init_step_mfma_attrs() {
 }
 
 // Launches one step; "" on success.
+std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
+                            hipStream_t st);
+
 std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
                              hipStream_t st) {
     if (s.r_out > kMaxMT * 16) return "step rank above 64";
@@ -505,6 +508,8 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
         const int MT = (s.r_out + 15) / 16;
         hipLaunchKernelGGL(switch_step_mfma, dim3((unsigned)nb), dim3(64 * MT),
                            lds, st, a);
+    } else if (step_sep_ok(p, s)) {
+        return launch_step_sep(p, s, a, st);
     } else {
         const long long nb = s.units * nct;
         if (nb > 0x7fffffffLL) return "step grid too large";

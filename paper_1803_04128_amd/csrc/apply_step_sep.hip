@@ -1,0 +1,281 @@
+// 2D per-step levels with the shared matrices contracted one dimension at a
+// time (FP32 MFMA).  In 2D the Lagrange matrix of a child is the Kronecker
+// product of 1D matrices, M_{(c1,c2)} = L^{c1} (x) L^{c2} (b x a each: b
+// output, a input points per dimension; boxes are square, so both
+// dimensions share L^0 and L^1).  Per unit and 16-column tile:
+//   xi level (eq. (eqn:2) regrouped), output child i:
+//     Z_{c1}[s1][t2] = sum_{c2, s2} L^{c2}[t2][s2] (W_{i,c} . X_c)[s1, s2]
+//     Y_i[t1][t2]    = sum_{c1, s1} L^{c1}[t1][s1] Z_{c1}[s1][t2]
+//   (the second-dimension children summed before the first dimension's
+//   matrix: 4 a^2 b + 2 a b^2 multiply-adds per output child and column);
+//   x level (eq. (eqn:3) regrouped), input child c:
+//     Z_c[i2][s1][t2] = sum_{s2} L^{i2}[t2][s2] X_c[s1, s2]
+//     Y_{i,c}[t1][t2] = sum_{s1} L^{i1}[t1][s1] Z_c[i2][s1][t2]
+//     D_i += T_{i,c} . Y_{i,c}
+//   (the second-dimension products formed once for both first-dimension
+//   children: 2 a^2 b + 4 a b^2 per input child and column).
+// Both stages run on v_mfma_f32_16x16x4f32 with the 1D matrices as A: the
+// xi stages stack the two children along K (rows t, K = (child, s) <= 16),
+// the x stages stack them along the rows (rows (child, t) <= 16, K = s);
+// the two stages of a level meet in LDS.  Operand layout: A lane l =
+// A[l % 16][l / 16], B lane l = B[l / 16][l % 16], D lane l holds
+// D[4 (l / 16) + j][l % 16].
+#include "apply_common.h"
+
+namespace bfi {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCols = 16;
+constexpr int kSepWaves = 16;     // waves per block
+
+__device__ __forceinline__ floatx4 mma(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 zero4() {
+    floatx4 z = {0.f, 0.f, 0.f, 0.f};
+    return z;
+}
+
+}  // namespace
+
+// xi step, block = (unit, 16-column tile), kSepWaves waves: 4 per output
+// child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16].
+__global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
+    extern __shared__ float2 lds_step[];
+    const int A1 = a.a1, B1 = a.b1;
+    float2* xs = lds_step;
+    float2* ws = xs + (size_t)4 * a.r_in * kCols;
+    float2* zs = ws + (size_t)16 * a.r_in;
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    const long long u = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const int shiftB = 2 * (a.L - a.level);
+    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    const int nthr = kSepWaves * 64;
+    const int nin = 4 * a.r_in * kCols;
+    for (int e = threadIdx.x; e < nin; e += nthr) {
+        const int n = e % kCols, cs = e / kCols;
+        const int c = cs / a.r_in, s = cs - c * a.r_in;
+        const int col = col0 + n;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < a.Vc) {
+            if (a.reads_f) {
+                v = head_value(a, b * 4 + c, s, col);
+            } else {
+                const long long pin = (ap << (shiftB + 2)) + (b << 2) + c;
+                v = a.in[(pin * a.r_in + s) * a.Vc + col];
+            }
+        }
+        xs[e] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * a.r_in; e += nthr)
+        ws[e] = a.tw[u * 16 * a.r_in + e];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = wave >> 2, h = wave & 3;
+    const int g = lane >> 4, n = lane & 15;
+    const int nks = (2 * A1 + 3) >> 2;
+    float am[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
+    __syncthreads();
+    // stage 1: combos (c1, s1), a wave every fourth
+    for (int cb = h; cb < 2 * A1; cb += 4) {
+        const int c1 = cb / A1, s1 = cb - c1 * A1;
+        floatx4 zr = zero4(), zi = zero4();
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k = 4 * ks + g;
+            float2 z = make_float2(0.f, 0.f);
+            if (k < 2 * A1) {
+                const int c2 = k / A1, s2 = k - c2 * A1;
+                const int c = c1 * 2 + c2, s = s1 * A1 + s2;
+                z = cmul(ws[(i * 4 + c) * a.r_in + s],
+                         xs[((size_t)c * a.r_in + s) * kCols + n]);
+            }
+            zr = mma(am[ks], z.x, zr);
+            zi = mma(am[ks], z.y, zi);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t2 = 4 * g + j;
+            if (t2 < B1)
+                zs[((((size_t)i * 2 + c1) * A1 + s1) * B1 + t2) * kCols + n] =
+                    make_float2(zr[j], zi[j]);
+        }
+    }
+    __syncthreads();
+    // stage 2: one t2 per wave at a time
+    const int col = col0 + n;
+    const long long pout = ((ap * 4 + i) << shiftB) + b;
+    float2* o = a.out + pout * a.r_out * a.Vc + col;
+    for (int t2 = h; t2 < B1; t2 += 4) {
+        floatx4 yr = zero4(), yi = zero4();
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k = 4 * ks + g;
+            float2 z = make_float2(0.f, 0.f);
+            if (k < 2 * A1) {
+                const int c1 = k / A1, s1 = k - c1 * A1;
+                z = zs[((((size_t)i * 2 + c1) * A1 + s1) * B1 + t2) * kCols + n];
+            }
+            yr = mma(am[ks], z.x, yr);
+            yi = mma(am[ks], z.y, yi);
+        }
+        if (col < a.Vc) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t1 = 4 * g + j;
+                if (t1 < B1)
+                    o[(size_t)(t1 * B1 + t2) * a.Vc] = make_float2(yr[j], yi[j]);
+            }
+        }
+    }
+}
+
+// x step, block = (unit, 16-column tile).  LDS: X [4][r_in][16],
+// T [4][4][r_out], Z [4][2][a][b][16].
+__global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
+    extern __shared__ float2 lds_step[];
+    const int A1 = a.a1, B1 = a.b1;
+    float2* xs = lds_step;
+    float2* ts = xs + (size_t)4 * a.r_in * kCols;
+    float2* zs = ts + (size_t)16 * a.r_out;
+    const int nct = (a.Vc + kCols - 1) / kCols;
+    const long long u = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const int shiftB = 2 * (a.L - a.level);
+    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+    const int nthr = kSepWaves * 64;
+    const int nin = 4 * a.r_in * kCols;
+    for (int e = threadIdx.x; e < nin; e += nthr) {
+        const int n = e % kCols, cs = e / kCols;
+        const int c = cs / a.r_in, s = cs - c * a.r_in;
+        const int col = col0 + n;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < a.Vc) {
+            const long long pin = (ap << (shiftB + 2)) + (b << 2) + c;
+            v = a.in[(pin * a.r_in + s) * a.Vc + col];
+        }
+        xs[e] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * a.r_out; e += nthr)
+        ts[e] = a.tw[u * 16 * a.r_out + e];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, n = lane & 15;
+    const int nks = (A1 + 3) >> 2;
+    float am[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
+    __syncthreads();
+    // stage 1: combos (c, s1); rows (i2, t2)
+    for (int cb = wave; cb < 4 * A1; cb += kSepWaves) {
+        const int c = cb / A1, s1 = cb - c * A1;
+        floatx4 zr = zero4(), zi = zero4();
+        for (int ks = 0; ks < nks; ++ks) {
+            const int s2 = 4 * ks + g;
+            const float2 x = s2 < A1
+                ? xs[((size_t)c * a.r_in + s1 * A1 + s2) * kCols + n]
+                : make_float2(0.f, 0.f);
+            zr = mma(am[ks], x.x, zr);
+            zi = mma(am[ks], x.y, zi);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 4 * g + j;
+            if (row < 2 * B1) {
+                const int i2 = row / B1, t2 = row - i2 * B1;
+                zs[((((size_t)c * 2 + i2) * A1 + s1) * B1 + t2) * kCols + n] =
+                    make_float2(zr[j], zi[j]);
+            }
+        }
+    }
+    __syncthreads();
+    // stage 2 and the twiddles: combos (i2, t2); rows (i1, t1); sum over c
+    const int col = col0 + n;
+    for (int cb = wave; cb < 2 * B1; cb += kSepWaves) {
+        const int i2 = cb / B1, t2 = cb - i2 * B1;
+        floatx4 dr = zero4(), di = zero4();
+        for (int c = 0; c < 4; ++c) {
+            floatx4 yr = zero4(), yi = zero4();
+            for (int ks = 0; ks < nks; ++ks) {
+                const int s1 = 4 * ks + g;
+                const float2 z = s1 < A1
+                    ? zs[((((size_t)c * 2 + i2) * A1 + s1) * B1 + t2) * kCols + n]
+                    : make_float2(0.f, 0.f);
+                yr = mma(am[ks], z.x, yr);
+                yi = mma(am[ks], z.y, yi);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 4 * g + j;
+                if (row < 2 * B1) {
+                    const int i1 = row / B1, t1 = row - i1 * B1;
+                    const int ii = i1 * 2 + i2, t = t1 * B1 + t2;
+                    const float2 T = ts[(ii * 4 + c) * a.r_out + t];
+                    dr[j] += T.x * yr[j] - T.y * yi[j];
+                    di[j] += T.x * yi[j] + T.y * yr[j];
+                }
+            }
+        }
+        if (col < a.Vc) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 4 * g + j;
+                if (row < 2 * B1) {
+                    const int i1 = row / B1, t1 = row - i1 * B1;
+                    const int ii = i1 * 2 + i2, t = t1 * B1 + t2;
+                    const long long pout = ((ap * 4 + ii) << shiftB) + b;
+                    a.out[(pout * a.r_out + t) * a.Vc + col] =
+                        make_float2(dr[j], di[j]);
+                }
+            }
+        }
+    }
+}
+
+size_t step_sep_lds(const Step& s) {
+    const int a1 = s.ax_in.r1, b1 = s.ax_out.r1;
+    const int rt = s.kind == STEP_XI ? s.r_in : s.r_out;
+    return ((size_t)4 * s.r_in * kCols + (size_t)16 * rt +
+            (size_t)8 * a1 * b1 * kCols) * sizeof(float2);
+}
+
+// The separable form applies to 2D steps whose stacked children fit one
+// 16-row / 16-deep MFMA operand (points per dimension <= 8).
+bool step_sep_ok(const Plan& p, const Step& s) {
+    return p.dim == 2 && s.kind != STEP_SWITCH && s.amat_sep &&
+           s.ax_in.r1 <= 8 && s.ax_out.r1 <= 8;
+}
+
+void init_step_sep_attrs() {
+    const void* fns[] = {(const void*)xi_step_sep, (const void*)x_step_sep};
+    for (const void* f : fns)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+}
+
+std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
+                            hipStream_t st) {
+    (void)p;
+    const long long nct = (a.Vc + kCols - 1) / kCols;
+    const long long nb = s.units * nct;
+    if (nb > 0x7fffffffLL) return "step grid too large";
+    const size_t lds = step_sep_lds(s);
+    if (lds > 160 * 1024) return "step does not fit in LDS";
+    a.a1 = s.ax_in.r1;
+    a.b1 = s.ax_out.r1;
+    a.amat_sep = s.amat_sep;
+    if (s.kind == STEP_XI)
+        hipLaunchKernelGGL(xi_step_sep, dim3((unsigned)nb),
+                           dim3(kSepWaves * 64), lds, st, a);
+    else
+        hipLaunchKernelGGL(x_step_sep, dim3((unsigned)nb),
+                           dim3(kSepWaves * 64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
+    return "";
+}
+
+}  // namespace bfi

@@ -87,6 +87,14 @@ struct Step {
     uint16_t* a16_hi = nullptr;
     uint16_t* a16_lo = nullptr;
     size_t a16_elems = 0;
+    // 2D: the 1D factors L^0, L^1 of the Kronecker matrices ([2][b][a],
+    // b = ax_out.r1, a = ax_in.r1) and their A tables for the
+    // one-dimension-at-a-time contractions (apply_step_sep.hip): xi steps
+    // [4][lane] = L^c[l % 16][s] at k = 4 ks + l / 16 = c a + s; x steps
+    // [2][lane] = L^i[t][s] at row l % 16 = i b + t, s = 4 ks + l / 16
+    std::vector<double> lag1_host;
+    float* amat_sep = nullptr;
+    size_t sep_elems = 0;
     std::vector<double> mats_host;  // FP64 Lagrange matrices
 };
 
@@ -224,6 +232,9 @@ inline bool reads_stored_switch(const Plan& p) {
 constexpr size_t kStaticScratchBytes = BF_STATIC_SCRATCH_BYTES;
 // its device address on `device` (current), recorded on first use
 std::string static_scratch(int device, void** out);
+// apply_step_sep.hip: 2D per-step levels contracted per dimension
+bool step_sep_ok(const Plan& p, const Step& s);
+void init_step_sep_attrs();
 // apply_step_split.hip: split-precision per-step kernels
 void init_step_split_attrs();
 // "" when the plan's execution form can run its precision

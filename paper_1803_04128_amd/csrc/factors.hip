@@ -321,6 +321,7 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct ArenaLayout {
     std::vector<size_t> off_tw, off_m, off_hi, off_lo, off_am, off_ax, off_af;
     std::vector<size_t> off_2f, off_2h, off_2l;   // 2D split tables
+    std::vector<size_t> off_sep;                  // 2D separable A tables
     size_t off_a = 0, off_b = 0, bytes = 0;
 };
 
@@ -364,6 +365,10 @@ static ArenaLayout arena_layout(Plan& p) {
         bytes = align_up(bytes + s.a16_elems * 2);
         A.off_2l.push_back(bytes);
         bytes = align_up(bytes + s.a16_elems * 2);
+        s.sep_elems = (p.dim == 2 && !s.lag1_host.empty())
+                          ? (s.kind == STEP_XI ? 256 : 128) : 0;
+        A.off_sep.push_back(bytes);
+        bytes = align_up(bytes + s.sep_elems * sizeof(float));
     }
     A.off_a = bytes;
     if (p.has_amp) bytes = align_up(bytes + (size_t)p.r_amp * p.N * sizeof(float2));
@@ -458,6 +463,34 @@ std::string build_factors(Plan& p) {
                     }
                 HIPCHK(hipMemcpy(s.amat_xi, ax.data(),
                                  s.amat_xi_elems * sizeof(float),
+                                 hipMemcpyHostToDevice));
+            }
+            if (s.sep_elems) {
+                // A tables of the one-dimension-at-a-time 2D contractions
+                const int a1 = s.ax_in.r1, b1 = s.ax_out.r1;
+                std::vector<float> sp(s.sep_elems, 0.f);
+                for (int l = 0; l < 64; ++l) {
+                    const int row = l % 16, kq = l / 16;
+                    if (s.kind == STEP_XI) {
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int k = 4 * ks + kq;
+                            const int c = k / a1, sx = k - c * a1;
+                            if (row < b1 && k < 2 * a1)
+                                sp[(size_t)ks * 64 + l] = (float)
+                                    s.lag1_host[((size_t)c * b1 + row) * a1 + sx];
+                        }
+                    } else {
+                        for (int ks = 0; ks < 2; ++ks) {
+                            const int sx = 4 * ks + kq;
+                            const int i = row / b1, t = row - i * b1;
+                            if (row < 2 * b1 && sx < a1)
+                                sp[(size_t)ks * 64 + l] = (float)
+                                    s.lag1_host[((size_t)i * b1 + t) * a1 + sx];
+                        }
+                    }
+                }
+                s.amat_sep = (float*)(base + A.off_sep[k]);
+                HIPCHK(hipMemcpy(s.amat_sep, sp.data(), sp.size() * sizeof(float),
                                  hipMemcpyHostToDevice));
             }
             if (s.a16_elems) {

@@ -91,6 +91,18 @@ static void xi_matrices(Step& s, int dim, int R) {
     const Axis& C = s.ax_in;
     s.mats_host.assign((size_t)R * s.r_out * s.r_in, 0.0);
     std::vector<double> w(B.r1);
+    // the 1D factors L^c[t][s] = M_t^B(c side_C + off_C[s]) (2D only)
+    s.lag1_host.clear();
+    if (dim == 2) {
+        s.lag1_host.assign((size_t)2 * B.r1 * C.r1, 0.0);
+        for (int c = 0; c < 2; ++c)
+            for (int si = 0; si < C.r1; ++si) {
+                double y = c * C.side + C.off[si];
+                lagrange_1d(B.off, B.r1, &y, 1, w.data());
+                for (int t = 0; t < B.r1; ++t)
+                    s.lag1_host[((size_t)c * B.r1 + t) * C.r1 + si] = w[t];
+            }
+    }
     for (int c = 0; c < R; ++c)
         for (int t = 0; t < s.r_out; ++t)
             for (int si = 0; si < s.r_in; ++si) {
@@ -112,6 +124,18 @@ static void x_matrices(Step& s, int dim, int R) {
     const Axis& A = s.ax_out;
     s.mats_host.assign((size_t)R * s.r_out * s.r_in, 0.0);
     std::vector<double> w(P.r1);
+    // the 1D factors L^i[t][s] = M_s^P(i side_A + off_A[t]) (2D only)
+    s.lag1_host.clear();
+    if (dim == 2) {
+        s.lag1_host.assign((size_t)2 * A.r1 * P.r1, 0.0);
+        for (int i = 0; i < 2; ++i)
+            for (int t = 0; t < A.r1; ++t) {
+                double y = i * A.side + A.off[t];
+                lagrange_1d(P.off, P.r1, &y, 1, w.data());
+                for (int si = 0; si < P.r1; ++si)
+                    s.lag1_host[((size_t)i * A.r1 + t) * P.r1 + si] = w[si];
+            }
+    }
     for (int i = 0; i < R; ++i)
         for (int t = 0; t < s.r_out; ++t)
             for (int si = 0; si < s.r_in; ++si) {

@@ -31,38 +31,44 @@ inline double nearest(double u, double target) {
     return u + std::copysign(std::floor(std::fabs(d) + 0.5), d);
 }
 
-// Algorithm 3 on u[0..n) with stride 1.  fix: optional per-entry values
-// already assigned (NaN = free).  Appends discontinuities to S (S[0] = 0).
+// Algorithm 3 (Section 3.2) on u[0..n) with stride 1, as one forward pass.
+// Each entry takes the representative of u modulo 1 nearest to a
+// prediction from the entries before it in its smooth piece: the very first
+// entry keeps u; with one entry of history the prediction is that entry
+// (the smallest jump), with two the linear continuation, with three or more
+// the continuation of the second difference (the smallest change of the
+// third difference, the TV^3 criterion).  A piece after a discontinuity has
+// the last entry of the previous piece as its first history entry.  Once an
+// entry is assigned from three entries of history, a second difference of
+// more than tau / (2 pi) cycles marks a discontinuity there: the entry
+// starts a new piece and is assigned again from one entry of history.
+// fix: optional per-entry values already assigned (NaN = free).  S receives
+// the piece starts (S[0] = 0).
 void unwrap(const double* u, long long n, double tau, const double* fix,
             double* v, std::vector<long long>& S) {
     S.assign(1, 0);
-    auto put = [&](long long a, double value) {
+    int hist = 0;                       // usable entries before a
+    for (long long a = 0; a < n; ++a) {
+        double value;
+        if (hist == 0)
+            value = u[a];
+        else if (hist == 1)
+            value = nearest(u[a], v[a - 1]);
+        else if (hist == 2)
+            value = nearest(u[a], 2.0 * v[a - 1] - v[a - 2]);
+        else
+            value = nearest(u[a], 3.0 * v[a - 1] - 3.0 * v[a - 2] + v[a - 3]);
         v[a] = (fix && !std::isnan(fix[a])) ? fix[a] : value;
-    };
-    for (size_t c = 0; c < S.size(); ++c) {
-        const long long st = S[c];
-        const long long ed = c + 1 < S.size() ? S[c + 1] - 1 : n - 1;
-        long long bg;
-        if (c == 0) {
-            put(st, u[st]);
-            if (st + 1 <= ed) put(st + 1, nearest(u[st + 1], v[st]));
-            if (st + 2 <= ed)
-                put(st + 2, nearest(u[st + 2], 2.0 * v[st + 1] - v[st]));
-            bg = st + 3;
-        } else {
-            put(st, nearest(u[st], v[st - 1]));
-            if (st + 1 <= ed)
-                put(st + 1, nearest(u[st + 1], 2.0 * v[st] - v[st - 1]));
-            bg = st + 2;
+        if (hist >= 3 &&
+            kTwoPi * std::fabs(v[a] + v[a - 2] - 2.0 * v[a - 1]) > tau) {
+            // a discontinuity: a piece starts here, continued from v[a - 1]
+            S.push_back(a);
+            const double again = nearest(u[a], v[a - 1]);
+            v[a] = (fix && !std::isnan(fix[a])) ? fix[a] : again;
+            hist = 2;
+            continue;
         }
-        for (long long a = bg; a <= ed; ++a) {
-            const double p = 3.0 * v[a - 1] - 3.0 * v[a - 2] + v[a - 3];
-            put(a, nearest(u[a], p));
-            if (kTwoPi * std::fabs(v[a] + v[a - 2] - 2.0 * v[a - 1]) > tau) {
-                S.push_back(a);
-                break;
-            }
-        }
+        ++hist;
     }
 }
 
