@@ -29,7 +29,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCols = 16;
-constexpr int kSepWaves = 16;     // waves per block
+constexpr int kSepWaves = 8;      // waves per block (two blocks share a CU)
 
 __device__ __forceinline__ floatx4 mma(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -42,8 +42,8 @@ __device__ __forceinline__ floatx4 zero4() {
 
 }  // namespace
 
-// xi step, block = (unit, 16-column tile), kSepWaves waves: 4 per output
-// child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16].
+// xi step, block = (unit, 16-column tile), kSepWaves waves: kSepWaves / 4
+// per output child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16].
 __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
@@ -56,45 +56,57 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
     const int shiftB = 2 * (a.L - a.level);
     const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nthr = kSepWaves * 64;
-    const int nin = 4 * a.r_in * kCols;
-    for (int e = threadIdx.x; e < nin; e += nthr) {
-        const int n = e % kCols, cs = e / kCols;
-        const int c = cs / a.r_in, s = cs - c * a.r_in;
-        const int col = col0 + n;
-        float2 v = make_float2(0.f, 0.f);
-        if (col < a.Vc) {
-            if (a.reads_f) {
-                v = head_value(a, b * 4 + c, s, col);
-            } else {
-                const long long pin = (ap << (shiftB + 2)) + (b << 2) + c;
-                v = a.in[(pin * a.r_in + s) * a.Vc + col];
+    {
+        // (child, point) rows advance by nthr / 16 per round; each thread
+        // keeps its column and steps its row without a division
+        const int n = threadIdx.x & (kCols - 1), col = col0 + n;
+        int row = threadIdx.x >> 4;
+        int c = row / a.r_in, s = row - c * a.r_in;
+        const long long pin0 = (ap << (shiftB + 2)) + (b << 2);
+        for (; c < 4; row += nthr / kCols) {
+            float2 v = make_float2(0.f, 0.f);
+            if (col < a.Vc)
+                v = a.reads_f ? head_value(a, b * 4 + c, s, col)
+                              : a.in[((pin0 + c) * a.r_in + s) * a.Vc + col];
+            xs[row * kCols + n] = v;
+            s += nthr / kCols;
+            while (s >= a.r_in) {
+                s -= a.r_in;
+                ++c;
             }
         }
-        xs[e] = v;
     }
     for (int e = threadIdx.x; e < 16 * a.r_in; e += nthr)
         ws[e] = a.tw[u * 16 * a.r_in + e];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = wave >> 2, h = wave & 3;
+    constexpr int WPC = kSepWaves / 4;            // waves per output child
+    const int i = wave / WPC, h = wave % WPC;
     const int g = lane >> 4, n = lane & 15;
     const int nks = (2 * A1 + 3) >> 2;
     float am[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
     __syncthreads();
-    // stage 1: combos (c1, s1), a wave every fourth
-    for (int cb = h; cb < 2 * A1; cb += 4) {
+    // this lane's K entries (child, point) per K step, k = 4 ks + g: their
+    // offsets in X and W (-1 past 2a)
+    int kx[4], kw[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + g;
+        const int c2 = k / A1, s2 = k - c2 * A1;
+        const bool ok = k < 2 * A1;
+        kx[ks] = ok ? (c2 * a.r_in + s2) * kCols + n : -1;
+        kw[ks] = ok ? (i * 4 + c2) * a.r_in + s2 : -1;
+    }
+    // stage 1: combos (c1, s1), split over the child's waves
+    for (int cb = h; cb < 2 * A1; cb += WPC) {
         const int c1 = cb / A1, s1 = cb - c1 * A1;
+        const int dx = (2 * c1 * a.r_in + s1 * A1) * kCols;
+        const int dw = 2 * c1 * a.r_in + s1 * A1;
         floatx4 zr = zero4(), zi = zero4();
         for (int ks = 0; ks < nks; ++ks) {
-            const int k = 4 * ks + g;
             float2 z = make_float2(0.f, 0.f);
-            if (k < 2 * A1) {
-                const int c2 = k / A1, s2 = k - c2 * A1;
-                const int c = c1 * 2 + c2, s = s1 * A1 + s2;
-                z = cmul(ws[(i * 4 + c) * a.r_in + s],
-                         xs[((size_t)c * a.r_in + s) * kCols + n]);
-            }
+            if (kx[ks] >= 0) z = cmul(ws[kw[ks] + dw], xs[kx[ks] + dx]);
             zr = mma(am[ks], z.x, zr);
             zi = mma(am[ks], z.y, zi);
         }
@@ -111,15 +123,18 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
     const int col = col0 + n;
     const long long pout = ((ap * 4 + i) << shiftB) + b;
     float2* o = a.out + pout * a.r_out * a.Vc + col;
-    for (int t2 = h; t2 < B1; t2 += 4) {
+    // stage-2 K entries (c1, s1) of this lane: offsets in Z (-1 past 2a)
+    int kz[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + g;
+        kz[ks] = k < 2 * A1 ? ((i * 2 * A1 + k) * B1) * kCols + n : -1;
+    }
+    for (int t2 = h; t2 < B1; t2 += WPC) {
         floatx4 yr = zero4(), yi = zero4();
         for (int ks = 0; ks < nks; ++ks) {
-            const int k = 4 * ks + g;
             float2 z = make_float2(0.f, 0.f);
-            if (k < 2 * A1) {
-                const int c1 = k / A1, s1 = k - c1 * A1;
-                z = zs[((((size_t)i * 2 + c1) * A1 + s1) * B1 + t2) * kCols + n];
-            }
+            if (kz[ks] >= 0) z = zs[kz[ks] + t2 * kCols];
             yr = mma(am[ks], z.x, yr);
             yi = mma(am[ks], z.y, yi);
         }
@@ -148,17 +163,21 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     const int shiftB = 2 * (a.L - a.level);
     const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nthr = kSepWaves * 64;
-    const int nin = 4 * a.r_in * kCols;
-    for (int e = threadIdx.x; e < nin; e += nthr) {
-        const int n = e % kCols, cs = e / kCols;
-        const int c = cs / a.r_in, s = cs - c * a.r_in;
-        const int col = col0 + n;
-        float2 v = make_float2(0.f, 0.f);
-        if (col < a.Vc) {
-            const long long pin = (ap << (shiftB + 2)) + (b << 2) + c;
-            v = a.in[(pin * a.r_in + s) * a.Vc + col];
+    {
+        const int n = threadIdx.x & (kCols - 1), col = col0 + n;
+        int row = threadIdx.x >> 4;
+        int c = row / a.r_in, s = row - c * a.r_in;
+        const long long pin0 = (ap << (shiftB + 2)) + (b << 2);
+        for (; c < 4; row += nthr / kCols) {
+            float2 v = make_float2(0.f, 0.f);
+            if (col < a.Vc) v = a.in[((pin0 + c) * a.r_in + s) * a.Vc + col];
+            xs[row * kCols + n] = v;
+            s += nthr / kCols;
+            while (s >= a.r_in) {
+                s -= a.r_in;
+                ++c;
+            }
         }
-        xs[e] = v;
     }
     for (int e = threadIdx.x; e < 16 * a.r_out; e += nthr)
         ts[e] = a.tw[u * 16 * a.r_out + e];
@@ -169,6 +188,19 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
     __syncthreads();
+    // this lane's D rows 4 g + j = (child, point) of both stages: stage 1
+    // writes Z at (i2, t2) = that split (offset rz, -1 past 2b), stage 2
+    // reads the same split as (i1, t1)
+    int rz[4], ri1[4], rt1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int row = 4 * g + j;
+        const int ch = row / B1, pt = row - ch * B1;
+        const bool ok = row < 2 * B1;
+        rz[j] = ok ? (ch * A1 * B1 + pt) * kCols + n : -1;
+        ri1[j] = ok ? ch : -1;
+        rt1[j] = ok ? pt : 0;
+    }
     // stage 1: combos (c, s1); rows (i2, t2)
     for (int cb = wave; cb < 4 * A1; cb += kSepWaves) {
         const int c = cb / A1, s1 = cb - c * A1;
@@ -182,38 +214,38 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
             zi = mma(am[ks], x.y, zi);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int row = 4 * g + j;
-            if (row < 2 * B1) {
-                const int i2 = row / B1, t2 = row - i2 * B1;
-                zs[((((size_t)c * 2 + i2) * A1 + s1) * B1 + t2) * kCols + n] =
+        for (int j = 0; j < 4; ++j)
+            if (rz[j] >= 0)
+                zs[rz[j] + (c * 2 * A1 + s1) * B1 * kCols] =
                     make_float2(zr[j], zi[j]);
-            }
-        }
     }
     __syncthreads();
     // stage 2 and the twiddles: combos (i2, t2); rows (i1, t1); sum over c
     const int col = col0 + n;
     for (int cb = wave; cb < 2 * B1; cb += kSepWaves) {
         const int i2 = cb / B1, t2 = cb - i2 * B1;
+        // this lane's output rows (i1, t1): child ii, coefficient t
+        int ii[4], tt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ii[j] = ri1[j] < 0 ? -1 : ri1[j] * 2 + i2;
+            tt[j] = rt1[j] * B1 + t2;
+        }
         floatx4 dr = zero4(), di = zero4();
         for (int c = 0; c < 4; ++c) {
             floatx4 yr = zero4(), yi = zero4();
+            const int zb = (((c * 2 + i2) * A1) * B1 + t2) * kCols + n;
             for (int ks = 0; ks < nks; ++ks) {
                 const int s1 = 4 * ks + g;
-                const float2 z = s1 < A1
-                    ? zs[((((size_t)c * 2 + i2) * A1 + s1) * B1 + t2) * kCols + n]
-                    : make_float2(0.f, 0.f);
+                const float2 z = s1 < A1 ? zs[zb + s1 * B1 * kCols]
+                                         : make_float2(0.f, 0.f);
                 yr = mma(am[ks], z.x, yr);
                 yi = mma(am[ks], z.y, yi);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int row = 4 * g + j;
-                if (row < 2 * B1) {
-                    const int i1 = row / B1, t1 = row - i1 * B1;
-                    const int ii = i1 * 2 + i2, t = t1 * B1 + t2;
-                    const float2 T = ts[(ii * 4 + c) * a.r_out + t];
+                if (ii[j] >= 0) {
+                    const float2 T = ts[(ii[j] * 4 + c) * a.r_out + tt[j]];
                     dr[j] += T.x * yr[j] - T.y * yi[j];
                     di[j] += T.x * yi[j] + T.y * yr[j];
                 }
@@ -222,12 +254,9 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
         if (col < a.Vc) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int row = 4 * g + j;
-                if (row < 2 * B1) {
-                    const int i1 = row / B1, t1 = row - i1 * B1;
-                    const int ii = i1 * 2 + i2, t = t1 * B1 + t2;
-                    const long long pout = ((ap * 4 + ii) << shiftB) + b;
-                    a.out[(pout * a.r_out + t) * a.Vc + col] =
+                if (ii[j] >= 0) {
+                    const long long pout = ((ap * 4 + ii[j]) << shiftB) + b;
+                    a.out[(pout * a.r_out + tt[j]) * a.Vc + col] =
                         make_float2(dr[j], di[j]);
                 }
             }
