@@ -104,11 +104,31 @@ def test_no_device_is_an_error_not_a_crash():
     assert not h.value
 
 
-def test_split_precision_2d_unsupported_before_device_use():
-    rc, h = _plan_rc(dim=2, n=16, kind=2, params=(2, 1, 16, 2, 1, 16), q=7,
-                     prec=1)
+_RADON16 = dict(dim=2, n=16, kind=2, params=(2, 1, 16, 2, 1, 16), q=7)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_split_precision_2d_planned_up_to_device_use(prec):
+    """2D split plans pass every host check: without a GPU they fail only
+    where the device is first needed, like an FP32 plan."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h = _plan_rc(prec=prec, **_RADON16)
+    assert rc in (_lib.BF_EHIP, _lib.BF_ENOMEM)
+    assert not h.value
+
+
+@pytest.mark.parametrize("env", ["BF_SWITCH_OTF", "BF_MFMA"])
+def test_split_precision_2d_forms_refused_before_device_use(env, monkeypatch):
+    """The split forms of a 2D plan are the per-step MFMA kernels with
+    stored switch blocks: on-the-fly switch evaluation or the scalar
+    per-step kernels are refused at plan time."""
+    monkeypatch.setenv(env, "1" if env == "BF_SWITCH_OTF" else "0")
+    rc, h = _plan_rc(prec=1, **_RADON16)
     assert rc == _lib.BF_EUNSUPPORTED
     assert not h.value
+    assert b"split" in _lib.load().bf_last_error().lower()
 
 
 @pytest.mark.parametrize("op", [-1, 4, 7])
