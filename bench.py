@@ -429,9 +429,9 @@ def composition_bench(args):
 
 
 def serve_bench(args):
-    """Serving: 13 resident plans (1D FIO N = 2^12..2^20 with r = 1, 2 or
-    4; 2D Radon n = 64..256), a seeded request mix with 1..32 vectors per
-    request.  First every request arrives at once (saturation throughput),
+    """Serving: 39 resident plans (1D FIO at every N = 2^12..2^20, odd and
+    even depths, and 2D Radon n = 64..512, each with amplitude rank r = 1,
+    2 or 4), a seeded request mix with 1..32 vectors per request.  First every request arrives at once (saturation throughput),
     then Poisson arrivals at 0.5x, 0.8x and 1.2x that request rate; each
     level reports p50/p99 latency from arrival to completion on the GPU."""
     import numpy as np

@@ -74,9 +74,10 @@ def alg1(entries, m, n, r, row_samples, col_samples, extra_rows,
          extra_cols):
     """Algorithm 1 (randomized sampling for a rank-r approximate SVD) of an
     m x n matrix known through entries(rows, cols).  row_samples[t],
-    col_samples[t]: the random rows and columns of round t (lines 4-6
-    repeated once per round); extra_rows, extra_cols: the extra samples of
-    the core matrix.  Returns U0 [m][k], s [k], V0 [n][k] with K ~ U0
+    col_samples[t]: the random rows and columns of round t (each round
+    alternates once between finding important columns from sampled rows
+    and important rows from sampled columns); extra_rows, extra_cols: the
+    extra samples of the core matrix.  Returns U0 [m][k], s [k], V0 [n][k] with K ~ U0
     diag(s) V0^H, k <= r."""
     pi_col = np.zeros(0, np.int64)
     pi_row = np.zeros(0, np.int64)
