@@ -300,6 +300,8 @@ static int configure_plan(const bf_grid* grid, const bf_phase* phase,
     p.tile_cols = tenv ? std::max(0, std::atoi(tenv)) : 0;
     const char* oenv = std::getenv("BF_SWITCH_OTF");
     p.switch_otf = oenv && std::atoi(oenv) != 0 && !p.fused && p.mfma;
+    const char* senv = std::getenv("BF_SEP_SWITCH");
+    p.sep_switch = !senv || std::atoi(senv) != 0;
     if (phase->kind == BF_PHASE_LOWRANK) p.phase.rank = phase->rank;
     std::string err = bfi::build_schedule(p);
     if (!err.empty()) return fail(BF_EUNSUPPORTED, "bf_plan: " + err);

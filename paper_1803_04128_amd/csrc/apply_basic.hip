@@ -200,6 +200,9 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
 std::string launch_step_split(const Plan& p, const Step& s,
                               const StepArgs& a, hipStream_t st);
 
+std::string launch_sep_switch(const Plan& p, const Step& xi, const Step& sw,
+                              StepArgs a, hipStream_t st);
+
 std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
                       float2* buf0, float2* buf1, hipStream_t st) {
     const int Vc = nv * p.r_amp;
@@ -208,19 +211,30 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
     int which = 0;
     const double N = (double)p.N, c8 = 8.0 * Vc;
     const double head_bytes = N * nv * 8.0 + (p.has_amp ? N * p.r_amp * 8.0 : 0);
-    for (auto& s : p.steps) {
+    for (size_t k = 0; k < p.steps.size(); ++k) {
+        const Step& s = p.steps[k];
         StepArgs a = make_step_args(p, s, Vc, f, cur, bufs[which]);
         const bool otf = p.mfma && p.switch_otf && s.kind == STEP_SWITCH;
-        const double bytes = (s.reads_f ? head_bytes : 0.0) + s.tw_elems * 8.0 +
-                             (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
-        const double sbytes = (s.reads_f ? 0.0 : N * s.r_in * c8) +
-                              N * s.r_out * c8;
-        const double flops = step_alg_flops(p, s, Vc);
+        double bytes = (s.reads_f ? head_bytes : 0.0) + s.tw_elems * 8.0 +
+                       (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
+        double sbytes = (s.reads_f ? 0.0 : N * s.r_in * c8) +
+                        N * s.r_out * c8;
+        double flops = step_alg_flops(p, s, Vc);
         const char* name = s.kind == STEP_XI ? "xi_step_basic"
                            : s.kind == STEP_X ? "x_step_basic"
                                               : "switch_basic";
         ProfScope ps(p, st);
-        if (p.mfma && p.precision != BF_FP32) {
+        if (k + 1 < p.steps.size() && sep_switch_ok(p, s, p.steps[k + 1])) {
+            // the last xi level and the switch in one launch
+            const Step& sw = p.steps[k + 1];
+            std::string err = launch_sep_switch(p, s, sw, a, st);
+            if (!err.empty()) return err;
+            name = "xi_sep_switch";
+            bytes += sw.S_elems * 8.0;
+            flops += step_alg_flops(p, sw, Vc);
+            sbytes += N * (double)(sw.r_out - s.r_out) * c8;
+            ++k;
+        } else if (p.mfma && p.precision != BF_FP32) {
             // split-precision contractions on MFMA
             std::string err = launch_step_split(p, s, a, st);
             if (!err.empty()) return err;

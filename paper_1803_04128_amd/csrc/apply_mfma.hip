@@ -146,14 +146,24 @@ struct TwStage {
 };
 
 // Register-staged twiddle entries per thread: what the largest tile
-// (Gk * VT = 512, r <= 16) needs, at most 4.
+// (Gk * VT = 512, r <= 16) needs, at most 2 (entries past them are copied
+// at the store; holding 4 spilled the width-4 passes to scratch).
 template <int VT>
 constexpr int tw_regs() {
-    return (kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads > 4
-               ? 4
+    return (kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads > 2
+               ? 2
                : ((kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads < 1
                       ? 1
                       : (kMfmaTileCap * 8 / VT) * 32 / kMfmaThreads);
+}
+
+// Register-staged entries per thread of the next sub-iteration's state tile
+// in the x pass: the width-8 tile (5 per thread at Gk = 64, r = 10) is
+// read whole; narrower tiles, whose passes hold more twiddle and tail
+// registers, read 3 and copy the rest at the store (more would spill).
+template <int VT>
+constexpr int pre_regs() {
+    return VT >= 8 ? 5 : 3;
 }
 
 // A operand of an FP32 level, one coalesced load per k step (lv.amat):
@@ -962,7 +972,7 @@ x_pass_mfma(PassArgs a) {
     // the current one's last level and written at the next one's start
     // (not in FP16x3, whose x levels leave no registers for them)
     constexpr bool kPre = PREC != BF_FP16X3;
-    TileLoad<5> pre;
+    TileLoad<pre_regs<VT>()> pre;
     TwStage<tw_regs<VT>()> pre_tw;
     for (int si = 0; si < a.n_sub; ++si) {
         const int sub = part * a.n_sub + si;

@@ -42,9 +42,23 @@ __device__ __forceinline__ floatx4 zero4() {
 
 }  // namespace
 
+// The switch of Algorithm 4.1 (step 4) fused behind the last xi level: the
+// level's four output pairs (A_i, B) stay in LDS and each is multiplied by
+// its block S_{A_i B} (read from HBM in the A layout of the switch step), so
+// the level's output and the switch's input never go through HBM.
+struct SwFuse {
+    const float2* S;     // switch blocks [pair][r_out][r_in], r_in = xi r_out
+    int r_out;           // switch output coefficients per pair
+    int ys_off;          // LDS offset (float2) of the level's output Y
+};
+
 // xi step, block = (unit, 16-column tile), kSepWaves waves: kSepWaves / 4
-// per output child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16].
-__global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
+// per output child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16];
+// with SW, Y [4][r_out][16] at sw.ys_off (over X and W once they are read,
+// or past Z).
+template <bool SW>
+__global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
+                                                              SwFuse sw) {
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
     float2* xs = lds_step;
@@ -56,6 +70,26 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
     const int shiftB = 2 * (a.L - a.level);
     const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nthr = kSepWaves * 64;
+    // switch: jobs (output child, 16-row tile of S), one wave each; the
+    // first job's block entries are read now, ahead of the level's work
+    const int MT = SW ? (sw.r_out + 15) >> 4 : 0;
+    const int KS = (a.r_out + 3) >> 2;
+    float2 sv0[16];
+    if constexpr (SW) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int job = wave;
+        const int ii = job / MT, m = job - ii * MT;
+        const int row = 16 * m + (lane & 15), g = lane >> 4;
+        const bool ok = job < 4 * MT && row < sw.r_out;
+        const long long p = ((ap * 4 + ii) << shiftB) + b;
+        const float2* Sp = sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int s = 4 * ks + g;
+            sv0[ks] = (ok && ks < KS && s < a.r_out) ? Sp[s]
+                                                     : make_float2(0.f, 0.f);
+        }
+    }
     {
         // (child, point) rows advance by nthr / 16 per round; each thread
         // keeps its column and steps its row without a division
@@ -104,11 +138,14 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
         const int dx = (2 * c1 * a.r_in + s1 * A1) * kCols;
         const int dw = 2 * c1 * a.r_in + s1 * A1;
         floatx4 zr = zero4(), zi = zero4();
-        for (int ks = 0; ks < nks; ++ks) {
-            float2 z = make_float2(0.f, 0.f);
-            if (kx[ks] >= 0) z = cmul(ws[kw[ks] + dw], xs[kx[ks] + dx]);
-            zr = mma(am[ks], z.x, zr);
-            zi = mma(am[ks], z.y, zi);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            if (ks < nks) {                             // uniform
+                float2 z = make_float2(0.f, 0.f);
+                if (kx[ks] >= 0) z = cmul(ws[kw[ks] + dw], xs[kx[ks] + dx]);
+                zr = mma(am[ks], z.x, zr);
+                zi = mma(am[ks], z.y, zi);
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -130,20 +167,81 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a) {
         const int k = 4 * ks + g;
         kz[ks] = k < 2 * A1 ? ((i * 2 * A1 + k) * B1) * kCols + n : -1;
     }
+    float2* ys = lds_step + sw.ys_off;
     for (int t2 = h; t2 < B1; t2 += WPC) {
         floatx4 yr = zero4(), yi = zero4();
-        for (int ks = 0; ks < nks; ++ks) {
-            float2 z = make_float2(0.f, 0.f);
-            if (kz[ks] >= 0) z = zs[kz[ks] + t2 * kCols];
-            yr = mma(am[ks], z.x, yr);
-            yi = mma(am[ks], z.y, yi);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            if (ks < nks) {                             // uniform
+                float2 z = make_float2(0.f, 0.f);
+                if (kz[ks] >= 0) z = zs[kz[ks] + t2 * kCols];
+                yr = mma(am[ks], z.x, yr);
+                yi = mma(am[ks], z.y, yi);
+            }
         }
-        if (col < a.Vc) {
+        if constexpr (SW) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t1 = 4 * g + j;
+                if (t1 < B1)
+                    ys[((size_t)i * a.r_out + t1 * B1 + t2) * kCols + n] =
+                        make_float2(yr[j], yi[j]);
+            }
+        } else if (col < a.Vc) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int t1 = 4 * g + j;
                 if (t1 < B1)
                     o[(size_t)(t1 * B1 + t2) * a.Vc] = make_float2(yr[j], yi[j]);
+            }
+        }
+    }
+    if constexpr (SW) {
+        // nu^{A_i B} = S_{A_i B} mu^{A_i B}: rows t of S (16 per job), K = s,
+        // complex products as four real chains (Re S Re Y, Im S Im Y,
+        // Re S Im Y, Im S Re Y)
+        __syncthreads();
+        for (int job = wave; job < 4 * MT; job += kSepWaves) {
+            const int ii = job / MT, m = job - ii * MT;
+            const long long p = ((ap * 4 + ii) << shiftB) + b;
+            float2 sv[16];
+            if (job == wave) {
+#pragma unroll
+                for (int ks = 0; ks < 16; ++ks) sv[ks] = sv0[ks];
+            } else {
+                const int row = 16 * m + n;
+                const float2* Sp = sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
+#pragma unroll
+                for (int ks = 0; ks < 16; ++ks) {
+                    const int s = 4 * ks + g;
+                    sv[ks] = (row < sw.r_out && ks < KS && s < a.r_out)
+                                 ? Sp[s]
+                                 : make_float2(0.f, 0.f);
+                }
+            }
+            floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                if (ks < KS) {                          // uniform
+                    const int s = 4 * ks + g;
+                    const float2 yv = s < a.r_out
+                                          ? ys[((size_t)ii * a.r_out + s) * kCols + n]
+                                          : make_float2(0.f, 0.f);
+                    p1 = mma(sv[ks].x, yv.x, p1);
+                    p2 = mma(sv[ks].y, yv.y, p2);
+                    p3 = mma(sv[ks].x, yv.y, p3);
+                    p4 = mma(sv[ks].y, yv.x, p4);
+                }
+            }
+            if (col < a.Vc) {
+                float2* os = a.out + p * sw.r_out * a.Vc + col;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t = 16 * m + 4 * g + j;
+                    if (t < sw.r_out)
+                        os[(size_t)t * a.Vc] = make_float2(p1[j] - p2[j],
+                                                           p3[j] + p4[j]);
+                }
             }
         }
     }
@@ -205,13 +303,16 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     for (int cb = wave; cb < 4 * A1; cb += kSepWaves) {
         const int c = cb / A1, s1 = cb - c * A1;
         floatx4 zr = zero4(), zi = zero4();
-        for (int ks = 0; ks < nks; ++ks) {
-            const int s2 = 4 * ks + g;
-            const float2 x = s2 < A1
-                ? xs[((size_t)c * a.r_in + s1 * A1 + s2) * kCols + n]
-                : make_float2(0.f, 0.f);
-            zr = mma(am[ks], x.x, zr);
-            zi = mma(am[ks], x.y, zi);
+        const int xb = (c * a.r_in + s1 * A1 + g) * kCols + n;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            if (ks < nks) {                             // uniform
+                const int s2 = 4 * ks + g;
+                const float2 x = s2 < A1 ? xs[xb + 4 * ks * kCols]
+                                         : make_float2(0.f, 0.f);
+                zr = mma(am[ks], x.x, zr);
+                zi = mma(am[ks], x.y, zi);
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -235,12 +336,15 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
         for (int c = 0; c < 4; ++c) {
             floatx4 yr = zero4(), yi = zero4();
             const int zb = (((c * 2 + i2) * A1) * B1 + t2) * kCols + n;
-            for (int ks = 0; ks < nks; ++ks) {
-                const int s1 = 4 * ks + g;
-                const float2 z = s1 < A1 ? zs[zb + s1 * B1 * kCols]
-                                         : make_float2(0.f, 0.f);
-                yr = mma(am[ks], z.x, yr);
-                yi = mma(am[ks], z.y, yi);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                if (ks < nks) {                         // uniform
+                    const int s1 = 4 * ks + g;
+                    const float2 z = s1 < A1 ? zs[zb + s1 * B1 * kCols]
+                                             : make_float2(0.f, 0.f);
+                    yr = mma(am[ks], z.x, yr);
+                    yi = mma(am[ks], z.y, yi);
+                }
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -271,6 +375,29 @@ size_t step_sep_lds(const Step& s) {
             (size_t)8 * a1 * b1 * kCols) * sizeof(float2);
 }
 
+// LDS of the xi level with the switch fused: Y over X and W where it fits
+// there (both are read before stage 2 starts), else past Z.
+static void sep_switch_lds(const Step& s, size_t* bytes, int* ys_off) {
+    const size_t xw = (size_t)4 * s.r_in * kCols + (size_t)16 * s.r_in;
+    const size_t y = (size_t)4 * s.r_out * kCols;
+    const size_t base = step_sep_lds(s) / sizeof(float2);
+    *ys_off = y <= xw ? 0 : (int)base;
+    *bytes = (y <= xw ? base : base + y) * sizeof(float2);
+}
+
+bool sep_switch_ok(const Plan& p, const Step& xi, const Step& sw) {
+    if (!(p.sep_switch && p.mfma && p.precision == BF_FP32 && !p.switch_otf))
+        return false;
+    if (xi.kind != STEP_XI || sw.kind != STEP_SWITCH || !step_sep_ok(p, xi))
+        return false;
+    if (!sw.S || sw.r_in != xi.r_out || sw.level != xi.level || sw.r_out > 64)
+        return false;
+    size_t bytes;
+    int off;
+    sep_switch_lds(xi, &bytes, &off);
+    return bytes <= 160 * 1024;
+}
+
 // The separable form applies to 2D steps whose stacked children fit one
 // 16-row / 16-deep MFMA operand (points per dimension <= 8).
 bool step_sep_ok(const Plan& p, const Step& s) {
@@ -279,7 +406,9 @@ bool step_sep_ok(const Plan& p, const Step& s) {
 }
 
 void init_step_sep_attrs() {
-    const void* fns[] = {(const void*)xi_step_sep, (const void*)x_step_sep};
+    const void* fns[] = {(const void*)xi_step_sep<false>,
+                         (const void*)xi_step_sep<true>,
+                         (const void*)x_step_sep};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
@@ -297,11 +426,32 @@ std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
     a.b1 = s.ax_out.r1;
     a.amat_sep = s.amat_sep;
     if (s.kind == STEP_XI)
-        hipLaunchKernelGGL(xi_step_sep, dim3((unsigned)nb),
-                           dim3(kSepWaves * 64), lds, st, a);
+        hipLaunchKernelGGL(xi_step_sep<false>, dim3((unsigned)nb),
+                           dim3(kSepWaves * 64), lds, st, a, SwFuse{});
     else
         hipLaunchKernelGGL(x_step_sep, dim3((unsigned)nb),
                            dim3(kSepWaves * 64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
+    return "";
+}
+
+// The last xi level and the switch in one launch: out receives the
+// switch's output (the pairs of level h after S).
+std::string launch_sep_switch(const Plan& p, const Step& xi, const Step& sw,
+                              StepArgs a, hipStream_t st) {
+    if (!sep_switch_ok(p, xi, sw)) return "fused switch does not apply";
+    const long long nct = (a.Vc + kCols - 1) / kCols;
+    const long long nb = xi.units * nct;
+    if (nb > 0x7fffffffLL) return "step grid too large";
+    size_t lds;
+    SwFuse f{sw.S, sw.r_out, 0};
+    sep_switch_lds(xi, &lds, &f.ys_off);
+    a.a1 = xi.ax_in.r1;
+    a.b1 = xi.ax_out.r1;
+    a.amat_sep = xi.amat_sep;
+    hipLaunchKernelGGL(xi_step_sep<true>, dim3((unsigned)nb),
+                       dim3(kSepWaves * 64), lds, st, a, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
     return "";

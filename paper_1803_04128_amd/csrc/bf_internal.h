@@ -167,6 +167,9 @@ struct Plan {
     // per-step MFMA form: generate the switch blocks during the apply
     // instead of reading the stored S
     bool switch_otf = false;
+    // 2D per-step MFMA form: the switch fused behind the last xi level
+    // (BF_SEP_SWITCH=0 at plan time keeps them separate launches)
+    bool sep_switch = true;
     float2* a_dev = nullptr;  // [r][N] complex64, nullptr when alpha = 1
     float2* b_dev = nullptr;
     void* ws = nullptr;
@@ -234,6 +237,8 @@ constexpr size_t kStaticScratchBytes = BF_STATIC_SCRATCH_BYTES;
 std::string static_scratch(int device, void** out);
 // apply_step_sep.hip: 2D per-step levels contracted per dimension
 bool step_sep_ok(const Plan& p, const Step& s);
+// the last xi level with the switch fused behind it (FP32, stored S)
+bool sep_switch_ok(const Plan& p, const Step& xi, const Step& sw);
 void init_step_sep_attrs();
 // apply_step_split.hip: split-precision per-step kernels
 void init_step_split_attrs();
