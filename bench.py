@@ -39,7 +39,7 @@ WORKLOADS = {
 
 # host-only sources that neither generate nor launch kernels: the C ABI
 # layer and the phase recovery
-HOST_ONLY = ("api.cpp", "recovery.cpp")
+HOST_ONLY = ("api.cpp", "recovery.cpp", "lifting.cpp")
 
 
 def kernel_source_hash():
@@ -154,10 +154,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fio1d_n1048576_sweep",
-                    choices=sorted(WORKLOADS) + ["serving", "composition"],
+                    choices=sorted(WORKLOADS) + ["serving", "composition",
+                                                 "lifted"],
                     help="'serving': the continuous-batching server on the "
                          "mixed request stream; 'composition': the chained "
-                         "applies L(L f) (each its own JSON line)")
+                         "applies L(L f) (each its own JSON line); "
+                         "'lifted': NUFFT by dimension lifting against the "
+                         "butterfly on one kernel")
     ap.add_argument("--requests", type=int, default=2000,
                     help="serving: requests per load level")
     ap.add_argument("--graph", action="store_true",
@@ -174,8 +177,9 @@ def main():
     ap.add_argument("--lowrank-phase", type=int, default=0, metavar="RANK",
                     help="replace the workload's phase by a seeded phase "
                          "given as real low-rank factors of this rank")
-    ap.add_argument("--comp-n", type=int, default=1 << 18,
-                    help="composition: grid size N (a power of two)")
+    ap.add_argument("--comp-n", type=int, default=None,
+                    help="composition and lifted: grid size N (a power of "
+                         "two; defaults 2^18 and 2^16)")
     ap.add_argument("--precision", default=None,
                     choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--nvec", type=int, default=None,
@@ -196,7 +200,12 @@ def main():
         serve_bench(args)
         return
     if args.workload == "composition":
+        args.comp_n = args.comp_n or 1 << 18
         composition_bench(args)
+        return
+    if args.workload == "lifted":
+        args.comp_n = args.comp_n or 1 << 16
+        lifted_bench(args)
         return
 
     import numpy as np
@@ -361,6 +370,118 @@ def main():
     if graph is not None:
         graph.close()
     plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def lifted_bench(args):
+    """Section 3's choice between NUFFT and butterfly on one kernel: the
+    wave-equation-like phase Phi = x xi + tau c(x)|xi| (tau = 8/N, c(x) =
+    (2 + sin 2 pi x)/8) given as real rank-2 factors, alpha = 1, N = 2^16
+    (--comp-n) and 16 vectors by default.  Algorithm 6 runs on the host
+    (bf_lift_decide: r = 1, r_eps = 24, q = 3, eps = 1e-9, seeded draws);
+    the lifted plan (eq. (eqn:tg3), bf_plan_lifted) and the butterfly plan
+    of the same low-rank phase (q = 10) are timed on the same vectors.
+    value: the lifted apply's N·nvec/s, the butterfly's beside it; the
+    cpu_baseline leg times the dense FP64 rows (oracle) on 64 seeded rows and
+    reports both GPU results' errors there."""
+    import numpy as np
+    import torch
+
+    import paper_1803_04128_amd as bfm
+    from synthetic import gaussian_vectors, sample_rows
+
+    N = args.comp_n
+    nvec = args.nvec or 16
+    r_eps, q_os, eps, q_bf = 24, 3, 1e-9, 10
+    x = np.arange(N) / N
+    xi = (np.arange(N) - N // 2).astype(float)
+    c = (2 + np.sin(2 * np.pi * x)) / 8
+    U1 = np.stack([x, (8.0 / N) * c], 1)
+    V1 = np.stack([xi, np.abs(xi)], 1)
+    ones = np.ones((N, 1))
+    rng = np.random.default_rng(12)
+    omega = rng.standard_normal((N, 5))
+    test = rng.choice(N, r_eps * q_os, replace=False)
+    rows_s = np.stack([rng.choice(N, r_eps * q_os, replace=False)
+                       for _ in range(2)])
+    cols_s = np.stack([rng.choice(N, r_eps * q_os, replace=False)
+                       for _ in range(2)])
+    extra = (rng.choice(N, 4, replace=False), rng.choice(N, 4, replace=False))
+    t0 = time.perf_counter()
+    y, n_rank, P, Q, a, b = bfm.lift_decide(U1, V1, ones, ones, 1, r_eps, eps,
+                                            omega, test,
+                                            (rows_s, cols_s) + extra)
+    decide_s = time.perf_counter() - t0
+    if y != 1:
+        print(json.dumps({"error": "Algorithm 6 refused the kernel",
+                          "n_rank": int(n_rank)}), flush=True)
+        sys.exit(1)
+    f64 = gaussian_vectors(N, nvec, 3)
+    f = torch.from_numpy(f64.astype(np.complex64)).to("cuda")
+    t0 = time.perf_counter()
+    lifted = bfm.plan_lifted(P, Q, a, b, max_nvec=nvec)
+    torch.cuda.synchronize()
+    lifted_plan_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bf = bfm.Plan(1, N, "lowrank", (U1, V1), q=q_bf, max_nvec=nvec)
+    torch.cuda.synchronize()
+    bf_plan_s = time.perf_counter() - t0
+
+    def timed(pl):
+        g = torch.empty_like(f)
+        for _ in range(args.warmup):
+            pl.apply(f, out=g)
+        torch.cuda.synchronize()
+        pl.profile(True)
+        pl.profile_read()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            pl.apply(f, out=g)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        pl.profile(False)
+        kern = {k: {"launches": v["launches"],
+                    "ms_per_launch": v["total_ms"] / v["launches"]}
+                for k, v in pl.profile_read().items()}
+        return el, kern, g.cpu().numpy().astype(np.complex128)
+
+    el_l, kern_l, g_l = timed(lifted)
+    el_b, kern_b, g_b = timed(bf)
+    lifted.close()
+    bf.close()
+    out = {"metric": "Kf applies: N·nvec/s",
+           "value": N * nvec * args.steps / el_l, "unit": "N·nvec/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el_l * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "lifted1d_wave", "N": N, "nvec": nvec,
+                      "r": 1, "r_eps": r_eps, "q_bf": q_bf},
+           "decision": {"y": int(y), "sampled_rank": int(n_rank),
+                        "terms": int(a.shape[0]), "host_s": decide_s},
+           "plan_s": {"lifted": lifted_plan_s, "butterfly": bf_plan_s},
+           "butterfly": {"value": N * nvec * args.steps / el_b,
+                         "ms_per_step": el_b * 1e3 / args.steps,
+                         "kernels": kern_b},
+           "kernels": kern_l}
+    if not args.no_cpu_baseline:
+        from oracle.dense import dense_rows
+        rows = sample_rows(N, 64, 5)
+        nproc, model = host_cpu()
+        t0 = time.perf_counter()
+        ref = dense_rows(1, N, "lowrank", (U1, V1), "one", f64, rows)
+        dt = time.perf_counter() - t0
+
+        def err(g):
+            return float(np.max(np.linalg.norm(g[:, rows] - ref, axis=1) /
+                                np.linalg.norm(ref, axis=1)))
+        out["cpu_baseline"] = {
+            "value": rows.size * nvec / dt, "unit": "N·nvec/s", "cores": 1,
+            "nproc": nproc, "cpu_model": model, "kind": "oracle",
+            "sample": f"dense FP64 rows of K (NumPy), 64 seeded rows x "
+                      f"{nvec} vectors; {dt:.1f} s"}
+        out["rel_err_vs_dense"] = {"lifted": err(g_l), "butterfly": err(g_b)}
     print(json.dumps(out), flush=True)
 
 

@@ -697,13 +697,18 @@ std::string run_fused(Plan& p, int nv, const float2* f, float2* g,
         // instead (from registers in FP32, else gathered again) when that
         // lets two workgroups of 512 threads share a CU; they then overlap
         // each other's factor reads and barriers
+        // (with one twiddle buffer where two do not fit twice)
         a.head_inplace = 0;
+        a.tw_single = 0;
         if (use_mfma && is_xi && a.has_head && a.head_r <= a.rmax) {
             const size_t keep = mfma_pass_lds(a, true);
             a.head_inplace = 1;
             const size_t in = mfma_pass_lds(a, true);
-            a.head_inplace = (2 * keep > 160 * 1024 && 2 * in <= 160 * 1024 &&
-                              nblocks >= 512) ? 1 : 0;
+            a.tw_single = 1;
+            const size_t in1 = mfma_pass_lds(a, true);
+            const bool want = 2 * keep > 160 * 1024 && nblocks >= 512;
+            a.head_inplace = want && 2 * in1 <= 160 * 1024 ? 1 : 0;
+            a.tw_single = a.head_inplace && 2 * in > 160 * 1024 ? 1 : 0;
         }
         if (use_mfma) {
             lds = mfma_pass_lds(a, is_xi);

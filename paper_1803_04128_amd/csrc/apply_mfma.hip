@@ -829,10 +829,14 @@ xi_pass_mfma(PassArgs a) {
     // pointers) so the compiler keeps them in the LDS address space and
     // emits ds_read / ds_write
     const int tsz = a.Gk * a.rmax * VT, wsz = 2 * a.Gk * a.rmax;
+    // two twiddle buffers (the next level's written while a level runs), or
+    // one (written after a barrier) where that lets two workgroups share a
+    // CU
+    const int nw = (HIN && a.tw_single) ? 1 : 2;
     float2* const T = lds;
     float2* const W0 = lds + tsz;
-    float2* const W1 = lds + tsz + wsz;
-    float2* const ftile = lds + tsz + 2 * wsz;
+    float2* const W1 = lds + tsz + (nw - 1) * wsz;
+    float2* const ftile = lds + tsz + nw * wsz;
     // the head in a tile of its own (kept for all sub-iterations), or
     // gathered into T at the tile's slot stride for each sub-iteration, so
     // that level 1 runs in place like the others
@@ -856,7 +860,7 @@ xi_pass_mfma(PassArgs a) {
             AX[e] = q < ((lv.r_in + 1) >> 1) ? lv.amat[q * 64 + ln] : 0.f;
         }
     }
-    zero_pass_lds(lds, tsz + 2 * wsz, pad);
+    zero_pass_lds(lds, tsz + nw * wsz, pad);
     const int part = (int)(spatial % a.sub_split);
     spatial /= a.sub_split;
     const long long bg = spatial % a.nbg;
@@ -899,6 +903,7 @@ xi_pass_mfma(PassArgs a) {
             mfma_xi_level<VT, PREC>(a, from_f ? ftile : T,
                                     from_f ? a.head_r : a.rmax, T,
                                     odd ? W0 : W1, j, aM, pad);
+            if (nw == 1) __syncthreads();   // the level's twiddles are read
             next.store(odd ? W1 : W0);
             __syncthreads();
             if constexpr (!kAX) {
@@ -1100,7 +1105,8 @@ std::string launch_sum_parts(const PassArgs& a, int nv, hipStream_t st) {
 
 size_t mfma_pass_lds(const PassArgs& a, bool is_xi) {
     const size_t tsz = (size_t)a.Gk * a.rmax * a.Vt, wsz = (size_t)2 * a.Gk * a.rmax;
-    size_t e = tsz + 2 * wsz + kMfmaLdsPad;
+    const int nw = (is_xi && a.head_inplace && a.tw_single) ? 1 : 2;
+    size_t e = tsz + nw * wsz + kMfmaLdsPad;
     if (is_xi && a.has_head && !a.head_inplace)
         e += (size_t)a.Gk * a.head_r * a.Vt;
     // A operands of the FP32 x passes and in-place head xi passes

@@ -77,6 +77,7 @@ size_t workspace_bytes(const Plan& p, int nvec) {
 
 std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
                          void* ws, size_t ws_bytes, hipStream_t st) {
+    if (nvec < 1) return "no vectors";
     if (p.nufft)
         return launch_nufft(p, nvec, (const float2*)fv, (float2*)gv, ws,
                             ws_bytes, st);
@@ -93,12 +94,15 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
         for (const auto& s : p.steps)
             if (s.S_elems) return "switch blocks are not stored";
     }
+    // as many chunks as that width needs, balanced: the first `extra` hold
+    // base + 1 vectors, the rest base (no small tail chunk)
+    const int nch = (nvec + chunk - 1) / chunk;
+    const int base = nvec / nch, extra = nvec % nch;
     if (p.fused) {
-        // every width this apply launches (the chunk and the tail) is
-        // planned before the first launch, so a failure leaves g untouched
-        const int widths[2] = {chunk, nvec % chunk};
+        // every width this apply launches is planned before the first
+        // launch, so a failure leaves g untouched
+        const int widths[2] = {base + (extra ? 1 : 0), base};
         for (int nv : widths) {
-            if (nv < 1) continue;
             std::string err = run_fused(p, nv, nullptr, nullptr, nullptr,
                                         nullptr, nullptr, true);
             if (!err.empty()) return err;
@@ -106,8 +110,8 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
     }
     const float2* f = (const float2*)fv;
     float2* g = (float2*)gv;
-    for (int v0 = 0; v0 < nvec; v0 += chunk) {
-        const int nv = std::min(chunk, nvec - v0);
+    for (int c = 0, v0 = 0; c < nch; ++c) {
+        const int nv = base + (c < extra ? 1 : 0);
         float2* b0 = (float2*)ws;
         float2* b1 = (float2*)((char*)ws + state_bytes(p, nv));
         std::string err =
@@ -116,6 +120,7 @@ std::string launch_apply(Plan& p, int nvec, const void* fv, void* gv,
                     : run_basic(p, nv, f + (size_t)v0 * p.N,
                                 g + (size_t)v0 * p.N, b0, b1, st);
         if (!err.empty()) return err;
+        v0 += nv;
     }
     return "";
 }

@@ -55,6 +55,9 @@ struct PassArgs {
                               // into the state tile (slot stride rmax) at
                               // every sub-iteration instead of being kept
                               // in a tile of its own for all of them
+    int tw_single;            // in-place head xi passes: 1 = one twiddle
+                              // buffer (the next level's twiddles written
+                              // after a barrier) instead of two
     int n_sub;                // sub-iterations per workgroup
     int x_split;              // tail x passes: workgroups sharing the
                               // sub-iterations (B groups) of one A group;
