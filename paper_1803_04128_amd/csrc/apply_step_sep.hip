@@ -74,20 +74,29 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
     // first job's block entries are read now, ahead of the level's work
     const int MT = SW ? (sw.r_out + 15) >> 4 : 0;
     const int KS = (a.r_out + 3) >> 2;
-    float2 sv0[16];
+    float2 sv0[16], sv1[16];
     if constexpr (SW) {
+        // this wave's first two jobs (all of them for blocks of up to 64 S
+        // rows: 4 children x 4 row tiles over 8 waves)
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        const int job = wave;
-        const int ii = job / MT, m = job - ii * MT;
-        const int row = 16 * m + (lane & 15), g = lane >> 4;
-        const bool ok = job < 4 * MT && row < sw.r_out;
-        const long long p = ((ap * 4 + ii) << shiftB) + b;
-        const float2* Sp = sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
+        const int row0 = lane & 15, g = lane >> 4;
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int s = 4 * ks + g;
-            sv0[ks] = (ok && ks < KS && s < a.r_out) ? Sp[s]
-                                                     : make_float2(0.f, 0.f);
+        for (int q = 0; q < 2; ++q) {
+            const int job = wave + q * kSepWaves;
+            const int ii = job / MT, m = job - ii * MT;
+            const int row = 16 * m + row0;
+            const bool ok = job < 4 * MT && row < sw.r_out;
+            const long long p = ((ap * 4 + ii) << shiftB) + b;
+            const float2* Sp =
+                sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                const int s = 4 * ks + g;
+                const float2 v = (ok && ks < KS && s < a.r_out)
+                                     ? Sp[s]
+                                     : make_float2(0.f, 0.f);
+                if (q == 0) sv0[ks] = v; else sv1[ks] = v;
+            }
         }
     }
     {
@@ -208,6 +217,9 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
             if (job == wave) {
 #pragma unroll
                 for (int ks = 0; ks < 16; ++ks) sv[ks] = sv0[ks];
+            } else if (job == wave + kSepWaves) {
+#pragma unroll
+                for (int ks = 0; ks < 16; ++ks) sv[ks] = sv1[ks];
             } else {
                 const int row = 16 * m + n;
                 const float2* Sp = sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
