@@ -47,6 +47,23 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Units of local level j (u < Gk / 2) in slot order: u = bl 2^(j-1) + rv,
+// rv the bit-reversed apl, so consecutive units read and write consecutive
+// slots of the tile (the lanes of one MFMA tile then spread over the LDS
+// banks instead of meeting at power-of-two slot strides).  The staged
+// twiddles of a level use the same order ([u][i][c][r]).
+struct UnitMap {
+    int bl, rv, apl;
+};
+
+__device__ __forceinline__ UnitMap unit_map(int u, int j) {
+    UnitMap m;
+    m.rv = u & ((1 << (j - 1)) - 1);
+    m.bl = u >> (j - 1);
+    m.apl = digit_rev(m.rv, j - 1, 1);
+    return m;
+}
+
 // ---- split precision: the Split<PREC> parts and products (split_common.h)
 
 // Exponent e of a power-of-two column scale for the half-precision split:
@@ -70,7 +87,8 @@ __device__ __forceinline__ int column_exponent(float m) {
 }
 
 // Twiddles of local level j for the group's units into LDS:
-// twl[unit_loc][i][c][r], unit_loc = apl 2^(k-j) + bl, contiguous per apl.
+// twl[u][i][c][r], u = bl 2^(j-1) + rv the unit in slot order (unit_map),
+// rv the bit-reversed apl.
 __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
                                                float2* twl, long long ap_grp,
                                                long long bg, bool xi) {
@@ -85,9 +103,9 @@ __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
     const unsigned bg0 = (unsigned)(bg << kj);
     Walk2 w(threadIdx.x, per_unit);
     for (int e = threadIdx.x; e < total; e += blockDim.x, w.next()) {
-        const unsigned unit = (unsigned)w.hi;
-        const unsigned apl = unit >> kj, bl = unit & ((1u << kj) - 1);
-        const unsigned u = ((apg0 + apl) << shiftB) + bg0 + bl;
+        const UnitMap um = unit_map(w.hi, j);
+        const unsigned u = ((apg0 + (unsigned)um.apl) << shiftB) + bg0 +
+                           (unsigned)um.bl;
         twl[e] = lv.tw[u * (unsigned)per_unit + (unsigned)w.lo];
     }
 }
@@ -99,14 +117,14 @@ __device__ __forceinline__ void stage_twiddles(const PassArgs& a, int j,
 template <int NT>
 struct TwStage {
     float2 v[NT];
-    int total, per_unit, kj, shiftB;
+    int total, per_unit, jl, shiftB;
     unsigned apg0, bg0;
     const float2* tw;
 
     __device__ __forceinline__ unsigned src_index(int unit, int lo) const {
-        const unsigned apl = (unsigned)unit >> kj;
-        const unsigned bl = (unsigned)unit & ((1u << kj) - 1);
-        const unsigned u = ((apg0 + apl) << shiftB) + bg0 + bl;
+        const UnitMap um = unit_map(unit, jl);
+        const unsigned u = ((apg0 + (unsigned)um.apl) << shiftB) + bg0 +
+                           (unsigned)um.bl;
         return u * (unsigned)per_unit + (unsigned)lo;
     }
 
@@ -115,7 +133,8 @@ struct TwStage {
                                          bool xi) {
         const PassLevel& lv = a.lv[j - 1];
         const int rr = xi ? lv.r_in : lv.r_out;
-        kj = a.k - j;
+        const int kj = a.k - j;
+        jl = j;
         per_unit = 4 * rr;
         total = (a.Gk >> 1) * per_unit;
         shiftB = a.L - (a.la + j - 1);
@@ -210,9 +229,11 @@ __device__ __forceinline__ void xi_tiles_fp32(const PassArgs& a,
         int ui = tau * CPT + sub;
         const bool ok = ui < a.Gk;
         if (!ok) ui = 0;                        // padding column: any valid data
+        // both children of a unit in one tile (one wave): the unit's output
+        // slots are its input slots, updated in place
         const int unit = ui >> 1, i = ui & 1;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const int rv = digit_rev(apl, j - 1, 1);
+        const UnitMap um = unit_map(unit, j);
+        const int bl = um.bl, rv = um.rv;
         const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
         const float2* wp = twl + (unit * 4 + i * 2) * r_in + woff;
         float2 xs[NK], ws[NK];
@@ -281,8 +302,8 @@ __device__ __forceinline__ void mfma_xi_level(const PassArgs& a,
             const bool ok = ui < a.Gk;
             if (!ok) ui = 0;
             const int unit = ui >> 1, i = ui & 1;
-            const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-            const int rv = digit_rev(apl, j - 1, 1);
+            const UnitMap um = unit_map(unit, j);
+            const int bl = um.bl, rv = um.rv;
             const float2* xp = src + (((bl * 2) << (j - 1)) + rv) * RS + xbase;
             const float2* wp = twl + (unit * 4 + i * 2) * r_in + wbase;
             float zr[8], zi[8];
@@ -386,8 +407,8 @@ __device__ __forceinline__ void x_tiles_fp32(const PassArgs& a,
         int unit = tau * UPT + sub;
         const bool ok = unit < nunits;
         if (!ok) unit = 0;
-        const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-        const int rv = digit_rev(apl, j - 1, 1);
+        const UnitMap um = unit_map(unit, j);
+        const int bl = um.bl, rv = um.rv;
         const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS + xoff;
         const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
         float2 x0[NK], x1[NK];
@@ -480,8 +501,8 @@ __device__ __forceinline__ void mfma_x_level(const PassArgs& a,
             int unit = tau * UPT + sub;
             const bool ok = unit < nunits;
             if (!ok) unit = 0;
-            const int apl = unit >> kj, bl = unit & ((1 << kj) - 1);
-            const int rv = digit_rev(apl, j - 1, 1);
+            const UnitMap um = unit_map(unit, j);
+            const int bl = um.bl, rv = um.rv;
             const float2* xp0 = src + (((bl * 2) << (j - 1)) + rv) * RS;
             const float2* xp1 = xp0 + ((1 << (j - 1)) * RS);
             float2 x0[4], x1[4];
@@ -1035,7 +1056,8 @@ x_pass_mfma(PassArgs a) {
             if (unit >= nunits) continue;
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const int aloc = unit * 2 + i;       // last level: unit = apl
+                // last level (j = k): the unit's A boxes are its apl's
+                const int aloc = unit_map(unit, a.k).apl * 2 + i;
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const int t = 4 * g + jj;
