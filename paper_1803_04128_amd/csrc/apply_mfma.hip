@@ -156,11 +156,11 @@ struct TwStage {
             const int e = threadIdx.x + m * (int)blockDim.x;
             if (e < total) twl[e] = v[m];
         }
-        for (int e = threadIdx.x + NT * (int)blockDim.x; e < total;
-             e += blockDim.x) {
-            const int unit = e / per_unit;
-            twl[e] = tw[src_index(unit, e - unit * per_unit)];
-        }
+        const int e0 = threadIdx.x + NT * (int)blockDim.x;
+        if (e0 >= total) return;
+        Walk2 w(e0, per_unit);
+        for (int e = e0; e < total; e += blockDim.x, w.next())
+            twl[e] = tw[src_index(w.hi, w.lo)];
     }
 };
 

@@ -259,8 +259,14 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
     }
 }
 
-// x step, block = (unit, 16-column tile).  LDS: X [4][r_in][16],
+// x step, block = (kSepUnits consecutive units, 16-column tile): the units
+// run one after the other, the next unit's input panel and twiddles read
+// into registers while the current one computes.  LDS: X [4][r_in][16],
 // T [4][4][r_out], Z [4][2][a][b][16].
+constexpr int kSepUnits = 4;
+constexpr int kSepPreX = 8;      // panel entries per thread: 4 r_in 16 <= 4096
+constexpr int kSepPreT = 2;      // twiddles per thread: 16 r_out <= 1024
+
 __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
@@ -268,36 +274,58 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     float2* ts = xs + (size_t)4 * a.r_in * kCols;
     float2* zs = ts + (size_t)16 * a.r_out;
     const int nct = (a.Vc + kCols - 1) / kCols;
-    const long long u = (long long)blockIdx.x / nct;
-    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const long long grp = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - grp * nct) * kCols;
+    const long long u0 = grp * kSepUnits;
+    const long long u1 = u0 + kSepUnits < a.units ? u0 + kSepUnits : a.units;
     const int shiftB = 2 * (a.L - a.level);
-    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nthr = kSepWaves * 64;
-    {
-        const int n = threadIdx.x & (kCols - 1), col = col0 + n;
-        int row = threadIdx.x >> 4;
-        int c = row / a.r_in, s = row - c * a.r_in;
-        const long long pin0 = (ap << (shiftB + 2)) + (b << 2);
-        for (; c < 4; row += nthr / kCols) {
-            float2 v = make_float2(0.f, 0.f);
-            if (col < a.Vc) v = a.in[((pin0 + c) * a.r_in + s) * a.Vc + col];
-            xs[row * kCols + n] = v;
+    const int rows = 4 * a.r_in, nt = 16 * a.r_out;
+    // panel rows (child, point) of this thread: row0 + (nthr / 16) m
+    const int n16 = threadIdx.x & (kCols - 1), pcol = col0 + n16;
+    const int row0 = threadIdx.x >> 4;
+    float2 px[kSepPreX], pt[kSepPreT];
+    auto issue = [&](long long uu) {
+        const long long apu = uu >> shiftB, bu = uu & ((1LL << shiftB) - 1);
+        const long long pin0 = (apu << (shiftB + 2)) + (bu << 2);
+        int c = row0 / a.r_in, s = row0 - c * a.r_in;
+#pragma unroll
+        for (int m = 0; m < kSepPreX; ++m) {
+            px[m] = make_float2(0.f, 0.f);
+            if (c < 4 && pcol < a.Vc)
+                px[m] = a.in[((pin0 + c) * a.r_in + s) * a.Vc + pcol];
             s += nthr / kCols;
             while (s >= a.r_in) {
                 s -= a.r_in;
                 ++c;
             }
         }
-    }
-    for (int e = threadIdx.x; e < 16 * a.r_out; e += nthr)
-        ts[e] = a.tw[u * 16 * a.r_out + e];
+#pragma unroll
+        for (int m = 0; m < kSepPreT; ++m) {
+            const int e = threadIdx.x + m * nthr;
+            if (e < nt) pt[m] = a.tw[uu * nt + e];
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int m = 0; m < kSepPreX; ++m) {
+            const int row = row0 + m * (nthr / kCols);
+            if (row < rows) xs[row * kCols + n16] = px[m];
+        }
+#pragma unroll
+        for (int m = 0; m < kSepPreT; ++m) {
+            const int e = threadIdx.x + m * nthr;
+            if (e < nt) ts[e] = pt[m];
+        }
+    };
+    issue(u0);
+    put();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, n = lane & 15;
     const int nks = (A1 + 3) >> 2;
     float am[2];
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
-    __syncthreads();
     // this lane's D rows 4 g + j = (child, point) of both stages: stage 1
     // writes Z at (i2, t2) = that split (offset rz, -1 past 2b), stage 2
     // reads the same split as (i1, t1)
@@ -305,77 +333,87 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int row = 4 * g + j;
-        const int ch = row / B1, pt = row - ch * B1;
+        const int ch = row / B1, pt1 = row - ch * B1;
         const bool ok = row < 2 * B1;
-        rz[j] = ok ? (ch * A1 * B1 + pt) * kCols + n : -1;
+        rz[j] = ok ? (ch * A1 * B1 + pt1) * kCols + n : -1;
         ri1[j] = ok ? ch : -1;
-        rt1[j] = ok ? pt : 0;
+        rt1[j] = ok ? pt1 : 0;
     }
-    // stage 1: combos (c, s1); rows (i2, t2)
-    for (int cb = wave; cb < 4 * A1; cb += kSepWaves) {
-        const int c = cb / A1, s1 = cb - c * A1;
-        floatx4 zr = zero4(), zi = zero4();
-        const int xb = (c * a.r_in + s1 * A1 + g) * kCols + n;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            if (ks < nks) {                             // uniform
-                const int s2 = 4 * ks + g;
-                const float2 x = s2 < A1 ? xs[xb + 4 * ks * kCols]
-                                         : make_float2(0.f, 0.f);
-                zr = mma(am[ks], x.x, zr);
-                zi = mma(am[ks], x.y, zi);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (rz[j] >= 0)
-                zs[rz[j] + (c * 2 * A1 + s1) * B1 * kCols] =
-                    make_float2(zr[j], zi[j]);
-    }
-    __syncthreads();
-    // stage 2 and the twiddles: combos (i2, t2); rows (i1, t1); sum over c
     const int col = col0 + n;
-    for (int cb = wave; cb < 2 * B1; cb += kSepWaves) {
-        const int i2 = cb / B1, t2 = cb - i2 * B1;
-        // this lane's output rows (i1, t1): child ii, coefficient t
-        int ii[4], tt[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            ii[j] = ri1[j] < 0 ? -1 : ri1[j] * 2 + i2;
-            tt[j] = rt1[j] * B1 + t2;
-        }
-        floatx4 dr = zero4(), di = zero4();
-        for (int c = 0; c < 4; ++c) {
-            floatx4 yr = zero4(), yi = zero4();
-            const int zb = (((c * 2 + i2) * A1) * B1 + t2) * kCols + n;
+    for (long long u = u0; u < u1; ++u) {
+        const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+        __syncthreads();                    // X and T of unit u in LDS
+        if (u + 1 < u1) issue(u + 1);       // in flight during the stages
+        // stage 1: combos (c, s1); rows (i2, t2)
+        for (int cb = wave; cb < 4 * A1; cb += kSepWaves) {
+            const int c = cb / A1, s1 = cb - c * A1;
+            floatx4 zr = zero4(), zi = zero4();
+            const int xb = (c * a.r_in + s1 * A1 + g) * kCols + n;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 if (ks < nks) {                         // uniform
-                    const int s1 = 4 * ks + g;
-                    const float2 z = s1 < A1 ? zs[zb + s1 * B1 * kCols]
+                    const int s2 = 4 * ks + g;
+                    const float2 x = s2 < A1 ? xs[xb + 4 * ks * kCols]
                                              : make_float2(0.f, 0.f);
-                    yr = mma(am[ks], z.x, yr);
-                    yi = mma(am[ks], z.y, yi);
+                    zr = mma(am[ks], x.x, zr);
+                    zi = mma(am[ks], x.y, zi);
                 }
             }
 #pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (rz[j] >= 0)
+                    zs[rz[j] + (c * 2 * A1 + s1) * B1 * kCols] =
+                        make_float2(zr[j], zi[j]);
+        }
+        __syncthreads();
+        // stage 2 and the twiddles: combos (i2, t2); rows (i1, t1); sum
+        // over c
+        for (int cb = wave; cb < 2 * B1; cb += kSepWaves) {
+            const int i2 = cb / B1, t2 = cb - i2 * B1;
+            // this lane's output rows (i1, t1): child ii, coefficient t
+            int ii[4], tt[4];
+#pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (ii[j] >= 0) {
-                    const float2 T = ts[(ii[j] * 4 + c) * a.r_out + tt[j]];
-                    dr[j] += T.x * yr[j] - T.y * yi[j];
-                    di[j] += T.x * yi[j] + T.y * yr[j];
+                ii[j] = ri1[j] < 0 ? -1 : ri1[j] * 2 + i2;
+                tt[j] = rt1[j] * B1 + t2;
+            }
+            floatx4 dr = zero4(), di = zero4();
+            for (int c = 0; c < 4; ++c) {
+                floatx4 yr = zero4(), yi = zero4();
+                const int zb = (((c * 2 + i2) * A1) * B1 + t2) * kCols + n;
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    if (ks < nks) {                     // uniform
+                        const int s1 = 4 * ks + g;
+                        const float2 z = s1 < A1 ? zs[zb + s1 * B1 * kCols]
+                                                 : make_float2(0.f, 0.f);
+                        yr = mma(am[ks], z.x, yr);
+                        yi = mma(am[ks], z.y, yi);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (ii[j] >= 0) {
+                        const float2 T = ts[(ii[j] * 4 + c) * a.r_out + tt[j]];
+                        dr[j] += T.x * yr[j] - T.y * yi[j];
+                        di[j] += T.x * yi[j] + T.y * yr[j];
+                    }
+                }
+            }
+            if (col < a.Vc) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (ii[j] >= 0) {
+                        const long long pout = ((ap * 4 + ii[j]) << shiftB) + b;
+                        a.out[(pout * a.r_out + tt[j]) * a.Vc + col] =
+                            make_float2(dr[j], di[j]);
+                    }
                 }
             }
         }
-        if (col < a.Vc) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (ii[j] >= 0) {
-                    const long long pout = ((ap * 4 + ii[j]) << shiftB) + b;
-                    a.out[(pout * a.r_out + tt[j]) * a.Vc + col] =
-                        make_float2(dr[j], di[j]);
-                }
-            }
+        if (u + 1 < u1) {
+            __syncthreads();                // X, Z and T of unit u are read
+            put();
         }
     }
 }
@@ -430,7 +468,9 @@ std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
                             hipStream_t st) {
     (void)p;
     const long long nct = (a.Vc + kCols - 1) / kCols;
-    const long long nb = s.units * nct;
+    const long long groups =
+        s.kind == STEP_XI ? s.units : (s.units + kSepUnits - 1) / kSepUnits;
+    const long long nb = groups * nct;
     if (nb > 0x7fffffffLL) return "step grid too large";
     const size_t lds = step_sep_lds(s);
     if (lds > 160 * 1024) return "step does not fit in LDS";

@@ -211,10 +211,12 @@ struct HeadRegs {
         const int per_box = a.head_r * a.Vt;
         const int total = a.Gk * per_box;
         const int gap = (rs - a.head_r) * a.Vt;
+        Walk2 w(threadIdx.x, per_box);
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
             const int e = threadIdx.x + m * (int)blockDim.x;
-            if (e < total) dst[e + (e / per_box) * gap] = v[m];
+            if (e < total) dst[e + w.hi * gap] = v[m];
+            w.next();
         }
     }
 };
