@@ -52,32 +52,51 @@ struct SwFuse {
     int ys_off;          // LDS offset (float2) of the level's output Y
 };
 
-// xi step, block = (unit, 16-column tile), kSepWaves waves: kSepWaves / 4
-// per output child i.  LDS: X [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16];
-// with SW, Y [4][r_out][16] at sw.ys_off (over X and W once they are read,
-// or past Z).
-template <bool SW>
+// Units per block of the per-step kernels: the units run one after the
+// other, the next unit's input panel and twiddles read into registers while
+// the current one computes.
+constexpr int kSepUnits = 4;
+constexpr int kSepPreX = 8;      // panel entries per thread: 4 r_in 16 <= 4096
+constexpr int kSepPreT = 2;      // twiddles per thread: 16 r <= 1024
+
+// xi step, block = (kSepUnits consecutive units, or one with SW, 16-column
+// tile), kSepWaves waves: kSepWaves / 4 per output child i.  LDS: X
+// [4][r_in][16], W [4][4][r_in], Z [4][2][a][b][16]; with SW, Y
+// [4][r_out][16] at sw.ys_off (over X and W once they are read, or past Z).
+// MODE: kSepPlain (kSepUnits units per block, pipelined), kSepHead (a level
+// that reads f: one unit per block, f gathered straight into LDS, few
+// registers so that four blocks share a CU), kSepSwitch (the switch fused
+// behind the level, one unit per block).
+enum { kSepPlain = 0, kSepHead = 1, kSepSwitch = 2 };
+
+template <int MODE>
 __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
                                                               SwFuse sw) {
+    constexpr bool SW = MODE == kSepSwitch;
+    constexpr int UPB = MODE == kSepPlain ? kSepUnits : 1;
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
     float2* xs = lds_step;
     float2* ws = xs + (size_t)4 * a.r_in * kCols;
     float2* zs = ws + (size_t)16 * a.r_in;
     const int nct = (a.Vc + kCols - 1) / kCols;
-    const long long u = (long long)blockIdx.x / nct;
-    const int col0 = (int)((long long)blockIdx.x - u * nct) * kCols;
+    const long long grp = (long long)blockIdx.x / nct;
+    const int col0 = (int)((long long)blockIdx.x - grp * nct) * kCols;
+    const long long u0 = grp * UPB;
+    // (the grid covers the units exactly when UPB = 1)
+    const long long u1 = UPB == 1 ? u0 + 1
+                                  : (u0 + UPB < a.units ? u0 + UPB : a.units);
     const int shiftB = 2 * (a.L - a.level);
-    const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
     const int nthr = kSepWaves * 64;
     // switch: jobs (output child, 16-row tile of S), one wave each; the
-    // first job's block entries are read now, ahead of the level's work
+    // first two jobs' block entries are read now, ahead of the level's work
+    // (all of them for blocks of up to 64 S rows: 4 children x 4 row tiles
+    // over 8 waves)
     const int MT = SW ? (sw.r_out + 15) >> 4 : 0;
     const int KS = (a.r_out + 3) >> 2;
     float2 sv0[16], sv1[16];
     if constexpr (SW) {
-        // this wave's first two jobs (all of them for blocks of up to 64 S
-        // rows: 4 children x 4 row tiles over 8 waves)
+        const long long ap = u0 >> shiftB, b = u0 & ((1LL << shiftB) - 1);
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int row0 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -99,28 +118,66 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
             }
         }
     }
-    {
-        // (child, point) rows advance by nthr / 16 per round; each thread
-        // keeps its column and steps its row without a division
-        const int n = threadIdx.x & (kCols - 1), col = col0 + n;
-        int row = threadIdx.x >> 4;
-        int c = row / a.r_in, s = row - c * a.r_in;
-        const long long pin0 = (ap << (shiftB + 2)) + (b << 2);
-        for (; c < 4; row += nthr / kCols) {
-            float2 v = make_float2(0.f, 0.f);
-            if (col < a.Vc)
-                v = a.reads_f ? head_value(a, b * 4 + c, s, col)
-                              : a.in[((pin0 + c) * a.r_in + s) * a.Vc + col];
-            xs[row * kCols + n] = v;
+    // input panel rows (child, point) of this thread: row0 + (nthr / 16) m,
+    // its column fixed; the row steps without a division
+    const int rows = 4 * a.r_in, nw = 16 * a.r_in;
+    const int n16 = threadIdx.x & (kCols - 1), pcol = col0 + n16;
+    const int prow0 = threadIdx.x >> 4;
+    float2 px[kSepPreX], pw[kSepPreT];
+    auto issue = [&](long long uu) {
+        const long long apu = uu >> shiftB, bu = uu & ((1LL << shiftB) - 1);
+        const long long pin0 = (apu << (shiftB + 2)) + (bu << 2);
+        int c = prow0 / a.r_in, s = prow0 - c * a.r_in;
+#pragma unroll
+        for (int m = 0; m < kSepPreX; ++m) {
+            px[m] = make_float2(0.f, 0.f);
+            if (c < 4 && pcol < a.Vc)
+                px[m] = a.reads_f
+                            ? head_value(a, bu * 4 + c, s, pcol)
+                            : a.in[((pin0 + c) * a.r_in + s) * a.Vc + pcol];
             s += nthr / kCols;
             while (s >= a.r_in) {
                 s -= a.r_in;
                 ++c;
             }
         }
+#pragma unroll
+        for (int m = 0; m < kSepPreT; ++m) {
+            const int e = threadIdx.x + m * nthr;
+            if (e < nw) pw[m] = a.tw[uu * nw + e];
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int m = 0; m < kSepPreX; ++m) {
+            const int row = prow0 + m * (nthr / kCols);
+            if (row < rows) xs[row * kCols + n16] = px[m];
+        }
+#pragma unroll
+        for (int m = 0; m < kSepPreT; ++m) {
+            const int e = threadIdx.x + m * nthr;
+            if (e < nw) ws[e] = pw[m];
+        }
+    };
+    if constexpr (MODE == kSepHead) {
+        // the head level: f gathered straight into LDS
+        const long long bu = u0 & ((1LL << shiftB) - 1);
+        int row = prow0, c = row / a.r_in, s = row - c * a.r_in;
+        for (; c < 4; row += nthr / kCols) {
+            xs[row * kCols + n16] = pcol < a.Vc
+                                        ? head_value(a, bu * 4 + c, s, pcol)
+                                        : make_float2(0.f, 0.f);
+            s += nthr / kCols;
+            while (s >= a.r_in) {
+                s -= a.r_in;
+                ++c;
+            }
+        }
+        for (int e = threadIdx.x; e < nw; e += nthr) ws[e] = a.tw[u0 * nw + e];
+    } else {
+        issue(u0);
+        put();
     }
-    for (int e = threadIdx.x; e < 16 * a.r_in; e += nthr)
-        ws[e] = a.tw[u * 16 * a.r_in + e];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     constexpr int WPC = kSepWaves / 4;            // waves per output child
     const int i = wave / WPC, h = wave % WPC;
@@ -129,7 +186,6 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
     float am[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) am[ks] = a.amat_sep[ks * 64 + lane];
-    __syncthreads();
     // this lane's K entries (child, point) per K step, k = 4 ks + g: their
     // offsets in X and W (-1 past 2a)
     int kx[4], kw[4];
@@ -141,34 +197,6 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
         kx[ks] = ok ? (c2 * a.r_in + s2) * kCols + n : -1;
         kw[ks] = ok ? (i * 4 + c2) * a.r_in + s2 : -1;
     }
-    // stage 1: combos (c1, s1), split over the child's waves
-    for (int cb = h; cb < 2 * A1; cb += WPC) {
-        const int c1 = cb / A1, s1 = cb - c1 * A1;
-        const int dx = (2 * c1 * a.r_in + s1 * A1) * kCols;
-        const int dw = 2 * c1 * a.r_in + s1 * A1;
-        floatx4 zr = zero4(), zi = zero4();
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            if (ks < nks) {                             // uniform
-                float2 z = make_float2(0.f, 0.f);
-                if (kx[ks] >= 0) z = cmul(ws[kw[ks] + dw], xs[kx[ks] + dx]);
-                zr = mma(am[ks], z.x, zr);
-                zi = mma(am[ks], z.y, zi);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int t2 = 4 * g + j;
-            if (t2 < B1)
-                zs[((((size_t)i * 2 + c1) * A1 + s1) * B1 + t2) * kCols + n] =
-                    make_float2(zr[j], zi[j]);
-        }
-    }
-    __syncthreads();
-    // stage 2: one t2 per wave at a time
-    const int col = col0 + n;
-    const long long pout = ((ap * 4 + i) << shiftB) + b;
-    float2* o = a.out + pout * a.r_out * a.Vc + col;
     // stage-2 K entries (c1, s1) of this lane: offsets in Z (-1 past 2a)
     int kz[4];
 #pragma unroll
@@ -176,97 +204,135 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
         const int k = 4 * ks + g;
         kz[ks] = k < 2 * A1 ? ((i * 2 * A1 + k) * B1) * kCols + n : -1;
     }
+    const int col = col0 + n;
     float2* ys = lds_step + sw.ys_off;
-    for (int t2 = h; t2 < B1; t2 += WPC) {
-        floatx4 yr = zero4(), yi = zero4();
+    for (long long u = u0; u < u1; ++u) {
+        const long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
+        __syncthreads();                    // X and W of unit u in LDS
+        if constexpr (UPB > 1)
+            if (u + 1 < u1) issue(u + 1);
+        // stage 1: combos (c1, s1), split over the child's waves
+        for (int cb = h; cb < 2 * A1; cb += WPC) {
+            const int c1 = cb / A1, s1 = cb - c1 * A1;
+            const int dx = (2 * c1 * a.r_in + s1 * A1) * kCols;
+            const int dw = 2 * c1 * a.r_in + s1 * A1;
+            floatx4 zr = zero4(), zi = zero4();
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            if (ks < nks) {                             // uniform
-                float2 z = make_float2(0.f, 0.f);
-                if (kz[ks] >= 0) z = zs[kz[ks] + t2 * kCols];
-                yr = mma(am[ks], z.x, yr);
-                yi = mma(am[ks], z.y, yi);
+            for (int ks = 0; ks < 4; ++ks) {
+                if (ks < nks) {                         // uniform
+                    float2 z = make_float2(0.f, 0.f);
+                    if (kx[ks] >= 0)
+                        z = cmul(ws[kw[ks] + dw], xs[kx[ks] + dx]);
+                    zr = mma(am[ks], z.x, zr);
+                    zi = mma(am[ks], z.y, zi);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t2 = 4 * g + j;
+                if (t2 < B1)
+                    zs[((((size_t)i * 2 + c1) * A1 + s1) * B1 + t2) * kCols +
+                       n] = make_float2(zr[j], zi[j]);
+            }
+        }
+        __syncthreads();
+        // stage 2: one t2 per wave at a time
+        const long long pout = ((ap * 4 + i) << shiftB) + b;
+        float2* o = a.out + pout * a.r_out * a.Vc + col;
+        for (int t2 = h; t2 < B1; t2 += WPC) {
+            floatx4 yr = zero4(), yi = zero4();
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                if (ks < nks) {                         // uniform
+                    float2 z = make_float2(0.f, 0.f);
+                    if (kz[ks] >= 0) z = zs[kz[ks] + t2 * kCols];
+                    yr = mma(am[ks], z.x, yr);
+                    yi = mma(am[ks], z.y, yi);
+                }
+            }
+            if constexpr (SW) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t1 = 4 * g + j;
+                    if (t1 < B1)
+                        ys[((size_t)i * a.r_out + t1 * B1 + t2) * kCols + n] =
+                            make_float2(yr[j], yi[j]);
+                }
+            } else if (col < a.Vc) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t1 = 4 * g + j;
+                    if (t1 < B1)
+                        o[(size_t)(t1 * B1 + t2) * a.Vc] =
+                            make_float2(yr[j], yi[j]);
+                }
             }
         }
         if constexpr (SW) {
+            // nu^{A_i B} = S_{A_i B} mu^{A_i B}: rows t of S (16 per job),
+            // K = s, complex products as four real chains (Re S Re Y,
+            // Im S Im Y, Re S Im Y, Im S Re Y)
+            __syncthreads();
+            for (int job = wave; job < 4 * MT; job += kSepWaves) {
+                const int ii = job / MT, m = job - ii * MT;
+                const long long p = ((ap * 4 + ii) << shiftB) + b;
+                float2 sv[16];
+                if (job == wave) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int t1 = 4 * g + j;
-                if (t1 < B1)
-                    ys[((size_t)i * a.r_out + t1 * B1 + t2) * kCols + n] =
-                        make_float2(yr[j], yi[j]);
-            }
-        } else if (col < a.Vc) {
+                    for (int ks = 0; ks < 16; ++ks) sv[ks] = sv0[ks];
+                } else if (job == wave + kSepWaves) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int t1 = 4 * g + j;
-                if (t1 < B1)
-                    o[(size_t)(t1 * B1 + t2) * a.Vc] = make_float2(yr[j], yi[j]);
-            }
-        }
-    }
-    if constexpr (SW) {
-        // nu^{A_i B} = S_{A_i B} mu^{A_i B}: rows t of S (16 per job), K = s,
-        // complex products as four real chains (Re S Re Y, Im S Im Y,
-        // Re S Im Y, Im S Re Y)
-        __syncthreads();
-        for (int job = wave; job < 4 * MT; job += kSepWaves) {
-            const int ii = job / MT, m = job - ii * MT;
-            const long long p = ((ap * 4 + ii) << shiftB) + b;
-            float2 sv[16];
-            if (job == wave) {
+                    for (int ks = 0; ks < 16; ++ks) sv[ks] = sv1[ks];
+                } else {
+                    const int row = 16 * m + n;
+                    const float2* Sp =
+                        sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
 #pragma unroll
-                for (int ks = 0; ks < 16; ++ks) sv[ks] = sv0[ks];
-            } else if (job == wave + kSepWaves) {
-#pragma unroll
-                for (int ks = 0; ks < 16; ++ks) sv[ks] = sv1[ks];
-            } else {
-                const int row = 16 * m + n;
-                const float2* Sp = sw.S + ((size_t)p * sw.r_out + row) * a.r_out;
+                    for (int ks = 0; ks < 16; ++ks) {
+                        const int s = 4 * ks + g;
+                        sv[ks] = (row < sw.r_out && ks < KS && s < a.r_out)
+                                     ? Sp[s]
+                                     : make_float2(0.f, 0.f);
+                    }
+                }
+                floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
 #pragma unroll
                 for (int ks = 0; ks < 16; ++ks) {
-                    const int s = 4 * ks + g;
-                    sv[ks] = (row < sw.r_out && ks < KS && s < a.r_out)
-                                 ? Sp[s]
-                                 : make_float2(0.f, 0.f);
+                    if (ks < KS) {                      // uniform
+                        const int s = 4 * ks + g;
+                        const float2 yv =
+                            s < a.r_out
+                                ? ys[((size_t)ii * a.r_out + s) * kCols + n]
+                                : make_float2(0.f, 0.f);
+                        p1 = mma(sv[ks].x, yv.x, p1);
+                        p2 = mma(sv[ks].y, yv.y, p2);
+                        p3 = mma(sv[ks].x, yv.y, p3);
+                        p4 = mma(sv[ks].y, yv.x, p4);
+                    }
+                }
+                if (col < a.Vc) {
+                    float2* os = a.out + p * sw.r_out * a.Vc + col;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int t = 16 * m + 4 * g + j;
+                        if (t < sw.r_out)
+                            os[(size_t)t * a.Vc] =
+                                make_float2(p1[j] - p2[j], p3[j] + p4[j]);
+                    }
                 }
             }
-            floatx4 p1 = zero4(), p2 = zero4(), p3 = zero4(), p4 = zero4();
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                if (ks < KS) {                          // uniform
-                    const int s = 4 * ks + g;
-                    const float2 yv = s < a.r_out
-                                          ? ys[((size_t)ii * a.r_out + s) * kCols + n]
-                                          : make_float2(0.f, 0.f);
-                    p1 = mma(sv[ks].x, yv.x, p1);
-                    p2 = mma(sv[ks].y, yv.y, p2);
-                    p3 = mma(sv[ks].x, yv.y, p3);
-                    p4 = mma(sv[ks].y, yv.x, p4);
-                }
-            }
-            if (col < a.Vc) {
-                float2* os = a.out + p * sw.r_out * a.Vc + col;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int t = 16 * m + 4 * g + j;
-                    if (t < sw.r_out)
-                        os[(size_t)t * a.Vc] = make_float2(p1[j] - p2[j],
-                                                           p3[j] + p4[j]);
-                }
+        }
+        if constexpr (UPB > 1) {
+            if (u + 1 < u1) {
+                __syncthreads();            // X, W and Z of unit u are read
+                put();
             }
         }
     }
 }
 
-// x step, block = (kSepUnits consecutive units, 16-column tile): the units
-// run one after the other, the next unit's input panel and twiddles read
-// into registers while the current one computes.  LDS: X [4][r_in][16],
-// T [4][4][r_out], Z [4][2][a][b][16].
-constexpr int kSepUnits = 4;
-constexpr int kSepPreX = 8;      // panel entries per thread: 4 r_in 16 <= 4096
-constexpr int kSepPreT = 2;      // twiddles per thread: 16 r_out <= 1024
-
+// x step, block = (kSepUnits consecutive units, 16-column tile).  LDS: X
+// [4][r_in][16], T [4][4][r_out], Z [4][2][a][b][16].
 __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
@@ -456,8 +522,9 @@ bool step_sep_ok(const Plan& p, const Step& s) {
 }
 
 void init_step_sep_attrs() {
-    const void* fns[] = {(const void*)xi_step_sep<false>,
-                         (const void*)xi_step_sep<true>,
+    const void* fns[] = {(const void*)xi_step_sep<kSepPlain>,
+                         (const void*)xi_step_sep<kSepHead>,
+                         (const void*)xi_step_sep<kSepSwitch>,
                          (const void*)x_step_sep};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -468,8 +535,8 @@ std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
                             hipStream_t st) {
     (void)p;
     const long long nct = (a.Vc + kCols - 1) / kCols;
-    const long long groups =
-        s.kind == STEP_XI ? s.units : (s.units + kSepUnits - 1) / kSepUnits;
+    const int upb = s.kind == STEP_XI && s.reads_f ? 1 : kSepUnits;
+    const long long groups = (s.units + upb - 1) / upb;
     const long long nb = groups * nct;
     if (nb > 0x7fffffffLL) return "step grid too large";
     const size_t lds = step_sep_lds(s);
@@ -478,8 +545,12 @@ std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
     a.b1 = s.ax_out.r1;
     a.amat_sep = s.amat_sep;
     if (s.kind == STEP_XI)
-        hipLaunchKernelGGL(xi_step_sep<false>, dim3((unsigned)nb),
-                           dim3(kSepWaves * 64), lds, st, a, SwFuse{});
+        if (s.reads_f)
+            hipLaunchKernelGGL(xi_step_sep<kSepHead>, dim3((unsigned)nb),
+                               dim3(kSepWaves * 64), lds, st, a, SwFuse{});
+        else
+            hipLaunchKernelGGL(xi_step_sep<kSepPlain>, dim3((unsigned)nb),
+                               dim3(kSepWaves * 64), lds, st, a, SwFuse{});
     else
         hipLaunchKernelGGL(x_step_sep, dim3((unsigned)nb),
                            dim3(kSepWaves * 64), lds, st, a);
@@ -502,7 +573,7 @@ std::string launch_sep_switch(const Plan& p, const Step& xi, const Step& sw,
     a.a1 = xi.ax_in.r1;
     a.b1 = xi.ax_out.r1;
     a.amat_sep = xi.amat_sep;
-    hipLaunchKernelGGL(xi_step_sep<true>, dim3((unsigned)nb),
+    hipLaunchKernelGGL(xi_step_sep<kSepSwitch>, dim3((unsigned)nb),
                        dim3(kSepWaves * 64), lds, st, a, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
