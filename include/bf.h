@@ -402,6 +402,10 @@ typedef struct bf_config {
                             reduced modulo 1, FP32 sincospi) instead of
                             reading the stored blocks; a plan whose form
                             never reads them does not store them        */
+    int max_pass_levels; /* fused forms: levels per pass at most this many
+                            (each half then split into equal passes; a
+                            single level left over joins the pass before
+                            it); 0 = as many as the LDS holds; 0..12   */
 } bf_config;
 
 /* Current execution form of the plan. */

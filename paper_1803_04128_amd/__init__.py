@@ -342,19 +342,23 @@ class Plan:
 
     def config(self):
         """Execution form: {"path", "tile_cols", "tile_cols_used",
-        "switch_otf"}."""
+        "switch_otf", "max_pass_levels"}."""
         c = _lib.BfConfig()
         _lib.check(self._lib.bf_get_config(self._h, C.byref(c)))
         names = {v: k for k, v in PATHS.items()}
         return dict(path=names[c.path], tile_cols=c.tile_cols,
                     tile_cols_used=c.tile_cols_used,
-                    switch_otf=bool(c.switch_otf))
+                    switch_otf=bool(c.switch_otf),
+                    max_pass_levels=c.max_pass_levels)
 
-    def set_config(self, path="fused", tile_cols=0, switch_otf=False):
+    def set_config(self, path="fused", tile_cols=0, switch_otf=False,
+                   max_pass_levels=0):
         """switch_otf (per_step_mfma only): generate the switch blocks
-        during the apply instead of storing them."""
+        during the apply instead of storing them.  max_pass_levels (fused
+        forms): at most this many levels per pass, each half split into
+        equal passes (0: as many as the LDS holds)."""
         c = _lib.BfConfig(PATHS[path], int(tile_cols), 0,
-                          1 if switch_otf else 0)
+                          1 if switch_otf else 0, int(max_pass_levels))
         _lib.check(self._lib.bf_set_config(self._h, C.byref(c)))
 
     def autotune(self, f, out=None, reps=3, stream=None):
@@ -371,7 +375,8 @@ class Plan:
         names = {v: k for k, v in PATHS.items()}
         return [dict(path=names[e.config.path], tile_cols=e.config.tile_cols,
                      tile_cols_used=e.config.tile_cols_used,
-                     switch_otf=bool(e.config.switch_otf), ms=e.ms)
+                     switch_otf=bool(e.config.switch_otf),
+                     max_pass_levels=e.config.max_pass_levels, ms=e.ms)
                 for e in arr[:min(cnt.value, cap)]]
 
     def graph(self, f, out=None):

@@ -69,11 +69,12 @@ int path_of(const bfi::Plan& p) {
     return p.mfma ? BF_PATH_FUSED : BF_PATH_FUSED_VALU;
 }
 
-void put_path(bfi::Plan& p, int path, int tile_cols, int switch_otf) {
-    p.fused = path == BF_PATH_FUSED || path == BF_PATH_FUSED_VALU;
-    p.mfma = path == BF_PATH_FUSED || path == BF_PATH_PER_STEP_MFMA;
-    p.tile_cols = tile_cols;
-    p.switch_otf = switch_otf != 0;
+void put_path(bfi::Plan& p, const bf_config& c) {
+    p.fused = c.path == BF_PATH_FUSED || c.path == BF_PATH_FUSED_VALU;
+    p.mfma = c.path == BF_PATH_FUSED || c.path == BF_PATH_PER_STEP_MFMA;
+    p.tile_cols = c.tile_cols;
+    p.switch_otf = c.switch_otf != 0;
+    p.max_pass_levels = c.max_pass_levels;
 }
 
 // Validates cfg against the plan and makes it current; the default workspace
@@ -89,16 +90,19 @@ int apply_config(bfi::Plan& p, const bf_config& cfg) {
                     "up to 64");
     if (cfg.switch_otf != 0 && cfg.switch_otf != 1)
         return fail(BF_EINVAL, "bf_set_config: switch_otf must be 0 or 1");
+    if (cfg.max_pass_levels < 0 || cfg.max_pass_levels > 12)
+        return fail(BF_EINVAL, "bf_set_config: max_pass_levels must be 0..12");
     if (cfg.switch_otf && cfg.path != BF_PATH_PER_STEP_MFMA)
         return fail(BF_EUNSUPPORTED,
                     "bf_set_config: on-the-fly switch blocks exist in "
                     "BF_PATH_PER_STEP_MFMA only");
     const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
-    const int t0 = p.tile_cols;
+    const int t0 = p.tile_cols, d0 = p.max_pass_levels;
     auto restore = [&] {
         p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
+        p.max_pass_levels = d0;
     };
-    put_path(p, cfg.path, cfg.tile_cols, cfg.switch_otf);
+    put_path(p, cfg);
     std::string err = bfi::check_config(p);
     if (!err.empty()) {
         restore();
@@ -861,6 +865,7 @@ int bf_get_config(bf_plan_t plan, bf_config* cfg) {
         cfg->tile_cols_used =
             p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
         cfg->switch_otf = p.switch_otf ? 1 : 0;
+        cfg->max_pass_levels = p.max_pass_levels;
         return BF_OK;
     });
 }
@@ -894,27 +899,45 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
         if (hipGetDevice(&cur) != hipSuccess || cur != p.device)
             return fail(BF_EINVAL, "bf_autotune: plan belongs to another device");
         hipStream_t st = (hipStream_t)stream;
-        // candidates: both fused forms at tile widths r * 2^j <= 16, and the
-        // per-step launches; forms that resolve to the same kernels are timed once
+        // candidates: both fused forms at tile widths r * 2^j <= 16, the
+        // MFMA passes also with each half split into two or three passes
+        // (fusion depth), and the per-step launches; forms that resolve to
+        // the same kernels are timed once
+        int half = 0;
+        {
+            int nx = 0, nxi = 0;
+            for (const auto& s : p.steps) {
+                nxi += s.kind == bfi::STEP_XI;
+                nx += s.kind == bfi::STEP_X;
+            }
+            half = std::max(nxi, nx);
+        }
         std::vector<bf_config> cand;
         for (int path : {BF_PATH_FUSED, BF_PATH_FUSED_VALU})
-            for (int tc = p.r_amp; tc <= 16; tc *= 2)
-                cand.push_back({path, tc, 0, 0});
-        cand.push_back({BF_PATH_PER_STEP, 0, 0, 0});
-        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0});
-        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1});
+            for (int tc = p.r_amp; tc <= 16; tc *= 2) {
+                cand.push_back({path, tc, 0, 0, 0});
+                if (path == BF_PATH_FUSED)
+                    for (int parts = 2; parts <= 3; ++parts)
+                        if (half >= 2 * parts)
+                            cand.push_back({path, tc, 0, 0,
+                                            (half + parts - 1) / parts});
+            }
+        cand.push_back({BF_PATH_PER_STEP, 0, 0, 0, 0});
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0, 0});
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1, 0});
         // the stored switch blocks are read by every candidate but one
         if (!p.S_arena && !bfi::build_switch_blocks(p).empty()) {
             (void)hipGetLastError();
             return fail(BF_ENOMEM, "bf_autotune: switch block storage");
         }
         const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
-        const int t0 = p.tile_cols;
+        const int t0 = p.tile_cols, d0 = p.max_pass_levels;
         std::vector<bf_tune_entry> res;
-        std::vector<std::pair<int, int>> seen;   // (path, tile width) timed
+        // (form, tile width, passes) timed
+        std::vector<std::pair<int, int>> seen;
         size_t ws_need = 0;
         for (auto& c : cand) {
-            put_path(p, c.path, c.tile_cols, c.switch_otf);
+            put_path(p, c);
             bf_tune_entry e{};
             e.config = c;
             e.ms = -1.0;
@@ -929,7 +952,11 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
                                 (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
                 const int key = !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) : 2)
                                          : (mf ? 0 : 1);
-                std::pair<int, int> k{key, e.config.tile_cols_used};
+                const int np = p.fused ? bfi::fused_pass_count(
+                                             p, std::min(nvec, p.chunk_nvec) *
+                                                    p.r_amp)
+                                       : 0;
+                std::pair<int, int> k{key * 64 + np, e.config.tile_cols_used};
                 bool dup = false;
                 for (auto& s2 : seen) dup |= s2 == k;
                 if (!dup) {
@@ -955,8 +982,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
         int best = -1;
         for (size_t i = 0; i < res.size() && err.empty(); ++i) {
             if (res[i].ms != 0.0) continue;
-            put_path(p, res[i].config.path, res[i].config.tile_cols,
-                     res[i].config.switch_otf);
+            put_path(p, res[i].config);
             err = bfi::launch_apply(p, nvec, f, g, ws, ws_need, st);   // warm-up
             if (!err.empty()) break;
             if (hipEventRecord(e0, st) != hipSuccess) { err = "event record"; break; }
@@ -979,6 +1005,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
+        p.max_pass_levels = d0;
         if (!err.empty()) {
             (void)hipGetLastError();
             return fail(BF_EHIP, "bf_autotune: " + err);

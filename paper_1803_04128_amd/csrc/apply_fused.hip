@@ -370,10 +370,21 @@ static bool mfma_mode(const Plan& p, int Vt) {
     return p.mfma && p.dim == 1 && pow2_le8(Vt) && pow2_le8(p.r_amp);
 }
 
+// Levels of the next pass when the n levels left of a half are split into
+// equal passes of at most d levels (d = 0: one pass); a single level is never
+// left over for a pass of its own (the pass before takes it).
+static int split_levels(int n, int d) {
+    if (d <= 0 || n <= d) return n;
+    const int parts = (n + d - 1) / d;
+    const int take = (n + parts - 1) / parts;
+    return n - take == 1 ? n : take;
+}
+
 // Columns per tile: a multiple of the amplitude rank (the final sums
 // recombine the r terms of a vector inside one workgroup), about 8.  For the
 // MFMA passes the width is a power of two, lowered (not below r) until the
-// larger half of the levels fits one pass (Gk * Vt <= 512).
+// larger half's passes fit (Gk * Vt <= 512; one pass per half unless the
+// fusion depth is capped).
 int fused_tile_cols(const Plan& p, int Vs) {
     // a configured width (a multiple of r) replaces the default of about 8
     int tv = std::max(1, 8 / p.r_amp);
@@ -383,7 +394,9 @@ int fused_tile_cols(const Plan& p, int Vs) {
         int v2 = 1;
         while (v2 * 2 <= vt) v2 *= 2;
         vt = v2;
-        const int m = std::max(count_kind(p, STEP_XI), count_kind(p, STEP_X));
+        const int m = split_levels(
+            std::max(count_kind(p, STEP_XI), count_kind(p, STEP_X)),
+            p.max_pass_levels);
         while (vt > p.r_amp && (1LL << m) * vt > 512) vt /= 2;
     }
     return vt;
@@ -441,11 +454,14 @@ std::vector<Pass> plan_passes(const Plan& p, int Vt) {
     int nxi = 0;
     while (nxi < nsteps && p.steps[nxi].kind == STEP_XI) ++nxi;
     const int sw = nxi;
-    // xi half: passes over [0, nxi) ; the switch rides on the last one
+    // xi half: passes over [0, nxi) ; the switch rides on the last one.
+    // With a fusion-depth cap the remaining levels are split into equal
+    // passes of at most that many; every pass is then shortened until it
+    // fits.
     if (nxi > 0) {
         int s0 = 0;
         while (s0 < nxi) {
-            int s1 = nxi - 1;
+            int s1 = s0 + split_levels(nxi - s0, p.max_pass_levels) - 1;
             while (s1 > s0 && !pass_fits(p, s0, s1, Vt, s0 == 0, false)) --s1;
             Pass ps{};
             ps.first = s0;
@@ -468,7 +484,7 @@ std::vector<Pass> plan_passes(const Plan& p, int Vt) {
     }
     bool first_x = true;
     while (s0 < nsteps) {
-        int s1 = nsteps - 1;
+        int s1 = s0 + split_levels(nsteps - s0, p.max_pass_levels) - 1;
         while (s1 > s0 &&
                !pass_fits(p, s0, s1, Vt, first_x && nxi == 0, s1 == nsteps - 1))
             --s1;

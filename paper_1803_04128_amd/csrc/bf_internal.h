@@ -179,6 +179,7 @@ struct Plan {
     bool fused = true;        // level-fused passes (else one launch per step)
     bool mfma = true;         // fused passes may use the MFMA kernels
     int tile_cols = 0;        // fused tile width override (0: heuristic)
+    int max_pass_levels = 0;  // fused: levels per pass cap (0: LDS-bound)
     int graphs = 0;           // live captured graphs bound to ws
     bool capturing = false;   // inside a graph capture (no event records)
     double flops_per_column = 0;

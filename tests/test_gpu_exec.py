@@ -56,6 +56,40 @@ def test_default_config_and_forms_agree_with_oracle():
         assert pl.info()["n_passes"] == pl.info()["n_steps"] + 1
 
 
+@pytest.mark.parametrize("precision,bar", [("fp32", TOL), ("bf16x3", 1e-4)])
+def test_fusion_depth_cap_agrees_with_oracle(precision, bar):
+    """max_pass_levels splits each half (5 levels here) into equal passes
+    of at most that many levels: more passes (n_passes), the same
+    factorization, every result within the bar of the oracle and of the
+    uncapped form."""
+    bfm = _bfm()
+    n, q, nvec = 65536, 10, 3
+    log(f"case fusion depth n={n} q={q} {precision}")
+    f32, f, ab = inputs(1, n, nvec, 33, amp="sincos", r=4)
+    ref = butterfly_matvec(1, n, "fio1d", PHASE_PARAMS["fio1d"], q, ab[0],
+                           ab[1], f)
+    with bfm.Plan(1, n, "fio1d", PHASE_PARAMS["fio1d"], q=q, amplitude=ab,
+                  max_nvec=nvec, precision=precision) as pl:
+        ft = _to_dev(f32)
+        g0 = _host(pl.apply(ft))
+        p0 = pl.info()["n_passes"]
+        for d in (2, 3, 4):
+            pl.set_config("fused", 0, max_pass_levels=d)
+            assert pl.config()["max_pass_levels"] == d
+            np_ = pl.info()["n_passes"]
+            g = _host(pl.apply(ft))
+            e_or, e_0 = np.max(rel(g, ref)), np.max(rel(g, g0))
+            log(f"  depth {d}: {np_} passes, width "
+                f"{pl.config()['tile_cols_used']}, vs oracle {e_or:.2e}, "
+                f"vs uncapped {e_0:.2e}")
+            assert np_ > p0
+            assert e_or < bar and e_0 < 2 * bar
+        with pytest.raises(bfm.BfError) as ei:
+            pl.set_config("fused", 0, max_pass_levels=13)
+        assert ei.value.code == bfm._lib.BF_EINVAL
+        assert pl.config()["max_pass_levels"] == 4
+
+
 def test_set_config_rejects_bad_forms():
     bfm = _bfm()
     with bfm.Plan(1, 1024, "fio1d", PHASE_PARAMS["fio1d"], q=8,
@@ -98,6 +132,11 @@ def test_autotune_picks_a_timed_form(dim, n, kind, q, nvec, amp, r):
         c = pl.config()
         assert c["path"] == best["path"]
         assert c["tile_cols"] == best["tile_cols"]
+        assert c["max_pass_levels"] == best["max_pass_levels"]
+        if dim == 1:
+            # fusion depth is among the tuned choices
+            assert any(e["max_pass_levels"] > 0 and e["ms"] > 0
+                       for e in res)
         g1 = _host(pl.apply(ft))
         assert np.max(rel(g1, g0)) < 2 * TOL
     if dim == 1 and n <= 8192:
