@@ -21,7 +21,8 @@ Readings taken where the text is silent or does not work as printed:
 * The center c_A (the index of A closest to the mean of its indices) is the
   lower middle index, start + floor((N_A - 1) / 2).
 * Trees are dyadic down to single-index leaves (the 16 x 16 illustration of
-  Section 4); the switch level is h = floor(L / 2) when L is odd.
+  Section 4); the switch level is h = floor(L / 2) when L is odd, and
+  L - floor(L / 2) for the transposed kernel (see butterfly_apply).
 * Inside Algorithm 4.1 the input vector is called g; here it is f and the
   output is g.
 
@@ -148,6 +149,16 @@ def _contract(Lag, z):
     return np.moveaxis(out.reshape(lead + (Lag.shape[0],)), -1, -2)
 
 
+def switch_level(L, transpose):
+    """Level h of the switch (Algorithm 4.1, step 4): floor(L / 2) for odd L
+    (the paper takes L even).  The factorization of the transposed kernel
+    mirrors K's levels (its recursion in xi is the transpose of K's
+    recursion in x, and the other way round), so it switches at
+    L - floor(L / 2); the two factorizations are then exact transposes of
+    each other at every depth."""
+    return L - L // 2 if transpose else L // 2
+
+
 def butterfly_apply(dim, n, phase_kind, phase_params, q, f, a_block=None,
                     transpose=False, conjugate=False):
     """Butterfly algorithm (Algorithm 4.1) applied to the columns of
@@ -164,7 +175,8 @@ def butterfly_apply(dim, n, phase_kind, phase_params, q, f, a_block=None,
     (with transpose, the adjoint K^H).
     """
     T = Trees(dim, n, q)
-    L, h = T.L, T.L // 2
+    L = T.L
+    h = switch_level(L, transpose)
     f = np.atleast_2d(np.asarray(f, np.complex128))
     V = f.shape[0]
     sgn = -1 if conjugate else 1

@@ -2,7 +2,8 @@
 //
 // Notation follows Section 4 of the paper: trees T_X and T_Omega of depth L
 // over an n^dim grid, tree level l, pairs (A, B) with A at level l of T_X and
-// B at level L - l of T_Omega, switch level h = floor(L / 2).  R = 2^dim is
+// B at level L - l of T_Omega, switch level h = floor(L / 2) (L - floor(L / 2)
+// when the plan factorizes the transposed kernel).  R = 2^dim is
 // the number of children of a box.
 #pragma once
 

@@ -18,7 +18,9 @@
 // 2^l <= q are copies of f and the x levels whose parent box has at most q
 // indices are plain sums (Algorithm 4.1, steps 2-3 and 5-6 specialised).
 // Only levels l0 = floor(log2 q) + 1 .. h (xi) and h+1 .. L+1-l0 (x) are
-// computed, plus the switch at h = floor(L / 2).
+// computed, plus the switch at h = floor(L / 2) (L - floor(L / 2) for the
+// transposed kernel, whose factorization is then the exact transpose of
+// K's).
 #include <cmath>
 #include <cstring>
 
@@ -153,7 +155,10 @@ static void x_matrices(Step& s, int dim, int R) {
 std::string build_schedule(Plan& p) {
     const int d = p.dim;
     p.L = ilog2(p.n);
-    p.h = p.L / 2;
+    // switch level floor(L / 2); the factorization of K^T mirrors K's (its
+    // recursion in xi is the transpose of K's recursion in x), so it
+    // switches at L - floor(L / 2) and is the exact transpose of K's
+    p.h = p.phase.transpose ? p.L - p.L / 2 : p.L / 2;
     p.R = 1 << d;
     p.N = 1;
     for (int k = 0; k < d; ++k) p.N *= p.n;

@@ -5,7 +5,10 @@ Same bars as the forward apply: relative l2 <= 1e-5 per vector against the
 oracle's butterfly of the same operator (same factorization), <= 1e-5
 against the dense matvec where the factorization is exact, the BF16x3 and
 FP16x3 bars of the forward apply for the split precisions, and at sizes the
-oracle cannot finish, the FFT closed form and the adjoint identity."""
+oracle cannot finish, the FFT closed form and the adjoint identity.  The
+factorization of K^T is the exact transpose of K's (the oracle pins it to
+rounding): as matrices the GPU's BF_{K^T} and BF_{K^H} equal BF_K^T and
+BF_K^H to FP32 rounding, at odd and even depth."""
 
 import numpy as np
 import pytest
@@ -151,13 +154,35 @@ def test_dft_adjoint_against_fft_full_size():
     assert rel(gt, n * np.fft.ifft(s * f, axis=-1))[0] < bound
 
 
-def test_adjoint_identity_at_full_size():
-    # <K f, h> = <f, K^H h> holds for the exact operators; the two
-    # factorizations approximate K and K^H each to eps_BF, so the FP32
-    # applies must agree to that plus rounding (N = 2^20, q = 10: eps_BF
-    # ~ 2e-8 in FP64)
+@pytest.mark.parametrize("dim,n,q,kind", [(1, 2048, 8, "fio1d"),
+                                          (1, 1024, 8, "fio1d"),
+                                          (2, 32, 5, "radon2d")])
+def test_transpose_is_exact_transpose_of_forward(dim, n, q, kind):
+    # depth L = 11, 10 (1D), 5 (2D): columns of the operators from applies
+    # to the unit vectors, BF_{K^T} against BF_K^T and BF_{K^H} against
+    # BF_K^H; the same FP32 factors in transposed order, so only rounding
+    # separates them (FP32 bar 1e-5 relative in Frobenius norm)
+    N = n ** dim
+    log(f"case exact transpose dim={dim} n={n} q={q}")
+    eye = np.eye(N, dtype=np.complex64)
+    mats = {}
+    for op in ("N", "T", "H"):
+        with _plan(dim, n, kind, q, op, nvec=N) as pl:
+            g, _ = gpu_apply(pl, eye)
+        mats[op] = g.T                      # column v = BF applied to e_v
+    nb = np.linalg.norm(mats["N"])
+    eT = np.linalg.norm(mats["T"] - mats["N"].T) / nb
+    eH = np.linalg.norm(mats["H"] - mats["N"].conj().T) / nb
+    log(f"  ||BF_T - BF^T|| {eT:.2e}, ||BF_H - BF^H|| {eH:.2e} (relative)")
+    assert eT < TOL and eH < TOL
+
+
+@pytest.mark.parametrize("n", [1 << 19, 1 << 20])
+def test_adjoint_identity_at_full_size(n):
+    # <K f, h> = <f, K^H h>: the factorization of K^H is the exact adjoint
+    # of K's at odd and even depth, so the FP32 applies agree to rounding
     import torch
-    n, q = 1 << 20, 10
+    q = 10
     log(f"case adjoint identity n={n}")
     f = gaussian_vectors(n, 1, 1900).astype(np.complex64)
     h = gaussian_vectors(n, 1, 1901).astype(np.complex64)

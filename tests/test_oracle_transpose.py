@@ -7,7 +7,11 @@ Phi(x_i, xi_j)) is again of the form of eq. (eqn:FIO), with the roles of x
 and xi exchanged, so Algorithm 4.1 factorizes it unchanged.  The pins here
 fix the dense flags to the plain matrix transpose and conjugate, the DFT
 case to the FFT, and the transposed butterfly to the dense transpose where
-it is exact and to the paper's error order where it is not."""
+it is exact and to the paper's error order where it is not.  As matrices,
+the factorization of K^T is the exact transpose of K's (its recursion in
+xi is the transpose of K's recursion in x, its switch the mirror level
+L - floor(L / 2)): pinned to rounding at odd and even depth, where only
+the mirrored switch level makes it so."""
 
 import os
 
@@ -231,6 +235,40 @@ def _unswapped_roles(kind, params, ix, jx, n, sign=1):
 
 def _dropped_conjugation(kind, params, ix, jx, n, sign=1):
     return kern.expi_phase(kind, params, ix, jx, n, abs(sign))
+
+
+def _bf_matrix(dim, n, kind, q, transpose=False, conjugate=False):
+    """The butterfly operator as a matrix: column v = BF applied to e_v."""
+    N = n ** dim
+    cols = butterfly_apply(dim, n, kind, PHASE_PARAMS[kind], q,
+                           np.eye(N, dtype=np.complex128),
+                           transpose=transpose, conjugate=conjugate)
+    return cols.T
+
+
+@pytest.mark.parametrize("dim,n,q,kind", [(1, 512, 6, "fio1d"),
+                                          (1, 256, 5, "fio1d"),
+                                          (1, 128, 4, "dft"),
+                                          (2, 32, 5, "radon2d"),
+                                          (2, 16, 3, "radon2d")])
+def test_butterfly_of_transpose_is_exact_transpose(dim, n, q, kind):
+    # depth L = 9, 8, 7 (1D) and 5, 4 (2D): BF_{K^T} = (BF_K)^T and
+    # BF_{K^H} = (BF_K)^H to rounding, not merely to eps_BF
+    B = _bf_matrix(dim, n, kind, q)
+    Bt = _bf_matrix(dim, n, kind, q, transpose=True)
+    Bh = _bf_matrix(dim, n, kind, q, transpose=True, conjugate=True)
+    nb = np.linalg.norm(B)
+    assert np.linalg.norm(Bt - B.T) < 1e-13 * nb
+    assert np.linalg.norm(Bh - B.conj().T) < 1e-13 * nb
+
+
+def test_unmirrored_switch_level_is_not_the_transpose(monkeypatch):
+    # the transposed factorization switching at floor(L / 2) like K's (odd
+    # L = 9) is a different approximation: the pin above would fail
+    B = _bf_matrix(1, 512, "fio1d", 6)
+    monkeypatch.setattr(bfo, "switch_level", lambda L, transpose: L // 2)
+    Bt = _bf_matrix(1, 512, "fio1d", 6, transpose=True)
+    assert np.linalg.norm(Bt - B.T) > 1e-4 * np.linalg.norm(B)
 
 
 def test_unmutated_transpose_pins_pass():
