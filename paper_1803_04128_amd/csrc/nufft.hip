@@ -52,6 +52,12 @@ struct NuArgs {
     const float2* post;
     const float* dec0;
     const float* dec1;
+    // 1D: the sources' contributions by grid cell (CSR, built at plan
+    // time): cell m takes entries cptr[m] .. cptr[m + 1] - 1, each a source
+    // index and its Gaussian weight times the cell's deconvolution factor
+    const int* cptr;
+    const int* cidx;
+    const float* cwt;
     const float2* a;
     const float2* b;
     const float2* f;                  // [nv][N] chunk
@@ -135,6 +141,48 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_spread(NuArgs a) {
                 }
             }
         }
+    }
+}
+
+// 1D spreading as a gather: thread per (grid cell, vector, group of kKG
+// amplitude terms) sums the contributions listed for its cell, in source
+// order, and writes every cell (no atomics, no zeroing, a deterministic
+// sum).  Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source
+// phase, as in nufft_spread.
+constexpr int kKG = 8;
+
+__global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
+    const int ngrp = (a.K + kKG - 1) / kKG;
+    const long long M = a.Mr[0];
+    const long long total = M * a.nv * ngrp;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+         e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)(e % M);
+        const long long rest = e / M;
+        const int grp = (int)(rest % ngrp), v = (int)(rest / ngrp);
+        const int k0 = grp * kKG;
+        float2 acc[kKG];
+#pragma unroll
+        for (int kk = 0; kk < kKG; ++kk) acc[kk] = make_float2(0.f, 0.f);
+        const int t1 = a.cptr[m + 1];
+        for (int t = a.cptr[m]; t < t1; ++t) {
+            const int j = a.cidx[t];
+            const float w = a.cwt[t];
+            const float2 fp = cmul(a.f[(size_t)v * a.N + j], a.pre[j]);
+            const float2 wf = make_float2(w * fp.x, w * fp.y);
+#pragma unroll
+            for (int kk = 0; kk < kKG; ++kk) {
+                if (k0 + kk < a.K) {
+                    const float2 z = cmul(a.b[(size_t)(k0 + kk) * a.N + j], wf);
+                    acc[kk].x += z.x;
+                    acc[kk].y += z.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < kKG; ++kk)
+            if (k0 + kk < a.K)
+                a.grid[(size_t)(v * a.K + k0 + kk) * a.cells + m] = acc[kk];
     }
 }
 
@@ -288,6 +336,9 @@ struct NufftPlan {
     float* dec[2] = {nullptr, nullptr};
     float2* a = nullptr;
     float2* bb = nullptr;
+    int* cptr = nullptr;      // 1D gather CSR (NuArgs)
+    int* cidx = nullptr;
+    float* cwt = nullptr;
     // FFT twiddle tables by log2 length
     std::vector<std::pair<int, float2*>> tw;
     const float2* twiddles(int logn) const {
@@ -403,7 +454,40 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
                                      std::exp(4 * kPi * kPi * q->b * x * x));
         }
     }
-    (void)b4;
+    // 1D: every source's 2 kW contributions listed by grid cell (CSR),
+    // each weight the Gaussian of the source's offset times the cell's
+    // deconvolution factor (FP64, stored FP32)
+    std::vector<int> cptr, cidx;
+    std::vector<float> cwt;
+    if (r == 1) {
+        const long long M = q->Mr[0];
+        const int Mh = q->Mh[0];
+        auto cell_of = [&](long long m) {
+            long long c = m % M;
+            return c < 0 ? c + M : c;
+        };
+        cptr.assign((size_t)M + 1, 0);
+        for (long long j = 0; j < N; ++j)
+            for (int e = 0; e < 2 * kW; ++e)
+                ++cptr[(size_t)cell_of(sbase[j] - kW + 1 + e) + 1];
+        for (long long m = 0; m < M; ++m) cptr[m + 1] += cptr[m];
+        std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+        cidx.resize((size_t)N * 2 * kW);
+        cwt.resize((size_t)N * 2 * kW);
+        for (long long j = 0; j < N; ++j)
+            for (int e = 0; e < 2 * kW; ++e) {
+                const long long m = sbase[j] - kW + 1 + e;   // mode index
+                if (m + Mh < 0 || m + Mh >= 2LL * Mh) {
+                    delete q;
+                    return "a source falls outside the lifted grid";
+                }
+                const double d = (double)(e - kW + 1) - (double)sfrac[j];
+                const int pos = fill[(size_t)cell_of(m)]++;
+                cidx[pos] = (int)j;
+                cwt[pos] = (float)(std::exp(-d * d / b4) *
+                                   (double)dec[0][m + Mh]);
+            }
+    }
     // FFT twiddles for every length the transforms use
     std::vector<int> lens;
     if (r == 1) {
@@ -435,6 +519,9 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
     }
     const size_t o_a = off; off = al(off + av.size() * 8);
     const size_t o_b = off; off = al(off + bv.size() * 8);
+    const size_t o_cp = off; off = al(off + cptr.size() * 4);
+    const size_t o_ci = off; off = al(off + cidx.size() * 4);
+    const size_t o_cw = off; off = al(off + cwt.size() * 4);
     std::vector<size_t> o_tw;
     for (int l : lens) {
         o_tw.push_back(off);
@@ -456,6 +543,9 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
     for (int d = 0; d < r; ++d) q->dec[d] = (float*)(base + o_dec[d]);
     q->a = (float2*)(base + o_a);
     q->bb = (float2*)(base + o_b);
+    q->cptr = (int*)(base + o_cp);
+    q->cidx = (int*)(base + o_ci);
+    q->cwt = (float*)(base + o_cw);
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t n) {
         if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
@@ -469,6 +559,9 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
     for (int d = 0; d < r; ++d) up(q->dec[d], dec[d].data(), dec[d].size() * 4);
     up(q->a, av.data(), av.size() * 8);
     up(q->bb, bv.data(), bv.size() * 8);
+    up(q->cptr, cptr.data(), cptr.size() * 4);
+    up(q->cidx, cidx.data(), cidx.size() * 4);
+    up(q->cwt, cwt.data(), cwt.size() * 4);
     for (size_t t = 0; t < lens.size(); ++t) {
         const int n = 1 << lens[t];
         std::vector<float2> w(std::max(1, n / 2));
@@ -554,12 +647,15 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         a.dec1 = q.dec[1];
         a.a = q.a;
         a.b = q.bb;
+        a.cptr = q.cptr;
+        a.cidx = q.cidx;
+        a.cwt = q.cwt;
         a.f = f + (size_t)v0 * q.N;
         a.g = g + (size_t)v0 * q.N;
         a.grid = (float2*)ws;
         const long long ncols = (long long)nv * q.K;
         const long long gcells = ncols * q.cells;
-        {
+        if (q.r == 2) {
             ProfScope ps(p, st);
             hipLaunchKernelGGL(nufft_zero, dim3(blocks_for_n(gcells)),
                                dim3(kNufftThreads), 0, st, a.grid, gcells);
@@ -568,8 +664,11 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         {
             ProfScope ps(p, st);
             if (q.r == 1)
-                hipLaunchKernelGGL(nufft_spread<1>, dim3(blocks_for_n(q.N)),
-                                   dim3(kNufftThreads), 0, st, a);
+                hipLaunchKernelGGL(
+                    nufft_gather1,
+                    dim3(blocks_for_n((long long)q.Mr[0] * nv *
+                                      ((q.K + kKG - 1) / kKG))),
+                    dim3(kNufftThreads), 0, st, a);
             else
                 hipLaunchKernelGGL(nufft_spread<2>, dim3(blocks_for_n(q.N)),
                                    dim3(kNufftThreads), 0, st, a);
