@@ -186,38 +186,50 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
     }
 }
 
-// Batched power-of-two FFT with the positive exponent, one sequence per
+// Batched power-of-two FFT with the positive exponent, `batch` sequences per
 // workgroup held in LDS: y_k = sum_t x_t exp(2 pi i t k / n).  Sequence s
 // of column col starts at col * col_dist + s * seq_dist, elements `stride`
-// apart.  Radix-2 decimation in time after a bit-reversed load.  With
-// total > 0 (first step of a four-step transform of length total), output
-// k of sequence s is multiplied by exp(2 pi i s k / total).
+// apart; the sequences of a workgroup are consecutive (s0 .. s0 + batch - 1),
+// so where seq_dist = 1 (the strided first step of a four-step transform)
+// each element index t is read and written as `batch` contiguous entries.
+// Radix-2 decimation in time after a bit-reversed load.  With total > 0
+// (first step of a four-step transform of length total), output k of
+// sequence s is multiplied by exp(2 pi i s k / total).
 struct FftArgs {
     float2* data;
     const float2* tw;       // exp(2 pi i k / n), k < n / 2
     int logn;
     long long stride, seq_dist, col_dist;
-    long long nseq;
+    long long nseq;         // sequences per column (a multiple of batch)
     long long total;
+    int batch;              // sequences per workgroup (power of two)
 };
 
 __global__ void __launch_bounds__(kNufftThreads) fft_lds(FftArgs a) {
-    __shared__ float2 x[kFftMax];
-    const int n = 1 << a.logn;
-    const long long sid = blockIdx.x;
-    const long long col = sid / a.nseq, s = sid - col * a.nseq;
-    float2* base = a.data + col * a.col_dist + s * a.seq_dist;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    extern __shared__ float2 x[];           // [batch][n]
+    const int n = 1 << a.logn, B = a.batch;
+    const long long groups = a.nseq / B;
+    const long long col = (long long)blockIdx.x / groups;
+    const long long s0 = ((long long)blockIdx.x - col * groups) * B;
+    float2* base = a.data + col * a.col_dist + s0 * a.seq_dist;
+    // element e: contiguous sequences (stride 1) are read one after the
+    // other (e = b n + t), strided ones element by element across the
+    // batch (e = t B + b), so that consecutive threads read neighbours
+    const bool bmajor = a.stride == 1;
+    for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
+        const int t = bmajor ? (e & (n - 1)) : e / B;
+        const int b = bmajor ? (e >> a.logn) : e - t * B;
         const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
-        x[rv] = base[(long long)t * a.stride];
+        x[b * n + rv] = base[(long long)t * a.stride + b * a.seq_dist];
     }
     __syncthreads();
     for (int lh = 0; lh < a.logn; ++lh) {
         const int half = 1 << lh;
         const int tstep = n >> (lh + 1);        // twiddle index step
-        for (int q = threadIdx.x; q < n / 2; q += blockDim.x) {
+        for (int qq = threadIdx.x; qq < (n / 2) * B; qq += blockDim.x) {
+            const int b = qq >> (a.logn - 1), q = qq & (n / 2 - 1);
             const int grp = q >> lh, jj = q & (half - 1);
-            const int i0 = (grp << (lh + 1)) + jj, i1 = i0 + half;
+            const int i0 = b * n + (grp << (lh + 1)) + jj, i1 = i0 + half;
             const float2 w = a.tw[jj * tstep];
             const float2 u = x[i0], v = cmul(x[i1], w);
             x[i0] = make_float2(u.x + v.x, u.y + v.y);
@@ -225,16 +237,18 @@ __global__ void __launch_bounds__(kNufftThreads) fft_lds(FftArgs a) {
         }
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        float2 y = x[t];
+    for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
+        const int t = bmajor ? (e & (n - 1)) : e / B;
+        const int b = bmajor ? (e >> a.logn) : e - t * B;
+        float2 y = x[b * n + t];
         if (a.total > 0) {
             // exp(2 pi i s t / total), the product reduced exactly first
-            const long long p = (s * t) & (a.total - 1);
+            const long long p = ((s0 + b) * t) & (a.total - 1);
             float sn, cs;
             sincospif(2.0f * (float)((double)p / (double)a.total), &sn, &cs);
             y = cmul(y, make_float2(cs, sn));
         }
-        base[(long long)t * a.stride] = y;
+        base[(long long)t * a.stride + b * a.seq_dist] = y;
     }
 }
 
@@ -361,6 +375,10 @@ size_t nufft_grid_bytes(const NufftPlan& q, int nv) {
 // FP64 host planning (see the head of this file).
 std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
                         int K, const double* a, const double* b) {
+    // batched FFT workgroups take up to 64 KB of LDS
+    (void)hipFuncSetAttribute((const void*)fft_lds,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536);
     NufftPlan* q = new (std::nothrow) NufftPlan();
     if (!q) return "host allocation";
     const long long N = p.N;
@@ -586,13 +604,23 @@ static std::string launch_fft(const NufftPlan& q, float2* data, int ncols,
                               hipStream_t st) {
     auto run = [&](int logn, long long stride, long long seq_dist,
                    long long nseq, long long total) -> std::string {
+        // adjacent sequences (seq_dist 1) share a workgroup in batches of
+        // up to 8 within 64 KB of LDS, so their reads coalesce (batching
+        // contiguous sequences measured no faster)
+        int batch = 1;
+        if (seq_dist == 1)
+            while (batch < 8 && ((long long)batch * 2 << logn) * 8 <= 65536 &&
+                   nseq % (batch * 2) == 0)
+                batch *= 2;
         FftArgs f{data, q.twiddles(logn), logn, stride, seq_dist, q.cells,
-                  nseq, total};
+                  nseq, total, batch};
         if (!f.tw) return "missing FFT twiddles";
-        const long long blocks = nseq * ncols;
+        const long long blocks = nseq / batch * ncols;
         if (blocks > 0x7fffffffLL) return "FFT grid too large";
         hipLaunchKernelGGL(fft_lds, dim3((unsigned)blocks),
-                           dim3(kNufftThreads), 0, st, f);
+                           dim3(kNufftThreads),
+                           (size_t)batch * ((size_t)1 << logn) * sizeof(float2),
+                           st, f);
         return "";
     };
     std::string err;
