@@ -108,7 +108,8 @@ def test_otf_plan_stores_no_switch_blocks_until_needed(monkeypatch):
             pl.set_config("fused", switch_otf=True)
         assert ei.value.code == bfm._lib.BF_EUNSUPPORTED
         assert pl.config() == dict(path="per_step_mfma", tile_cols=0,
-                                   tile_cols_used=0, switch_otf=False)
+                                   tile_cols_used=0, switch_otf=False,
+                                   max_pass_levels=0)
 
 
 def test_otf_fused_env_is_ignored(monkeypatch):
