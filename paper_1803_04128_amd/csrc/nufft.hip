@@ -12,7 +12,8 @@
 //   turns the sum into (1 / phihat(t')) h sum_m F_m e^{2 pi i m theta},
 //   theta = t' h, |theta| <= 1/4; that Fourier series is evaluated by the
 //   second gridding: coefficients h F_m / psihat_m on an oversampled FFT
-//   grid of Mr >= 4 Mh points (modes |m| <= Mh), one FFT with the positive
+//   grid of Mr points, a power of two of at least 4 Mh (63/64) (modes
+//   |m| <= Mh), one FFT with the positive
 //   exponent, and the Gaussian psi(theta) = exp(-(theta Mr)^2 / (4 b)) at
 //   each target, divided by Mr.
 // Both Gaussians use b = W / (4 pi sqrt(1/2)) and 2 W grid points per
@@ -35,6 +36,8 @@ namespace {
 constexpr int kW = 7;                 // stencil half-width (2 kW points)
 constexpr int kFftMax = 4096;         // longest FFT held in one workgroup
 constexpr int kNufftThreads = 256;
+constexpr int kFftLds = 80 * 1024;    // FFT workgroup LDS (two per CU)
+constexpr int kFftThreads = 1024;     // FFT workgroup (16 waves)
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 struct NuArgs {
@@ -43,7 +46,6 @@ struct NuArgs {
     int Mr[2], Mh[2];
     long long cells;
     float b4;                         // 4 b
-    int n1, n2;                       // 1D four-step split (n1 = 0: none)
     const int* sbase;
     const float* sfrac;
     const float2* pre;
@@ -187,59 +189,98 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
 }
 
 // Batched power-of-two FFT with the positive exponent, `batch` sequences per
-// workgroup held in LDS: y_k = sum_t x_t exp(2 pi i t k / n).  Sequence s
-// of column col starts at col * col_dist + s * seq_dist, elements `stride`
-// apart; the sequences of a workgroup are consecutive (s0 .. s0 + batch - 1),
-// so where seq_dist = 1 (the strided first step of a four-step transform)
-// each element index t is read and written as `batch` contiguous entries.
-// Radix-2 decimation in time after a bit-reversed load.  With total > 0
-// (first step of a four-step transform of length total), output k of
-// sequence s is multiplied by exp(2 pi i s k / total).
+// workgroup held in LDS: y_k = sum_t x_t exp(2 pi i t k / n).  Element t of
+// sequence s in column col is read at src + col col_dist + s seq_dist +
+// t stride, and output k is written at dst + col ocol_dist + s oseq_dist +
+// k ostride (dst = src with the same addressing transforms in place: a
+// workgroup reads all of its sequences before it writes any).  The
+// sequences of a workgroup are consecutive (s0 .. s0 + batch - 1), so where
+// a side is strided (adjacent sequences adjacent in memory) its element
+// loop runs across the batch and each element index moves as `batch`
+// contiguous entries.  Decimation in time after a bit-reversed load: the
+// radix-2 stages are taken two at a time (one radix-4 pass over LDS, the
+// same butterflies and table twiddles as the two stages), with a single
+// stage first when log2 n is odd, and the twiddle table of the length is
+// staged in LDS.  With total > 0 (first step of a four-step transform of
+// length total), output k of sequence s is multiplied by exp(2 pi i s k /
+// total).
 struct FftArgs {
-    float2* data;
+    const float2* src;
+    float2* dst;
     const float2* tw;       // exp(2 pi i k / n), k < n / 2
     int logn;
     long long stride, seq_dist, col_dist;
+    long long ostride, oseq_dist, ocol_dist;
     long long nseq;         // sequences per column (a multiple of batch)
     long long total;
     int batch;              // sequences per workgroup (power of two)
 };
 
-__global__ void __launch_bounds__(kNufftThreads) fft_lds(FftArgs a) {
-    extern __shared__ float2 x[];           // [batch][n]
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+    return make_float2(a.x - b.x, a.y - b.y);
+}
+
+__global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
+    extern __shared__ float2 lds_fft[];
     const int n = 1 << a.logn, B = a.batch;
+    float2* x = lds_fft;                        // [batch][n]
+    float2* tws = lds_fft + (size_t)B * n;      // [n / 2]
     const long long groups = a.nseq / B;
     const long long col = (long long)blockIdx.x / groups;
     const long long s0 = ((long long)blockIdx.x - col * groups) * B;
-    float2* base = a.data + col * a.col_dist + s0 * a.seq_dist;
-    // element e: contiguous sequences (stride 1) are read one after the
-    // other (e = b n + t), strided ones element by element across the
-    // batch (e = t B + b), so that consecutive threads read neighbours
-    const bool bmajor = a.stride == 1;
+    const float2* in = a.src + col * a.col_dist + s0 * a.seq_dist;
+    const bool bin = a.stride != 1;
     for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bmajor ? (e & (n - 1)) : e / B;
-        const int b = bmajor ? (e >> a.logn) : e - t * B;
+        const int t = bin ? e / B : (e & (n - 1));
+        const int b = bin ? e - t * B : (e >> a.logn);
         const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
-        x[b * n + rv] = base[(long long)t * a.stride + b * a.seq_dist];
+        x[b * n + rv] = in[(long long)t * a.stride + b * a.seq_dist];
     }
+    for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = a.tw[e];
     __syncthreads();
-    for (int lh = 0; lh < a.logn; ++lh) {
-        const int half = 1 << lh;
-        const int tstep = n >> (lh + 1);        // twiddle index step
+    int lh = 0;
+    if (a.logn & 1) {
+        // span-1 stage: consecutive pairs, twiddle 1
         for (int qq = threadIdx.x; qq < (n / 2) * B; qq += blockDim.x) {
-            const int b = qq >> (a.logn - 1), q = qq & (n / 2 - 1);
+            const float2 u = x[2 * qq], v = x[2 * qq + 1];
+            x[2 * qq] = cadd(u, v);
+            x[2 * qq + 1] = csub(u, v);
+        }
+        __syncthreads();
+        lh = 1;
+    }
+    for (; lh + 1 < a.logn; lh += 2) {
+        // stages lh (span half) and lh + 1 (span 2 half) on the four
+        // entries i0 + {0, 1, 2, 3} half
+        const int half = 1 << lh;
+        const int ts1 = n >> (lh + 1), ts2 = n >> (lh + 2);
+        for (int qq = threadIdx.x; qq < (n / 4) * B; qq += blockDim.x) {
+            const int b = qq >> (a.logn - 2), q = qq & (n / 4 - 1);
             const int grp = q >> lh, jj = q & (half - 1);
-            const int i0 = b * n + (grp << (lh + 1)) + jj, i1 = i0 + half;
-            const float2 w = a.tw[jj * tstep];
-            const float2 u = x[i0], v = cmul(x[i1], w);
-            x[i0] = make_float2(u.x + v.x, u.y + v.y);
-            x[i1] = make_float2(u.x - v.x, u.y - v.y);
+            const int i0 = b * n + (grp << (lh + 2)) + jj;
+            const int i1 = i0 + half, i2 = i1 + half, i3 = i2 + half;
+            const float2 w1 = tws[jj * ts1];
+            const float2 u0 = x[i0], v0 = cmul(x[i1], w1);
+            const float2 u1 = x[i2], v1 = cmul(x[i3], w1);
+            const float2 b0 = cadd(u0, v0), b1 = csub(u0, v0);
+            const float2 c2 = cmul(cadd(u1, v1), tws[jj * ts2]);
+            const float2 c3 = cmul(csub(u1, v1), tws[(jj + half) * ts2]);
+            x[i0] = cadd(b0, c2);
+            x[i2] = csub(b0, c2);
+            x[i1] = cadd(b1, c3);
+            x[i3] = csub(b1, c3);
         }
         __syncthreads();
     }
+    float2* out = a.dst + col * a.ocol_dist + s0 * a.oseq_dist;
+    const bool bout = a.ostride != 1;
     for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bmajor ? (e & (n - 1)) : e / B;
-        const int b = bmajor ? (e >> a.logn) : e - t * B;
+        const int t = bout ? e / B : (e & (n - 1));
+        const int b = bout ? e - t * B : (e >> a.logn);
         float2 y = x[b * n + t];
         if (a.total > 0) {
             // exp(2 pi i s t / total), the product reduced exactly first
@@ -248,7 +289,7 @@ __global__ void __launch_bounds__(kNufftThreads) fft_lds(FftArgs a) {
             sincospif(2.0f * (float)((double)p / (double)a.total), &sn, &cs);
             y = cmul(y, make_float2(cs, sn));
         }
-        base[(long long)t * a.stride + b * a.seq_dist] = y;
+        out[(long long)t * a.ostride + b * a.oseq_dist] = y;
     }
 }
 
@@ -269,9 +310,7 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_interp(NuArgs a) {
             gauss(a.tfrac[i * R], a.b4, w0);
 #pragma unroll
             for (int q = 0; q < 2 * kW; ++q) {
-                const int k = wrap(m0 - kW + 1 + q, a.Mr[0]);
-                // four-step output order: frequency k at (k % n1) n2 + k / n1
-                p0[q] = a.n1 ? (k & (a.n1 - 1)) * a.n2 + k / a.n1 : k;
+                p0[q] = wrap(m0 - kW + 1 + q, a.Mr[0]);
             }
         }
         if (R == 2) {
@@ -368,17 +407,19 @@ void nufft_free(NufftPlan* q) {
     delete q;
 }
 
+// The grid of nv vectors, twice over for a four-step transform (its second
+// step writes the spectrum to a buffer of its own, in natural order).
 size_t nufft_grid_bytes(const NufftPlan& q, int nv) {
-    return (size_t)nv * q.K * q.cells * sizeof(float2);
+    return (q.n1 ? 2 : 1) * (size_t)nv * q.K * q.cells * sizeof(float2);
 }
 
 // FP64 host planning (see the head of this file).
 std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
                         int K, const double* a, const double* b) {
-    // batched FFT workgroups take up to 64 KB of LDS
+    // batched FFT workgroups take up to kFftLds bytes of LDS
     (void)hipFuncSetAttribute((const void*)fft_lds,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                              65536);
+                              kFftLds);
     NufftPlan* q = new (std::nothrow) NufftPlan();
     if (!q) return "host allocation";
     const long long N = p.N;
@@ -403,7 +444,13 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
         h[d] = X > 0 ? std::min(1.0 / (4.0 * X), std::max(S, 1.0))
                      : std::max(S, 1.0);
         q->Mh[d] = (int)std::ceil(S / h[d]) + kW + 1;
-        const long long mr = std::max<long long>(16, next_pow2(4LL * q->Mh[d]));
+        // Mr >= 4 Mh, or half the power of two when that still keeps 4 Mh
+        // within 64/63 of it (the second gridding's oversampling then at
+        // least 1.97: its aliasing term at the highest mode goes from
+        // exp(-15.55) to at most exp(-15.30)); a grid of 4 (N/2 + kW + 1)
+        // cells otherwise doubles to the next power of two
+        long long mr = std::max<long long>(16, next_pow2(4LL * q->Mh[d]));
+        if (mr > 16 && 4LL * q->Mh[d] * 63 <= (mr / 2) * 64) mr /= 2;
         if (mr > (r == 1 ? (1LL << 24) : (long long)kFftMax)) {
             delete q;
             return "the lifted grid is too large (space-bandwidth product)";
@@ -600,43 +647,55 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
 
 size_t nufft_factor_bytes(const NufftPlan& q) { return q.arena_bytes; }
 
-static std::string launch_fft(const NufftPlan& q, float2* data, int ncols,
-                              hipStream_t st) {
-    auto run = [&](int logn, long long stride, long long seq_dist,
+// FFTs of every column of the grid; a four-step transform writes its
+// spectrum to out in natural order (elsewhere out = data).
+static std::string launch_fft(const NufftPlan& q, float2* data, float2* out,
+                              int ncols, hipStream_t st) {
+    auto run = [&](float2* src, float2* dst, int logn, long long stride,
+                   long long seq_dist, long long ostride, long long oseq_dist,
                    long long nseq, long long total) -> std::string {
-        // adjacent sequences (seq_dist 1) share a workgroup in batches of
-        // up to 8 within 64 KB of LDS, so their reads coalesce (batching
-        // contiguous sequences measured no faster)
+        // where one side is strided (adjacent sequences adjacent in
+        // memory), up to 16 sequences share a workgroup so that its reads
+        // or writes move as runs of contiguous entries (batching the
+        // contiguous side alone measured no faster)
+        const long long n = 1LL << logn;
         int batch = 1;
-        if (seq_dist == 1)
-            while (batch < 8 && ((long long)batch * 2 << logn) * 8 <= 65536 &&
+        if (seq_dist == 1 || oseq_dist == 1)
+            while (batch < 16 &&
+                   ((long long)batch * 2 * n + n / 2) * 8 <= kFftLds &&
                    nseq % (batch * 2) == 0)
                 batch *= 2;
-        FftArgs f{data, q.twiddles(logn), logn, stride, seq_dist, q.cells,
-                  nseq, total, batch};
+        FftArgs f{src, dst, q.twiddles(logn), logn, stride, seq_dist,
+                  q.cells, ostride, oseq_dist, q.cells, nseq, total, batch};
         if (!f.tw) return "missing FFT twiddles";
+        const size_t lds = ((size_t)batch * n + n / 2) * sizeof(float2);
+        if (lds > (size_t)kFftLds) return "FFT does not fit in LDS";
         const long long blocks = nseq / batch * ncols;
         if (blocks > 0x7fffffffLL) return "FFT grid too large";
         hipLaunchKernelGGL(fft_lds, dim3((unsigned)blocks),
-                           dim3(kNufftThreads),
-                           (size_t)batch * ((size_t)1 << logn) * sizeof(float2),
-                           st, f);
+                           dim3(kFftThreads), lds, st, f);
         return "";
     };
     std::string err;
     if (q.r == 1) {
         if (q.n1) {
-            // four-step: n1-point transforms over j1 (stride n2), twiddle,
-            // n2-point transforms over j2; frequency k1 + n1 k2 lands at
-            // k1 n2 + k2
-            err = run(ilog2i(q.n1), q.n2, 1, q.n2, q.Mr[0]);
-            if (err.empty()) err = run(ilog2i(q.n2), 1, q.n2, q.n1, 0);
+            // four-step over j = j1 n2 + j2: n1-point transforms over j1
+            // (stride n2) in place, twiddle exp(2 pi i j2 k1 / Mr), then
+            // n2-point transforms over j2 (contiguous rows k1); frequency
+            // k1 + n1 k2 is written to out at that index
+            err = run(data, data, ilog2i(q.n1), q.n2, 1, q.n2, 1, q.n2,
+                      q.Mr[0]);
+            if (err.empty())
+                err = run(data, out, ilog2i(q.n2), 1, q.n2, q.n1, 1, q.n1, 0);
         } else {
-            err = run(ilog2i(q.Mr[0]), 1, 0, 1, 0);
+            err = run(data, data, ilog2i(q.Mr[0]), 1, 0, 1, 0, 1, 0);
         }
     } else {
-        err = run(ilog2i(q.Mr[1]), 1, q.Mr[1], q.Mr[0], 0);      // rows
-        if (err.empty()) err = run(ilog2i(q.Mr[0]), q.Mr[1], 1, q.Mr[1], 0);
+        err = run(data, data, ilog2i(q.Mr[1]), 1, q.Mr[1], 1, q.Mr[1],
+                  q.Mr[0], 0);                                    // rows
+        if (err.empty())
+            err = run(data, data, ilog2i(q.Mr[0]), q.Mr[1], 1, q.Mr[1], 1,
+                      q.Mr[1], 0);                                // columns
     }
     return err;
 }
@@ -663,8 +722,6 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         }
         a.cells = q.cells;
         a.b4 = (float)(4.0 * q.b);
-        a.n1 = q.n1;
-        a.n2 = q.n2;
         a.sbase = q.sbase;
         a.sfrac = q.sfrac;
         a.pre = q.pre;
@@ -683,6 +740,8 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         a.grid = (float2*)ws;
         const long long ncols = (long long)nv * q.K;
         const long long gcells = ncols * q.cells;
+        // the spectrum: in place, or (four-step) the second half of ws
+        float2* const spec = q.n1 ? a.grid + gcells : a.grid;
         if (q.r == 2) {
             ProfScope ps(p, st);
             hipLaunchKernelGGL(nufft_zero, dim3(blocks_for_n(gcells)),
@@ -705,7 +764,7 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         }
         {
             ProfScope ps(p, st);
-            std::string err = launch_fft(q, a.grid, (int)ncols, st);
+            std::string err = launch_fft(q, a.grid, spec, (int)ncols, st);
             if (!err.empty()) return err;
             const double passes = q.r == 2 || q.n1 ? 2.0 : 1.0;
             ps.end("nufft_fft", 0.0,
@@ -714,6 +773,7 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         }
         {
             ProfScope ps(p, st);
+            a.grid = spec;
             const long long nt = q.N * nv;
             if (q.r == 1)
                 hipLaunchKernelGGL(nufft_interp<1>, dim3(blocks_for_n(nt)),
