@@ -172,6 +172,10 @@ def main():
     ap.add_argument("--switch-otf", action="store_true",
                     help="per-step MFMA form with the switch blocks "
                          "generated during the apply")
+    ap.add_argument("--twiddle-otf", action="store_true",
+                    help="per-step MFMA form with the twiddles evaluated "
+                         "during the apply (the plan stores none; with "
+                         "--switch-otf no factor is stored)")
     ap.add_argument("--op", default="N", choices=["N", "T", "C", "H"],
                     help="operator: K, K^T, conj(K) or K^H (bf_plan_op)")
     ap.add_argument("--lowrank-phase", type=int, default=0, metavar="RANK",
@@ -243,6 +247,10 @@ def main():
         # read at plan construction: the plan then stores no switch blocks
         os.environ["BF_FUSED"] = "0"
         os.environ["BF_SWITCH_OTF"] = "1"
+    if args.twiddle_otf:
+        # read at plan construction: the plan then stores no twiddles
+        os.environ["BF_FUSED"] = "0"
+        os.environ["BF_TWIDDLE_OTF"] = "1"
     phase = (w.phase_kind, w.phase_params)
     if args.lowrank_phase:
         from synthetic import lowrank_phase
@@ -253,8 +261,9 @@ def main():
     plan_s = time.perf_counter() - t0
     info = plan.info()
 
-    if args.switch_otf:
-        plan.set_config("per_step_mfma", switch_otf=True)
+    if args.switch_otf or args.twiddle_otf:
+        plan.set_config("per_step_mfma", switch_otf=args.switch_otf,
+                        twiddle_otf=args.twiddle_otf)
     tune = None
     if args.autotune:
         tune = plan.autotune(f, out=g, reps=2)
@@ -307,7 +316,12 @@ def main():
     else:
         peak_c, unit_c = BF16_PEAK_TFLOPS, "TFLOP/s"
     ridge = peak_c * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = traffic_from_profiles(args.workload, precision, name)
+    # the counters were taken on the workload's default form and batch
+    default_form = not (args.switch_otf or args.twiddle_otf or args.autotune
+                        or args.graph or args.op != "N" or args.lowrank_phase
+                        or args.nvec)
+    traffic = (traffic_from_profiles(args.workload, precision, name)
+               if default_form else None)
     if ai >= ridge:
         achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
         # the vector-ALU forms are the *_basic steps and the plain passes;
@@ -361,6 +375,7 @@ def main():
                                 peak_c),
         "roofline": roof,
         "exec": dict(plan.config(), graph=graph is not None),
+        "factor_bytes": info["factor_bytes"],
     }
     if tune is not None:
         out["autotune"] = tune

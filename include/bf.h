@@ -406,6 +406,15 @@ typedef struct bf_config {
                             (each half then split into equal passes; a
                             single level left over joins the pass before
                             it); 0 = as many as the LDS holds; 0..12   */
+    int twiddle_otf;     /* BF_PATH_PER_STEP_MFMA, FP32 only: 1 = evaluate
+                            each twiddle entry during the apply exactly as
+                            the plan stores it (FP64 phase reduced modulo
+                            1, FP64 sincospi, rounded to complex64)
+                            instead of reading it (Section 4: Algorithm
+                            4.1 applied without precomputed factors).  A
+                            plan built with the environment variable
+                            BF_TWIDDLE_OTF=1 (and BF_FUSED=0) stores no
+                            twiddles and runs only with twiddle_otf = 1  */
 } bf_config;
 
 /* Current execution form of the plan. */
@@ -426,7 +435,8 @@ int bf_set_config(bf_plan_t plan, const bf_config* cfg);
  * Candidates: BF_PATH_FUSED and BF_PATH_FUSED_VALU at tile widths r * 2^j
  * <= 16, BF_PATH_PER_STEP, and BF_PATH_PER_STEP_MFMA with stored and with
  * on-the-fly switch blocks (the stored blocks are built first if the plan
- * has none); out (capacity cap) receives one entry per
+ * has none), each also with twiddles evaluated in the apply; out (capacity
+ * cap) receives one entry per
  * candidate with its mean milliseconds per apply, -1 when the form cannot
  * run the plan, -2 when it resolves to kernels already timed; *count
  * receives the number of candidates.  Synchronous; allocates a temporary

@@ -342,23 +342,27 @@ class Plan:
 
     def config(self):
         """Execution form: {"path", "tile_cols", "tile_cols_used",
-        "switch_otf", "max_pass_levels"}."""
+        "switch_otf", "max_pass_levels", "twiddle_otf"}."""
         c = _lib.BfConfig()
         _lib.check(self._lib.bf_get_config(self._h, C.byref(c)))
         names = {v: k for k, v in PATHS.items()}
         return dict(path=names[c.path], tile_cols=c.tile_cols,
                     tile_cols_used=c.tile_cols_used,
                     switch_otf=bool(c.switch_otf),
-                    max_pass_levels=c.max_pass_levels)
+                    max_pass_levels=c.max_pass_levels,
+                    twiddle_otf=bool(c.twiddle_otf))
 
     def set_config(self, path="fused", tile_cols=0, switch_otf=False,
-                   max_pass_levels=0):
+                   max_pass_levels=0, twiddle_otf=False):
         """switch_otf (per_step_mfma only): generate the switch blocks
         during the apply instead of storing them.  max_pass_levels (fused
         forms): at most this many levels per pass, each half split into
-        equal passes (0: as many as the LDS holds)."""
+        equal passes (0: as many as the LDS holds).  twiddle_otf
+        (per_step_mfma, FP32): evaluate the twiddles during the apply, as
+        stored, instead of reading them."""
         c = _lib.BfConfig(PATHS[path], int(tile_cols), 0,
-                          1 if switch_otf else 0, int(max_pass_levels))
+                          1 if switch_otf else 0, int(max_pass_levels),
+                          1 if twiddle_otf else 0)
         _lib.check(self._lib.bf_set_config(self._h, C.byref(c)))
 
     def autotune(self, f, out=None, reps=3, stream=None):
@@ -376,7 +380,8 @@ class Plan:
         return [dict(path=names[e.config.path], tile_cols=e.config.tile_cols,
                      tile_cols_used=e.config.tile_cols_used,
                      switch_otf=bool(e.config.switch_otf),
-                     max_pass_levels=e.config.max_pass_levels, ms=e.ms)
+                     max_pass_levels=e.config.max_pass_levels,
+                     twiddle_otf=bool(e.config.twiddle_otf), ms=e.ms)
                 for e in arr[:min(cnt.value, cap)]]
 
     def graph(self, f, out=None):

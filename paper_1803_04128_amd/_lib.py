@@ -66,7 +66,7 @@ PATHS = {"fused": 0, "fused_valu": 1, "per_step": 2, "per_step_mfma": 3}
 class BfConfig(C.Structure):
     _fields_ = [("path", C.c_int), ("tile_cols", C.c_int),
                 ("tile_cols_used", C.c_int), ("switch_otf", C.c_int),
-                ("max_pass_levels", C.c_int)]
+                ("max_pass_levels", C.c_int), ("twiddle_otf", C.c_int)]
 
 
 class BfTuneEntry(C.Structure):

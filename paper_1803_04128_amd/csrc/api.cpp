@@ -75,6 +75,7 @@ void put_path(bfi::Plan& p, const bf_config& c) {
     p.tile_cols = c.tile_cols;
     p.switch_otf = c.switch_otf != 0;
     p.max_pass_levels = c.max_pass_levels;
+    p.twiddle_otf = c.twiddle_otf != 0;
 }
 
 // Validates cfg against the plan and makes it current; the default workspace
@@ -92,15 +93,18 @@ int apply_config(bfi::Plan& p, const bf_config& cfg) {
         return fail(BF_EINVAL, "bf_set_config: switch_otf must be 0 or 1");
     if (cfg.max_pass_levels < 0 || cfg.max_pass_levels > 12)
         return fail(BF_EINVAL, "bf_set_config: max_pass_levels must be 0..12");
+    if (cfg.twiddle_otf != 0 && cfg.twiddle_otf != 1)
+        return fail(BF_EINVAL, "bf_set_config: twiddle_otf must be 0 or 1");
     if (cfg.switch_otf && cfg.path != BF_PATH_PER_STEP_MFMA)
         return fail(BF_EUNSUPPORTED,
                     "bf_set_config: on-the-fly switch blocks exist in "
                     "BF_PATH_PER_STEP_MFMA only");
     const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
+    const bool w0 = p.twiddle_otf;
     const int t0 = p.tile_cols, d0 = p.max_pass_levels;
     auto restore = [&] {
         p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
-        p.max_pass_levels = d0;
+        p.max_pass_levels = d0, p.twiddle_otf = w0;
     };
     put_path(p, cfg);
     std::string err = bfi::check_config(p);
@@ -304,6 +308,12 @@ static int configure_plan(const bf_grid* grid, const bf_phase* phase,
     p.tile_cols = tenv ? std::max(0, std::atoi(tenv)) : 0;
     const char* oenv = std::getenv("BF_SWITCH_OTF");
     p.switch_otf = oenv && std::atoi(oenv) != 0 && !p.fused && p.mfma;
+    // a plan built for the per-step MFMA form that evaluates its twiddles
+    // in the apply stores none
+    const char* wenv = std::getenv("BF_TWIDDLE_OTF");
+    p.twiddle_otf = wenv && std::atoi(wenv) != 0 && !p.fused && p.mfma &&
+                    precision == BF_FP32;
+    p.tw_stored = !p.twiddle_otf;
     const char* senv = std::getenv("BF_SEP_SWITCH");
     p.sep_switch = !senv || std::atoi(senv) != 0;
     if (phase->kind == BF_PHASE_LOWRANK) p.phase.rank = phase->rank;
@@ -865,6 +875,7 @@ int bf_get_config(bf_plan_t plan, bf_config* cfg) {
         cfg->tile_cols_used =
             p.fused ? bfi::fused_tile_cols(p, p.chunk_nvec * p.r_amp) : 0;
         cfg->switch_otf = p.switch_otf ? 1 : 0;
+        cfg->twiddle_otf = p.twiddle_otf ? 1 : 0;
         cfg->max_pass_levels = p.max_pass_levels;
         return BF_OK;
     });
@@ -925,12 +936,17 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
         cand.push_back({BF_PATH_PER_STEP, 0, 0, 0, 0});
         cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0, 0});
         cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1, 0});
-        // the stored switch blocks are read by every candidate but one
+        // the forms that evaluate the twiddles in the apply (the only ones
+        // a plan built without stored twiddles runs)
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 0, 0, 1});
+        cand.push_back({BF_PATH_PER_STEP_MFMA, 0, 0, 1, 0, 1});
+        // the stored switch blocks are read by every candidate but two
         if (!p.S_arena && !bfi::build_switch_blocks(p).empty()) {
             (void)hipGetLastError();
             return fail(BF_ENOMEM, "bf_autotune: switch block storage");
         }
         const bool f0 = p.fused, m0 = p.mfma, o0 = p.switch_otf;
+        const bool w0 = p.twiddle_otf;
         const int t0 = p.tile_cols, d0 = p.max_pass_levels;
         std::vector<bf_tune_entry> res;
         // (form, tile width, passes) timed
@@ -950,8 +966,11 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
                 // fused form is then the vector-ALU one
                 const bool mf = p.fused && p.mfma && p.dim == 1 &&
                                 (p.r_amp & (p.r_amp - 1)) == 0 && p.r_amp <= 8;
-                const int key = !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) : 2)
-                                         : (mf ? 0 : 1);
+                const int key =
+                    !p.fused ? (p.mfma ? (p.switch_otf ? 4 : 3) +
+                                             (p.twiddle_otf ? 2 : 0)
+                                       : 2)
+                             : (mf ? 0 : 1);
                 const int np = p.fused ? bfi::fused_pass_count(
                                              p, std::min(nvec, p.chunk_nvec) *
                                                     p.r_amp)
@@ -1005,7 +1024,7 @@ int bf_autotune(bf_plan_t plan, int nvec, const void* f, void* g, int reps,
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         p.fused = f0, p.mfma = m0, p.tile_cols = t0, p.switch_otf = o0;
-        p.max_pass_levels = d0;
+        p.max_pass_levels = d0, p.twiddle_otf = w0;
         if (!err.empty()) {
             (void)hipGetLastError();
             return fail(BF_EHIP, "bf_autotune: " + err);

@@ -215,7 +215,8 @@ std::string run_basic(Plan& p, int nv, const float2* f, float2* g,
         const Step& s = p.steps[k];
         StepArgs a = make_step_args(p, s, Vc, f, cur, bufs[which]);
         const bool otf = p.mfma && p.switch_otf && s.kind == STEP_SWITCH;
-        double bytes = (s.reads_f ? head_bytes : 0.0) + s.tw_elems * 8.0 +
+        double bytes = (s.reads_f ? head_bytes : 0.0) +
+                       (p.twiddle_otf ? 0.0 : s.tw_elems * 8.0) +
                        (otf ? 0.0 : s.S_elems * 8.0) + s.mat_elems * 4.0;
         double sbytes = (s.reads_f ? 0.0 : N * s.r_in * c8) +
                         N * s.r_out * c8;

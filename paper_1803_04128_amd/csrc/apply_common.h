@@ -1,7 +1,7 @@
 // Launch arguments and the input gather shared by the apply kernels.
 #pragma once
 
-#include "bf_device.h"
+#include "factor_terms.h"
 
 namespace bfi {
 
@@ -26,7 +26,20 @@ struct StepArgs {
     int r_amp;
     int reads_f;
     int head_side;         // side of the boxes f is read over
+    TwArgs twa;            // the step's twiddle entries as functions of
+                           // their index (kernels that generate them)
 };
+
+// Twiddle entry idx of the step: read from the stored array, or (TWO)
+// evaluated in the apply exactly as the construction kernels store it.
+template <bool TWO>
+__device__ __forceinline__ float2 step_twiddle(const StepArgs& a, int kind,
+                                               long long idx) {
+    if constexpr (TWO)
+        return twiddle_entry(a.twa, kind, idx);
+    else
+        return a.tw[idx];
+}
 
 struct TailArgs {
     const float2* in;
@@ -84,6 +97,13 @@ inline StepArgs make_step_args(const Plan& p, const Step& s, int Vc,
     a.r_amp = p.r_amp;
     a.reads_f = s.reads_f ? 1 : 0;
     a.head_side = p.head_step_side;
+    a.twa.P = p.phase;
+    a.twa.L = p.L;
+    a.twa.ax_in = s.ax_in;
+    a.twa.ax_out = s.ax_out;
+    a.twa.level = s.level;
+    a.twa.reads_f = s.reads_f ? 1 : 0;
+    a.twa.writes_lambda = s.writes_lambda ? 1 : 0;
     return a;
 }
 

@@ -35,7 +35,7 @@ __device__ __forceinline__ floatx4 zero4() {
 // xi step (eq. (eqn:2) regrouped), block = (unit, 16-column tile); WPC waves
 // per output child i share its row tiles (wave h takes tiles h, h + WPC,
 // ...): D_i = sum_c M_c (W_{i,c} . X_c).
-template <int R, int WPC>
+template <int R, int WPC, bool TWO>
 __global__ void __launch_bounds__(R * 64 * WPC) xi_step_mfma(StepArgs a) {
     constexpr int NT = kMaxMT / WPC;                    // tiles per wave
     extern __shared__ float2 lds_step[];
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(R * 64 * WPC) xi_step_mfma(StepArgs a) {
     }
     const int ntw = R * R * a.r_in;
     for (int e = threadIdx.x; e < ntw; e += R * 64 * WPC)
-        ws[e] = a.tw[u * ntw + e];
+        ws[e] = step_twiddle<TWO>(a, STEP_XI, u * ntw + e);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = wave / WPC, h = wave - i * WPC;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(R * 64 * WPC) xi_step_mfma(StepArgs a) {
 // x step (eq. (eqn:3) regrouped), block = (unit, 16-column tile); WPC waves
 // per output child i share its row tiles (wave h takes tiles h, h + WPC,
 // ...): D_i = sum_c T_{i,c} . (M_i X_c).
-template <int R, int WPC>
+template <int R, int WPC, bool TWO>
 __global__ void __launch_bounds__(R * 64 * WPC) x_step_mfma(StepArgs a) {
     constexpr int NT = kMaxMT / WPC;                    // tiles per wave
     extern __shared__ float2 lds_step[];
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(R * 64 * WPC) x_step_mfma(StepArgs a) {
     }
     const int ntw = R * R * a.r_out;
     for (int e = threadIdx.x; e < ntw; e += R * 64 * WPC)
-        ts[e] = a.tw[u * ntw + e];
+        ts[e] = step_twiddle<TWO>(a, STEP_X, u * ntw + e);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = wave / WPC, h = wave - i * WPC;
@@ -437,8 +437,14 @@ size_t step_mfma_lds(const Plan& p, const Step& s) {
 void init_step_mfma_attrs() {
     static bool done = false;
     if (done) return;
-    const void* fns[] = {(const void*)xi_step_mfma<2, 1>, (const void*)xi_step_mfma<4, 2>,
-                         (const void*)x_step_mfma<2, 1>, (const void*)x_step_mfma<4, 2>,
+    const void* fns[] = {(const void*)xi_step_mfma<2, 1, false>,
+                         (const void*)xi_step_mfma<4, 2, false>,
+                         (const void*)x_step_mfma<2, 1, false>,
+                         (const void*)x_step_mfma<4, 2, false>,
+                         (const void*)xi_step_mfma<2, 1, true>,
+                         (const void*)xi_step_mfma<4, 2, true>,
+                         (const void*)x_step_mfma<2, 1, true>,
+                         (const void*)x_step_mfma<4, 2, true>,
                          (const void*)switch_step_mfma,
                          (const void*)switch_otf_mfma<BF_PHASE_DFT>,
                          (const void*)switch_otf_mfma<BF_PHASE_FIO1D>,
@@ -513,19 +519,35 @@ std::string launch_step_mfma(const Plan& p, const Step& s, const StepArgs& a,
     } else {
         const long long nb = s.units * nct;
         if (nb > 0x7fffffffLL) return "step grid too large";
-        if (p.R == 2) {
-            if (s.kind == STEP_XI)
-                hipLaunchKernelGGL((xi_step_mfma<2, 1>), dim3((unsigned)nb),
+        const dim3 grid((unsigned)nb);
+        const bool xi = s.kind == STEP_XI;
+        if (p.R == 2 && p.twiddle_otf) {
+            if (xi)
+                hipLaunchKernelGGL((xi_step_mfma<2, 1, true>), grid, dim3(128),
+                                   lds, st, a);
+            else
+                hipLaunchKernelGGL((x_step_mfma<2, 1, true>), grid, dim3(128),
+                                   lds, st, a);
+        } else if (p.R == 2) {
+            if (xi)
+                hipLaunchKernelGGL((xi_step_mfma<2, 1, false>), grid,
                                    dim3(128), lds, st, a);
             else
-                hipLaunchKernelGGL((x_step_mfma<2, 1>), dim3((unsigned)nb),
+                hipLaunchKernelGGL((x_step_mfma<2, 1, false>), grid,
                                    dim3(128), lds, st, a);
+        } else if (p.twiddle_otf) {
+            if (xi)
+                hipLaunchKernelGGL((xi_step_mfma<4, 2, true>), grid, dim3(512),
+                                   lds, st, a);
+            else
+                hipLaunchKernelGGL((x_step_mfma<4, 2, true>), grid, dim3(512),
+                                   lds, st, a);
         } else {
-            if (s.kind == STEP_XI)
-                hipLaunchKernelGGL((xi_step_mfma<4, 2>), dim3((unsigned)nb),
+            if (xi)
+                hipLaunchKernelGGL((xi_step_mfma<4, 2, false>), grid,
                                    dim3(512), lds, st, a);
             else
-                hipLaunchKernelGGL((x_step_mfma<4, 2>), dim3((unsigned)nb),
+                hipLaunchKernelGGL((x_step_mfma<4, 2, false>), grid,
                                    dim3(512), lds, st, a);
         }
     }

@@ -69,7 +69,7 @@ constexpr int kSepPreT = 2;      // twiddles per thread: 16 r <= 1024
 // behind the level, one unit per block).
 enum { kSepPlain = 0, kSepHead = 1, kSepSwitch = 2 };
 
-template <int MODE>
+template <int MODE, bool TWO>
 __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
                                                               SwFuse sw) {
     constexpr bool SW = MODE == kSepSwitch;
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
 #pragma unroll
         for (int m = 0; m < kSepPreT; ++m) {
             const int e = threadIdx.x + m * nthr;
-            if (e < nw) pw[m] = a.tw[uu * nw + e];
+            if (e < nw) pw[m] = step_twiddle<TWO>(a, STEP_XI, uu * nw + e);
         }
     };
     auto put = [&]() {
@@ -173,7 +173,8 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
                 ++c;
             }
         }
-        for (int e = threadIdx.x; e < nw; e += nthr) ws[e] = a.tw[u0 * nw + e];
+        for (int e = threadIdx.x; e < nw; e += nthr)
+            ws[e] = step_twiddle<TWO>(a, STEP_XI, u0 * nw + e);
     } else {
         issue(u0);
         put();
@@ -333,6 +334,7 @@ __global__ void __launch_bounds__(kSepWaves * 64) xi_step_sep(StepArgs a,
 
 // x step, block = (kSepUnits consecutive units, 16-column tile).  LDS: X
 // [4][r_in][16], T [4][4][r_out], Z [4][2][a][b][16].
+template <bool TWO>
 __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
     extern __shared__ float2 lds_step[];
     const int A1 = a.a1, B1 = a.b1;
@@ -369,7 +371,7 @@ __global__ void __launch_bounds__(kSepWaves * 64) x_step_sep(StepArgs a) {
 #pragma unroll
         for (int m = 0; m < kSepPreT; ++m) {
             const int e = threadIdx.x + m * nthr;
-            if (e < nt) pt[m] = a.tw[uu * nt + e];
+            if (e < nt) pt[m] = step_twiddle<TWO>(a, STEP_X, uu * nt + e);
         }
     };
     auto put = [&]() {
@@ -522,10 +524,14 @@ bool step_sep_ok(const Plan& p, const Step& s) {
 }
 
 void init_step_sep_attrs() {
-    const void* fns[] = {(const void*)xi_step_sep<kSepPlain>,
-                         (const void*)xi_step_sep<kSepHead>,
-                         (const void*)xi_step_sep<kSepSwitch>,
-                         (const void*)x_step_sep};
+    const void* fns[] = {(const void*)xi_step_sep<kSepPlain, false>,
+                         (const void*)xi_step_sep<kSepHead, false>,
+                         (const void*)xi_step_sep<kSepSwitch, false>,
+                         (const void*)x_step_sep<false>,
+                         (const void*)xi_step_sep<kSepPlain, true>,
+                         (const void*)xi_step_sep<kSepHead, true>,
+                         (const void*)xi_step_sep<kSepSwitch, true>,
+                         (const void*)x_step_sep<true>};
     for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
@@ -533,7 +539,6 @@ void init_step_sep_attrs() {
 
 std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
                             hipStream_t st) {
-    (void)p;
     const long long nct = (a.Vc + kCols - 1) / kCols;
     const int upb = s.kind == STEP_XI && s.reads_f ? 1 : kSepUnits;
     const long long groups = (s.units + upb - 1) / upb;
@@ -544,16 +549,26 @@ std::string launch_step_sep(const Plan& p, const Step& s, StepArgs a,
     a.a1 = s.ax_in.r1;
     a.b1 = s.ax_out.r1;
     a.amat_sep = s.amat_sep;
-    if (s.kind == STEP_XI)
-        if (s.reads_f)
-            hipLaunchKernelGGL(xi_step_sep<kSepHead>, dim3((unsigned)nb),
-                               dim3(kSepWaves * 64), lds, st, a, SwFuse{});
+    const dim3 grid((unsigned)nb), block(kSepWaves * 64);
+    if (p.twiddle_otf) {
+        if (s.kind == STEP_XI && s.reads_f)
+            hipLaunchKernelGGL((xi_step_sep<kSepHead, true>), grid, block, lds,
+                               st, a, SwFuse{});
+        else if (s.kind == STEP_XI)
+            hipLaunchKernelGGL((xi_step_sep<kSepPlain, true>), grid, block,
+                               lds, st, a, SwFuse{});
         else
-            hipLaunchKernelGGL(xi_step_sep<kSepPlain>, dim3((unsigned)nb),
-                               dim3(kSepWaves * 64), lds, st, a, SwFuse{});
-    else
-        hipLaunchKernelGGL(x_step_sep, dim3((unsigned)nb),
-                           dim3(kSepWaves * 64), lds, st, a);
+            hipLaunchKernelGGL((x_step_sep<true>), grid, block, lds, st, a);
+    } else {
+        if (s.kind == STEP_XI && s.reads_f)
+            hipLaunchKernelGGL((xi_step_sep<kSepHead, false>), grid, block,
+                               lds, st, a, SwFuse{});
+        else if (s.kind == STEP_XI)
+            hipLaunchKernelGGL((xi_step_sep<kSepPlain, false>), grid, block,
+                               lds, st, a, SwFuse{});
+        else
+            hipLaunchKernelGGL((x_step_sep<false>), grid, block, lds, st, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
     return "";
@@ -573,8 +588,12 @@ std::string launch_sep_switch(const Plan& p, const Step& xi, const Step& sw,
     a.a1 = xi.ax_in.r1;
     a.b1 = xi.ax_out.r1;
     a.amat_sep = xi.amat_sep;
-    hipLaunchKernelGGL(xi_step_sep<kSepSwitch>, dim3((unsigned)nb),
-                       dim3(kSepWaves * 64), lds, st, a, f);
+    if (p.twiddle_otf)
+        hipLaunchKernelGGL((xi_step_sep<kSepSwitch, true>), dim3((unsigned)nb),
+                           dim3(kSepWaves * 64), lds, st, a, f);
+    else
+        hipLaunchKernelGGL((xi_step_sep<kSepSwitch, false>), dim3((unsigned)nb),
+                           dim3(kSepWaves * 64), lds, st, a, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return std::string("step launch: ") + hipGetErrorString(e);
     return "";

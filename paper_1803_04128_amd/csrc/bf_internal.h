@@ -168,6 +168,10 @@ struct Plan {
     // per-step MFMA form: generate the switch blocks during the apply
     // instead of reading the stored S
     bool switch_otf = false;
+    // per-step MFMA form: evaluate the twiddles during the apply instead of
+    // reading them; a plan built for that form (BF_TWIDDLE_OTF) stores none
+    bool twiddle_otf = false;
+    bool tw_stored = true;
     // 2D per-step MFMA form: the switch fused behind the last xi level
     // (BF_SEP_SWITCH=0 at plan time keeps them separate launches)
     bool sep_switch = true;

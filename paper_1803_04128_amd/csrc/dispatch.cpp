@@ -137,6 +137,12 @@ std::string split_form_error(const Plan& p) {
 
 std::string check_config(Plan& p) {
     if (p.nufft) return "";
+    if (p.twiddle_otf && (p.fused || !p.mfma || p.precision != BF_FP32))
+        return "twiddles are evaluated in the apply by the FP32 per-step "
+               "MFMA form only";
+    if (!p.tw_stored && !p.twiddle_otf)
+        return "the plan stores no twiddles (built with BF_TWIDDLE_OTF): "
+               "only the form that evaluates them runs it";
     {
         std::string why = split_form_error(p);
         if (!why.empty()) return why;

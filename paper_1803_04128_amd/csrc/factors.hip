@@ -15,17 +15,9 @@
 
 #include <hip/hip_fp16.h>
 
-#include "bf_device.h"
+#include "factor_terms.h"
 
 namespace bfi {
-
-struct TwArgs {
-    PhaseSpec P;
-    Axis ax_in, ax_out;
-    int L, level, reads_f, writes_lambda;
-    long long total;
-    float2* out;
-};
 
 constexpr int kFactorBlock = 256;
 
@@ -78,113 +70,6 @@ __device__ __forceinline__ float2 join_split(float2 raw, int split) {
                            __uint_as_float((unsigned)q.y << 16),
                        __uint_as_float((unsigned)q.z << 16) +
                            __uint_as_float((unsigned)q.w << 16));
-}
-
-// The phase terms of one stored factor entry: the entry is
-// exp(2 pi i [Phi(ix_0, jx_0) - Phi(ix_1, jx_1) - Phi(ix_2, jx_2)]) over the
-// first `count` terms (grid coordinates; ix on the output tree, jx on the
-// input tree, as phase_value takes them).  The construction kernels and the
-// diagnostic read-back (factor_entries) decode entries with these functions.
-struct Terms {
-    int count;
-    int ix[3][2];
-    int jx[3][2];
-};
-
-// W (or D+ when the step reads f): [u][i][c][s]
-__device__ __forceinline__ Terms xi_terms(const TwArgs& a, long long idx) {
-    const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
-    const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
-    const int shiftB = dim * (a.L - a.level);
-    int s = (int)(idx % r_in);
-    long long rest = idx / r_in;
-    int c = (int)(rest % R);
-    rest /= R;
-    int i = (int)(rest % R);
-    long long u = rest / R;
-    long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
-    int Ac[2], Pc[2], Cc[2];
-    Terms T;
-    box_coords(ap * R + i, dim, Ac);
-    box_coords(ap, dim, Pc);
-    box_coords(b * R + c, dim, Cc);
-    point_grid(Cc, a.ax_in, s, dim, T.jx[0]);
-    center_grid(Ac, n >> a.level, dim, T.ix[0]);
-    T.count = 1;
-    if (!a.reads_f) {
-        center_grid(Pc, n >> (a.level - 1), dim, T.ix[1]);
-        for (int d = 0; d < dim; ++d) T.jx[1][d] = T.jx[0][d];
-        T.count = 2;
-    }
-    return T;
-}
-
-// T (or E+ on the last x step): [u][i][c][t]
-__device__ __forceinline__ Terms x_terms(const TwArgs& a, long long idx) {
-    const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
-    const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
-    const int shiftB = dim * (a.L - a.level);
-    int t = (int)(idx % r_out);
-    long long rest = idx / r_out;
-    int c = (int)(rest % R);
-    rest /= R;
-    int i = (int)(rest % R);
-    long long u = rest / R;
-    long long ap = u >> shiftB, b = u & ((1LL << shiftB) - 1);
-    int Ac[2], Bc[2], Cc[2];
-    Terms T;
-    box_coords(ap * R + i, dim, Ac);
-    box_coords(b, dim, Bc);
-    box_coords(b * R + c, dim, Cc);
-    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
-    center_grid(Cc, n >> (a.L - a.level + 1), dim, T.jx[0]);
-    T.count = 1;
-    if (!a.writes_lambda) {
-        for (int d = 0; d < dim; ++d) T.ix[1][d] = T.ix[0][d];
-        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[1]);
-        T.count = 2;
-    }
-    return T;
-}
-
-// S: [p][t][s]
-__device__ __forceinline__ Terms switch_terms(const TwArgs& a,
-                                              long long idx) {
-    const int dim = a.P.dim, n = a.P.n;
-    const int r_in = a.ax_in.r1 * (dim == 2 ? a.ax_in.r1 : 1);
-    const int r_out = a.ax_out.r1 * (dim == 2 ? a.ax_out.r1 : 1);
-    const int shiftB = dim * (a.L - a.level);
-    int s = (int)(idx % r_in);
-    long long rest = idx / r_in;
-    int t = (int)(rest % r_out);
-    long long p = rest / r_out;
-    long long am = p >> shiftB, bm = p & ((1LL << shiftB) - 1);
-    int Ac[2], Bc[2];
-    Terms T;
-    box_coords(am, dim, Ac);
-    box_coords(bm, dim, Bc);
-    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
-    point_grid(Bc, a.ax_in, s, dim, T.jx[0]);
-    T.count = 1;
-    if (!a.reads_f) {
-        center_grid(Ac, n >> a.level, dim, T.ix[T.count]);
-        for (int d = 0; d < dim; ++d) T.jx[T.count][d] = T.jx[0][d];
-        ++T.count;
-    }
-    if (!a.writes_lambda) {
-        for (int d = 0; d < dim; ++d) T.ix[T.count][d] = T.ix[0][d];
-        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[T.count]);
-        ++T.count;
-    }
-    return T;
-}
-
-// The entry's phase: FP64 terms, differences before the reduction modulo 1.
-__device__ __forceinline__ double terms_phase(const PhaseSpec& P,
-                                              const Terms& T) {
-    double v = phase_value(P, T.ix[0], T.jx[0]);
-    for (int k = 1; k < T.count; ++k) v -= phase_value(P, T.ix[k], T.jx[k]);
-    return v;
 }
 
 __global__ void xi_twiddles(TwArgs a) {
@@ -342,7 +227,7 @@ static ArenaLayout arena_layout(Plan& p) {
         off_ax.push_back(bytes);
         bytes = align_up(bytes + s.amat_xi_elems * sizeof(float));
         off_tw.push_back(bytes);
-        bytes = align_up(bytes + s.tw_elems * sizeof(float2));
+        if (p.tw_stored) bytes = align_up(bytes + s.tw_elems * sizeof(float2));
         off_m.push_back(bytes);
         bytes = align_up(bytes + s.mat_elems * sizeof(float));
         // split precisions: the arranged FP32 table, then its hi and lo parts
@@ -400,7 +285,8 @@ std::string build_factors(Plan& p) {
     t.L = p.L;
     for (size_t k = 0; k < p.steps.size(); ++k) {
         Step& s = p.steps[k];
-        s.tw = s.tw_elems ? (float2*)(base + off_tw[k]) : nullptr;
+        s.tw = s.tw_elems && p.tw_stored ? (float2*)(base + off_tw[k])
+                                         : nullptr;
         s.S = nullptr;   // build_switch_blocks
         s.mats = s.mat_elems ? (float*)(base + off_m[k]) : nullptr;
         s.amat = s.amat_elems ? (float*)(base + off_am[k]) : nullptr;
@@ -414,8 +300,9 @@ std::string build_factors(Plan& p) {
         t.level = s.level;
         t.reads_f = s.reads_f;
         t.writes_lambda = s.writes_lambda;
-        if (s.kind == STEP_SWITCH) {
-            // stored switch blocks are built by build_switch_blocks
+        if (s.kind == STEP_SWITCH || !s.tw) {
+            // stored switch blocks are built by build_switch_blocks; a plan
+            // built without stored twiddles evaluates them in the apply
         } else if (s.kind == STEP_XI) {
             t.total = (long long)s.tw_elems;
             t.out = s.tw;

@@ -109,7 +109,7 @@ def test_otf_plan_stores_no_switch_blocks_until_needed(monkeypatch):
         assert ei.value.code == bfm._lib.BF_EUNSUPPORTED
         assert pl.config() == dict(path="per_step_mfma", tile_cols=0,
                                    tile_cols_used=0, switch_otf=False,
-                                   max_pass_levels=0)
+                                   max_pass_levels=0, twiddle_otf=False)
 
 
 def test_otf_fused_env_is_ignored(monkeypatch):
@@ -134,7 +134,7 @@ def test_otf_autotune_candidate_and_graph():
         res = pl.autotune(ft, reps=2)
         for e in res:
             log("  ", e)
-        otf = [e for e in res if e["switch_otf"]]
+        otf = [e for e in res if e["switch_otf"] and not e["twiddle_otf"]]
         assert len(otf) == 1 and otf[0]["ms"] > 0
         pl.set_config("per_step_mfma", switch_otf=True)
         eager = pl.apply(ft)
