@@ -30,6 +30,30 @@ struct Terms {
     int jx[3][2];
 };
 
+// point_grid / center_grid with the dimension loop at a fixed trip count,
+// so that the term arrays stay in registers (a loop over the run-time
+// dimension indexes them dynamically, which puts them in scratch memory)
+__device__ __forceinline__ void term_point(const int* bc, const Axis& ax,
+                                           int t, int dim, int* g) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+        if (d < dim)
+            g[d] = bc[d] * ax.side + ax.off[point_digit(t, ax.r1, dim, d)];
+}
+
+__device__ __forceinline__ void term_center(const int* bc, int side, int dim,
+                                            int* g) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+        if (d < dim) g[d] = bc[d] * side + (side - 1) / 2;
+}
+
+__device__ __forceinline__ void term_copy(const int* from, int dim, int* to) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+        if (d < dim) to[d] = from[d];
+}
+
 // W (or D+ when the step reads f): [u][i][c][s]
 __device__ __forceinline__ Terms xi_terms(const TwArgs& a, long long idx) {
     const int dim = a.P.dim, R = 1 << dim, n = a.P.n;
@@ -47,12 +71,12 @@ __device__ __forceinline__ Terms xi_terms(const TwArgs& a, long long idx) {
     box_coords(ap * R + i, dim, Ac);
     box_coords(ap, dim, Pc);
     box_coords(b * R + c, dim, Cc);
-    point_grid(Cc, a.ax_in, s, dim, T.jx[0]);
-    center_grid(Ac, n >> a.level, dim, T.ix[0]);
+    term_point(Cc, a.ax_in, s, dim, T.jx[0]);
+    term_center(Ac, n >> a.level, dim, T.ix[0]);
     T.count = 1;
     if (!a.reads_f) {
-        center_grid(Pc, n >> (a.level - 1), dim, T.ix[1]);
-        for (int d = 0; d < dim; ++d) T.jx[1][d] = T.jx[0][d];
+        term_center(Pc, n >> (a.level - 1), dim, T.ix[1]);
+        term_copy(T.jx[0], dim, T.jx[1]);
         T.count = 2;
     }
     return T;
@@ -75,12 +99,12 @@ __device__ __forceinline__ Terms x_terms(const TwArgs& a, long long idx) {
     box_coords(ap * R + i, dim, Ac);
     box_coords(b, dim, Bc);
     box_coords(b * R + c, dim, Cc);
-    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
-    center_grid(Cc, n >> (a.L - a.level + 1), dim, T.jx[0]);
+    term_point(Ac, a.ax_out, t, dim, T.ix[0]);
+    term_center(Cc, n >> (a.L - a.level + 1), dim, T.jx[0]);
     T.count = 1;
     if (!a.writes_lambda) {
-        for (int d = 0; d < dim; ++d) T.ix[1][d] = T.ix[0][d];
-        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[1]);
+        term_copy(T.ix[0], dim, T.ix[1]);
+        term_center(Bc, n >> (a.L - a.level), dim, T.jx[1]);
         T.count = 2;
     }
     return T;
@@ -102,17 +126,24 @@ __device__ __forceinline__ Terms switch_terms(const TwArgs& a,
     Terms T;
     box_coords(am, dim, Ac);
     box_coords(bm, dim, Bc);
-    point_grid(Ac, a.ax_out, t, dim, T.ix[0]);
-    point_grid(Bc, a.ax_in, s, dim, T.jx[0]);
+    term_point(Ac, a.ax_out, t, dim, T.ix[0]);
+    term_point(Bc, a.ax_in, s, dim, T.jx[0]);
+    // the terms present: 0, then 1 unless the step reads f, then 2 unless
+    // it writes lambda; slot k holds the k-th present term
     T.count = 1;
     if (!a.reads_f) {
-        center_grid(Ac, n >> a.level, dim, T.ix[T.count]);
-        for (int d = 0; d < dim; ++d) T.jx[T.count][d] = T.jx[0][d];
-        ++T.count;
+        term_center(Ac, n >> a.level, dim, T.ix[1]);
+        term_copy(T.jx[0], dim, T.jx[1]);
+        T.count = 2;
     }
     if (!a.writes_lambda) {
-        for (int d = 0; d < dim; ++d) T.ix[T.count][d] = T.ix[0][d];
-        center_grid(Bc, n >> (a.L - a.level), dim, T.jx[T.count]);
+        if (T.count == 1) {
+            term_copy(T.ix[0], dim, T.ix[1]);
+            term_center(Bc, n >> (a.L - a.level), dim, T.jx[1]);
+        } else {
+            term_copy(T.ix[0], dim, T.ix[2]);
+            term_center(Bc, n >> (a.L - a.level), dim, T.jx[2]);
+        }
         ++T.count;
     }
     return T;
@@ -122,7 +153,9 @@ __device__ __forceinline__ Terms switch_terms(const TwArgs& a,
 __device__ __forceinline__ double terms_phase(const PhaseSpec& P,
                                               const Terms& T) {
     double v = phase_value(P, T.ix[0], T.jx[0]);
-    for (int k = 1; k < T.count; ++k) v -= phase_value(P, T.ix[k], T.jx[k]);
+#pragma unroll
+    for (int k = 1; k < 3; ++k)
+        if (k < T.count) v -= phase_value(P, T.ix[k], T.jx[k]);
     return v;
 }
 
