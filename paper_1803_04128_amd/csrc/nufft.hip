@@ -201,9 +201,12 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
 // radix-2 stages are taken two at a time (one radix-4 pass over LDS, the
 // same butterflies and table twiddles as the two stages), with a single
 // stage first when log2 n is odd, and the twiddle table of the length is
-// staged in LDS.  With total > 0 (first step of a four-step transform of
-// length total), output k of sequence s is multiplied by exp(2 pi i s k /
-// total).
+// staged in LDS.  In LDS, entry i of sequence b sits at b P + i + i / 16
+// (P = fft_pitch(n)): one pad entry every 16 entries and one more per
+// sequence spread the bit-reversed stores, the batch-fastest element loops
+// and the short butterfly spans over the banks.  With total > 0 (first step
+// of a four-step transform of length total, a power of two), output k of
+// sequence s is multiplied by exp(2 pi i s k / total).
 struct FftArgs {
     const float2* src;
     float2* dst;
@@ -213,8 +216,19 @@ struct FftArgs {
     long long ostride, oseq_dist, ocol_dist;
     long long nseq;         // sequences per column (a multiple of batch)
     long long total;
+    float tscale;           // 2 / total (exact), 0 without the twiddle
     int batch;              // sequences per workgroup (power of two)
+    int logb;               // log2 batch
 };
+
+// LDS entries per sequence of an n-point FFT workgroup (see above).
+__host__ __device__ constexpr long long fft_pitch(long long n) {
+    return n + n / 16 + 1;
+}
+
+__device__ __forceinline__ int fft_ix(int b, int P, int i) {
+    return b * P + i + (i >> 4);
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) {
     return make_float2(a.x + b.x, a.y + b.y);
@@ -227,18 +241,19 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) {
 __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
     extern __shared__ float2 lds_fft[];
     const int n = 1 << a.logn, B = a.batch;
-    float2* x = lds_fft;                        // [batch][n]
-    float2* tws = lds_fft + (size_t)B * n;      // [n / 2]
+    const int P = (int)fft_pitch(n);
+    float2* x = lds_fft;                        // [batch][P]
+    float2* tws = lds_fft + (size_t)B * P;      // [n / 2]
     const long long groups = a.nseq / B;
     const long long col = (long long)blockIdx.x / groups;
     const long long s0 = ((long long)blockIdx.x - col * groups) * B;
     const float2* in = a.src + col * a.col_dist + s0 * a.seq_dist;
     const bool bin = a.stride != 1;
     for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bin ? e / B : (e & (n - 1));
-        const int b = bin ? e - t * B : (e >> a.logn);
+        const int t = bin ? e >> a.logb : (e & (n - 1));
+        const int b = bin ? e & (B - 1) : (e >> a.logn);
         const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
-        x[b * n + rv] = in[(long long)t * a.stride + b * a.seq_dist];
+        x[fft_ix(b, P, rv)] = in[(long long)t * a.stride + b * a.seq_dist];
     }
     for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = a.tw[e];
     __syncthreads();
@@ -246,9 +261,11 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
     if (a.logn & 1) {
         // span-1 stage: consecutive pairs, twiddle 1
         for (int qq = threadIdx.x; qq < (n / 2) * B; qq += blockDim.x) {
-            const float2 u = x[2 * qq], v = x[2 * qq + 1];
-            x[2 * qq] = cadd(u, v);
-            x[2 * qq + 1] = csub(u, v);
+            const int b = qq >> (a.logn - 1), j = 2 * (qq & (n / 2 - 1));
+            const int i0 = fft_ix(b, P, j);     // j even: i0 + 1 is j + 1
+            const float2 u = x[i0], v = x[i0 + 1];
+            x[i0] = cadd(u, v);
+            x[i0 + 1] = csub(u, v);
         }
         __syncthreads();
         lh = 1;
@@ -261,8 +278,10 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
         for (int qq = threadIdx.x; qq < (n / 4) * B; qq += blockDim.x) {
             const int b = qq >> (a.logn - 2), q = qq & (n / 4 - 1);
             const int grp = q >> lh, jj = q & (half - 1);
-            const int i0 = b * n + (grp << (lh + 2)) + jj;
-            const int i1 = i0 + half, i2 = i1 + half, i3 = i2 + half;
+            const int j0 = (grp << (lh + 2)) + jj;
+            const int i0 = fft_ix(b, P, j0), i1 = fft_ix(b, P, j0 + half);
+            const int i2 = fft_ix(b, P, j0 + 2 * half);
+            const int i3 = fft_ix(b, P, j0 + 3 * half);
             const float2 w1 = tws[jj * ts1];
             const float2 u0 = x[i0], v0 = cmul(x[i1], w1);
             const float2 u1 = x[i2], v1 = cmul(x[i3], w1);
@@ -279,14 +298,15 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
     float2* out = a.dst + col * a.ocol_dist + s0 * a.oseq_dist;
     const bool bout = a.ostride != 1;
     for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bout ? e / B : (e & (n - 1));
-        const int b = bout ? e - t * B : (e >> a.logn);
-        float2 y = x[b * n + t];
+        const int t = bout ? e >> a.logb : (e & (n - 1));
+        const int b = bout ? e & (B - 1) : (e >> a.logn);
+        float2 y = x[fft_ix(b, P, t)];
         if (a.total > 0) {
-            // exp(2 pi i s t / total), the product reduced exactly first
+            // exp(2 pi i s t / total), the product reduced exactly first;
+            // p < total <= 2^24, so 2 p / total is exact in FP32
             const long long p = ((s0 + b) * t) & (a.total - 1);
             float sn, cs;
-            sincospif(2.0f * (float)((double)p / (double)a.total), &sn, &cs);
+            sincospif((float)p * a.tscale, &sn, &cs);
             y = cmul(y, make_float2(cs, sn));
         }
         out[(long long)t * a.ostride + b * a.oseq_dist] = y;
@@ -658,17 +678,22 @@ static std::string launch_fft(const NufftPlan& q, float2* data, float2* out,
         // memory), up to 16 sequences share a workgroup so that its reads
         // or writes move as runs of contiguous entries (batching the
         // contiguous side alone measured no faster)
-        const long long n = 1LL << logn;
-        int batch = 1;
+        const long long n = 1LL << logn, P = fft_pitch(n);
+        int batch = 1, logb = 0;
         if (seq_dist == 1 || oseq_dist == 1)
             while (batch < 16 &&
-                   ((long long)batch * 2 * n + n / 2) * 8 <= kFftLds &&
-                   nseq % (batch * 2) == 0)
+                   ((long long)batch * 2 * P + n / 2) * 8 <= kFftLds &&
+                   nseq % (batch * 2) == 0) {
                 batch *= 2;
+                ++logb;
+            }
+        const float tscale =
+            total > 0 ? (float)std::ldexp(1.0, 1 - ilog2i(total)) : 0.f;
         FftArgs f{src, dst, q.twiddles(logn), logn, stride, seq_dist,
-                  q.cells, ostride, oseq_dist, q.cells, nseq, total, batch};
+                  q.cells, ostride, oseq_dist, q.cells, nseq, total,
+                  tscale, batch, logb};
         if (!f.tw) return "missing FFT twiddles";
-        const size_t lds = ((size_t)batch * n + n / 2) * sizeof(float2);
+        const size_t lds = ((size_t)batch * P + n / 2) * sizeof(float2);
         if (lds > (size_t)kFftLds) return "FFT does not fit in LDS";
         const long long blocks = nseq / batch * ncols;
         if (blocks > 0x7fffffffLL) return "FFT grid too large";
