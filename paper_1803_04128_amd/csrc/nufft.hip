@@ -61,7 +61,8 @@ struct NuArgs {
     const int* cidx;
     const float* cwt;
     const float2* a;
-    const float2* b;
+    const float2* b;                  // 2D: [K][N]; 1D: [N][Kp] (below)
+    int kp;                           // 1D: terms per source row of b
     const float2* f;                  // [nv][N] chunk
     float2* g;
     float2* grid;                     // [nv * K][cells]
@@ -146,15 +147,16 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_spread(NuArgs a) {
     }
 }
 
-// 1D spreading as a gather: thread per (grid cell, vector, group of kKG
+// 1D spreading as a gather: thread per (grid cell, vector, group of G
 // amplitude terms) sums the contributions listed for its cell, in source
 // order, and writes every cell (no atomics, no zeroing, a deterministic
 // sum).  Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source
-// phase, as in nufft_spread.
-constexpr int kKG = 8;
-
+// phase, as in nufft_spread.  b is stored by source, b[j kp + k] with kp =
+// G times the groups (zero past K), so that a contribution's G terms come
+// in 16-byte reads and its index, weight, f and phase reads serve all G.
+template <int G>
 __global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
-    const int ngrp = (a.K + kKG - 1) / kKG;
+    const int ngrp = a.kp / G;
     const long long M = a.Mr[0];
     const long long total = M * a.nv * ngrp;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -162,30 +164,39 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
         const int m = (int)(e % M);
         const long long rest = e / M;
         const int grp = (int)(rest % ngrp), v = (int)(rest / ngrp);
-        const int k0 = grp * kKG;
-        float2 acc[kKG];
+        const int k0 = grp * G;
+        float2 acc[G];
 #pragma unroll
-        for (int kk = 0; kk < kKG; ++kk) acc[kk] = make_float2(0.f, 0.f);
+        for (int kk = 0; kk < G; ++kk) acc[kk] = make_float2(0.f, 0.f);
         const int t1 = a.cptr[m + 1];
         for (int t = a.cptr[m]; t < t1; ++t) {
             const int j = a.cidx[t];
             const float w = a.cwt[t];
             const float2 fp = cmul(a.f[(size_t)v * a.N + j], a.pre[j]);
             const float2 wf = make_float2(w * fp.x, w * fp.y);
+            const float4* bp =
+                (const float4*)(a.b + (size_t)j * a.kp + k0);
 #pragma unroll
-            for (int kk = 0; kk < kKG; ++kk) {
-                if (k0 + kk < a.K) {
-                    const float2 z = cmul(a.b[(size_t)(k0 + kk) * a.N + j], wf);
-                    acc[kk].x += z.x;
-                    acc[kk].y += z.y;
-                }
+            for (int h = 0; h < G / 2; ++h) {
+                const float4 b2 = bp[h];
+                const float2 z0 = cmul(make_float2(b2.x, b2.y), wf);
+                const float2 z1 = cmul(make_float2(b2.z, b2.w), wf);
+                acc[2 * h].x += z0.x;
+                acc[2 * h].y += z0.y;
+                acc[2 * h + 1].x += z1.x;
+                acc[2 * h + 1].y += z1.y;
             }
         }
 #pragma unroll
-        for (int kk = 0; kk < kKG; ++kk)
+        for (int kk = 0; kk < G; ++kk)
             if (k0 + kk < a.K)
                 a.grid[(size_t)(v * a.K + k0 + kk) * a.cells + m] = acc[kk];
     }
+}
+
+// Terms per gather group: all K when K <= 32 (rounded up to 8), else 32.
+int gather_group(int K) {
+    return K >= 32 ? 32 : ((K + 7) / 8) * 8;
 }
 
 // Batched power-of-two FFT with the positive exponent, `batch` sequences per
@@ -408,7 +419,8 @@ struct NufftPlan {
     float2* post = nullptr;
     float* dec[2] = {nullptr, nullptr};
     float2* a = nullptr;
-    float2* bb = nullptr;
+    float2* bb = nullptr;     // NuArgs::b
+    int kp = 0;
     int* cptr = nullptr;      // 1D gather CSR (NuArgs)
     int* cidx = nullptr;
     float* cwt = nullptr;
@@ -524,9 +536,23 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
         post[i] = make_float2((float)(mag * std::cos(2 * kPi * ph)),
                               (float)(mag * std::sin(2 * kPi * ph)));
     }
-    for (long long e = 0; e < (long long)K * N; ++e) {
+    for (long long e = 0; e < (long long)K * N; ++e)
         av[e] = make_float2((float)a[2 * e], (float)a[2 * e + 1]);
-        bv[e] = make_float2((float)b[2 * e], (float)b[2 * e + 1]);
+    if (r == 1) {
+        // by source, kp terms a row (the gather reads a source's terms
+        // together), zero past K
+        const int G = gather_group(K);
+        q->kp = (K + G - 1) / G * G;
+        bv.assign((size_t)N * q->kp, make_float2(0.f, 0.f));
+        for (int k = 0; k < K; ++k)
+            for (long long j = 0; j < N; ++j) {
+                const long long e = (long long)k * N + j;
+                bv[(size_t)j * q->kp + k] =
+                    make_float2((float)b[2 * e], (float)b[2 * e + 1]);
+            }
+    } else {
+        for (long long e = 0; e < (long long)K * N; ++e)
+            bv[e] = make_float2((float)b[2 * e], (float)b[2 * e + 1]);
     }
     std::vector<float> dec[2];
     for (int d = 0; d < r; ++d) {
@@ -757,6 +783,7 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         a.dec1 = q.dec[1];
         a.a = q.a;
         a.b = q.bb;
+        a.kp = q.kp;
         a.cptr = q.cptr;
         a.cidx = q.cidx;
         a.cwt = q.cwt;
@@ -775,13 +802,29 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         }
         {
             ProfScope ps(p, st);
-            if (q.r == 1)
-                hipLaunchKernelGGL(
-                    nufft_gather1,
-                    dim3(blocks_for_n((long long)q.Mr[0] * nv *
-                                      ((q.K + kKG - 1) / kKG))),
-                    dim3(kNufftThreads), 0, st, a);
-            else
+            if (q.r == 1) {
+                const int G = gather_group(q.K);
+                const dim3 grid(
+                    blocks_for_n((long long)q.Mr[0] * nv * (q.kp / G)));
+                switch (G) {
+                    case 8:
+                        hipLaunchKernelGGL(nufft_gather1<8>, grid,
+                                           dim3(kNufftThreads), 0, st, a);
+                        break;
+                    case 16:
+                        hipLaunchKernelGGL(nufft_gather1<16>, grid,
+                                           dim3(kNufftThreads), 0, st, a);
+                        break;
+                    case 24:
+                        hipLaunchKernelGGL(nufft_gather1<24>, grid,
+                                           dim3(kNufftThreads), 0, st, a);
+                        break;
+                    default:
+                        hipLaunchKernelGGL(nufft_gather1<32>, grid,
+                                           dim3(kNufftThreads), 0, st, a);
+                        break;
+                }
+            } else
                 hipLaunchKernelGGL(nufft_spread<2>, dim3(blocks_for_n(q.N)),
                                    dim3(kNufftThreads), 0, st, a);
             ps.end("nufft_spread", N * nv * 8.0 + N * q.K * 8.0 + N * 16.0,
