@@ -212,7 +212,9 @@ int gather_group(int K) {
 // radix-2 stages are taken two at a time (one radix-4 pass over LDS, the
 // same butterflies and table twiddles as the two stages), with a single
 // stage first when log2 n is odd, and the twiddle table of the length is
-// staged in LDS.  In LDS, entry i of sequence b sits at b P + i + i / 16
+// staged in LDS.  That single stage is formed as the entries are read, and
+// the last radix-4 pass writes its outputs from registers, so the entries
+// cross LDS two times fewer.  In LDS, entry i of sequence b sits at b P + i + i / 16
 // (P = fft_pitch(n)): one pad entry every 16 entries and one more per
 // sequence spread the bit-reversed stores, the batch-fastest element loops
 // and the short butterfly spans over the banks.  With total > 0 (first step
@@ -260,30 +262,37 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
     const long long s0 = ((long long)blockIdx.x - col * groups) * B;
     const float2* in = a.src + col * a.col_dist + s0 * a.seq_dist;
     const bool bin = a.stride != 1;
-    for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bin ? e >> a.logb : (e & (n - 1));
-        const int b = bin ? e & (B - 1) : (e >> a.logn);
-        const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
-        x[fft_ix(b, P, rv)] = in[(long long)t * a.stride + b * a.seq_dist];
-    }
-    for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = a.tw[e];
-    __syncthreads();
     int lh = 0;
     if (a.logn & 1) {
-        // span-1 stage: consecutive pairs, twiddle 1
-        for (int qq = threadIdx.x; qq < (n / 2) * B; qq += blockDim.x) {
-            const int b = qq >> (a.logn - 1), j = 2 * (qq & (n / 2 - 1));
-            const int i0 = fft_ix(b, P, j);     // j even: i0 + 1 is j + 1
-            const float2 u = x[i0], v = x[i0 + 1];
+        // odd length: the span-1 stage (pairs t, t + n/2 of the natural
+        // order, adjacent after the bit reversal, twiddle 1) as they are
+        // read
+        for (int pe = threadIdx.x; pe < (n / 2) * B; pe += blockDim.x) {
+            const int t = bin ? pe >> a.logb : (pe & (n / 2 - 1));
+            const int b = bin ? pe & (B - 1) : (pe >> (a.logn - 1));
+            const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
+            const float2* src = in + (long long)t * a.stride + b * a.seq_dist;
+            const float2 u = src[0];
+            const float2 v = src[(long long)(n / 2) * a.stride];
+            const int i0 = fft_ix(b, P, rv);    // rv even: i0 + 1 is rv + 1
             x[i0] = cadd(u, v);
             x[i0 + 1] = csub(u, v);
         }
-        __syncthreads();
         lh = 1;
+    } else {
+        for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
+            const int t = bin ? e >> a.logb : (e & (n - 1));
+            const int b = bin ? e & (B - 1) : (e >> a.logn);
+            const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
+            x[fft_ix(b, P, rv)] = in[(long long)t * a.stride + b * a.seq_dist];
+        }
     }
-    for (; lh + 1 < a.logn; lh += 2) {
-        // stages lh (span half) and lh + 1 (span 2 half) on the four
-        // entries i0 + {0, 1, 2, 3} half
+    for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = a.tw[e];
+    __syncthreads();
+    // radix-4 passes: stages lh (span half) and lh + 1 (span 2 half) on the
+    // four entries j0 + {0, 1, 2, 3} half; the last (lh = logn - 2) writes
+    // the output from registers
+    for (; lh + 2 < a.logn; lh += 2) {
         const int half = 1 << lh;
         const int ts1 = n >> (lh + 1), ts2 = n >> (lh + 2);
         for (int qq = threadIdx.x; qq < (n / 4) * B; qq += blockDim.x) {
@@ -308,19 +317,48 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
     }
     float2* out = a.dst + col * a.ocol_dist + s0 * a.oseq_dist;
     const bool bout = a.ostride != 1;
-    for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-        const int t = bout ? e >> a.logb : (e & (n - 1));
-        const int b = bout ? e & (B - 1) : (e >> a.logn);
-        float2 y = x[fft_ix(b, P, t)];
+    // output t of sequence b (with the four-step twiddle exp(2 pi i s t /
+    // total), the product reduced exactly first; p < total <= 2^24, so
+    // 2 p / total is exact in FP32)
+    auto put = [&](int b, int t, float2 y) {
         if (a.total > 0) {
-            // exp(2 pi i s t / total), the product reduced exactly first;
-            // p < total <= 2^24, so 2 p / total is exact in FP32
             const long long p = ((s0 + b) * t) & (a.total - 1);
             float sn, cs;
             sincospif((float)p * a.tscale, &sn, &cs);
             y = cmul(y, make_float2(cs, sn));
         }
         out[(long long)t * a.ostride + b * a.oseq_dist] = y;
+    };
+    if (lh + 2 == a.logn) {
+        // the last radix-4 pass (half = n/4, one group): entries q + c n/4
+        // are the outputs t = q, q + n/4, q + n/2, q + 3n/4; on a strided
+        // output side the sequence index runs fastest across the lanes so
+        // that the writes move in runs
+        const int half = n / 4;
+        for (int qq = threadIdx.x; qq < (n / 4) * B; qq += blockDim.x) {
+            const int b = bout ? qq & (B - 1) : qq >> (a.logn - 2);
+            const int q = bout ? qq >> a.logb : qq & (n / 4 - 1);
+            const int i0 = fft_ix(b, P, q), i1 = fft_ix(b, P, q + half);
+            const int i2 = fft_ix(b, P, q + 2 * half);
+            const int i3 = fft_ix(b, P, q + 3 * half);
+            const float2 w1 = tws[q * 2];
+            const float2 u0 = x[i0], v0 = cmul(x[i1], w1);
+            const float2 u1 = x[i2], v1 = cmul(x[i3], w1);
+            const float2 b0 = cadd(u0, v0), b1 = csub(u0, v0);
+            const float2 c2 = cmul(cadd(u1, v1), tws[q]);
+            const float2 c3 = cmul(csub(u1, v1), tws[q + half]);
+            put(b, q, cadd(b0, c2));
+            put(b, q + half, cadd(b1, c3));
+            put(b, q + 2 * half, csub(b0, c2));
+            put(b, q + 3 * half, csub(b1, c3));
+        }
+    } else {
+        // length 2: the span-1 stage was the only one
+        for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
+            const int t = bout ? e >> a.logb : (e & (n - 1));
+            const int b = bout ? e & (B - 1) : (e >> a.logn);
+            put(b, t, x[fft_ix(b, P, t)]);
+        }
     }
 }
 
