@@ -212,9 +212,10 @@ int gather_group(int K) {
 // radix-2 stages are taken two at a time (one radix-4 pass over LDS, the
 // same butterflies and table twiddles as the two stages), with a single
 // stage first when log2 n is odd, and the twiddle table of the length is
-// staged in LDS.  That single stage is formed as the entries are read, and
-// the last radix-4 pass writes its outputs from registers, so the entries
-// cross LDS two times fewer.  In LDS, entry i of sequence b sits at b P + i + i / 16
+// staged in LDS.  That single stage (odd lengths) or the first radix-4
+// pass (even lengths) is formed as the entries are read, and the last
+// radix-4 pass writes its outputs from registers, so the entries cross LDS
+// two times fewer.  In LDS, entry i of sequence b sits at b P + i + i / 16
 // (P = fft_pitch(n)): one pad entry every 16 entries and one more per
 // sequence spread the bit-reversed stores, the batch-fastest element loops
 // and the short butterfly spans over the banks.  With total > 0 (first step
@@ -280,12 +281,30 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
         }
         lh = 1;
     } else {
-        for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
-            const int t = bin ? e >> a.logb : (e & (n - 1));
-            const int b = bin ? e & (B - 1) : (e >> a.logn);
+        // even length: the first radix-4 pass (stages 0 and 1 on the
+        // entries t, t + n/2, t + n/4, t + 3n/4 of the natural order, which
+        // sit at rv .. rv + 3 after the bit reversal) as they are read, with
+        // the table's twiddles 0 and n/4 (read from the table itself: the
+        // LDS copy is not staged yet)
+        const float2 w0 = a.tw[0], wq = a.tw[n / 4];
+        for (int pe = threadIdx.x; pe < (n / 4) * B; pe += blockDim.x) {
+            const int t = bin ? pe >> a.logb : (pe & (n / 4 - 1));
+            const int b = bin ? pe & (B - 1) : (pe >> (a.logn - 2));
             const int rv = (int)(__brev((unsigned)t) >> (32 - a.logn));
-            x[fft_ix(b, P, rv)] = in[(long long)t * a.stride + b * a.seq_dist];
+            const float2* src = in + (long long)t * a.stride + b * a.seq_dist;
+            const long long qs = (long long)(n / 4) * a.stride;
+            const float2 u0 = src[0], v0 = cmul(src[2 * qs], w0);
+            const float2 u1 = src[qs], v1 = cmul(src[3 * qs], w0);
+            const float2 b0 = cadd(u0, v0), b1 = csub(u0, v0);
+            const float2 c2 = cmul(cadd(u1, v1), w0);
+            const float2 c3 = cmul(csub(u1, v1), wq);
+            const int i0 = fft_ix(b, P, rv);    // rv % 4 = 0: i0 + c is rv + c
+            x[i0] = cadd(b0, c2);
+            x[i0 + 2] = csub(b0, c2);
+            x[i0 + 1] = cadd(b1, c3);
+            x[i0 + 3] = csub(b1, c3);
         }
+        lh = 2;
     }
     for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = a.tw[e];
     __syncthreads();
@@ -353,7 +372,7 @@ __global__ void __launch_bounds__(kFftThreads) fft_lds(FftArgs a) {
             put(b, q + 3 * half, csub(b1, c3));
         }
     } else {
-        // length 2: the span-1 stage was the only one
+        // lengths 2 and 4: the stages formed at the read were all of them
         for (int e = threadIdx.x; e < n * B; e += blockDim.x) {
             const int t = bout ? e >> a.logb : (e & (n - 1));
             const int b = bout ? e & (B - 1) : (e >> a.logn);
