@@ -34,7 +34,10 @@ namespace bfi {
 namespace {
 
 constexpr int kW = 7;                 // stencil half-width (2 kW points)
+// 2D spreading gathers while its contribution lists (N (2 kW)^2 entries of
+// 8 bytes) stay within 2 GiB, and spreads by atomics past that
 constexpr int kFftMax = 4096;         // longest FFT held in one workgroup
+constexpr long long kMaxGatherEntries = 1LL << 28;
 constexpr int kNufftThreads = 256;
 constexpr int kFftLds = 80 * 1024;    // FFT workgroup LDS (two per CU)
 constexpr int kFftThreads = 1024;     // FFT workgroup (16 waves)
@@ -54,15 +57,16 @@ struct NuArgs {
     const float2* post;
     const float* dec0;
     const float* dec1;
-    // 1D: the sources' contributions by grid cell (CSR, built at plan
-    // time): cell m takes entries cptr[m] .. cptr[m + 1] - 1, each a source
-    // index and its Gaussian weight times the cell's deconvolution factor
+    // the sources' contributions by grid cell (CSR, built at plan time):
+    // cell m takes entries cptr[m] .. cptr[m + 1] - 1, each a source index
+    // and its Gaussian weight times the cell's deconvolution factor (the
+    // products over the dimensions in 2D); null where 2D spreads by atomics
     const int* cptr;
     const int* cidx;
     const float* cwt;
     const float2* a;
-    const float2* b;                  // 2D: [K][N]; 1D: [N][Kp] (below)
-    int kp;                           // 1D: terms per source row of b
+    const float2* b;                  // gather: [N][kp]; atomics: [K][N]
+    int kp;                           // gather: terms per source row of b
     const float2* f;                  // [nv][N] chunk
     float2* g;
     float2* grid;                     // [nv * K][cells]
@@ -147,21 +151,21 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_spread(NuArgs a) {
     }
 }
 
-// 1D spreading as a gather: thread per (grid cell, vector, group of G
+// Spreading as a gather: thread per (grid cell, vector, group of G
 // amplitude terms) sums the contributions listed for its cell, in source
 // order, and writes every cell (no atomics, no zeroing, a deterministic
-// sum).  Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source
+// sum; cells in row-major order in 2D).  Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source
 // phase, as in nufft_spread.  b is stored by source, b[j kp + k] with kp =
 // G times the groups (zero past K), so that a contribution's G terms come
 // in 16-byte reads and its index, weight, f and phase reads serve all G.
 template <int G>
-__global__ void __launch_bounds__(kNufftThreads) nufft_gather1(NuArgs a) {
+__global__ void __launch_bounds__(kNufftThreads) nufft_gather(NuArgs a) {
     const int ngrp = a.kp / G;
-    const long long M = a.Mr[0];
+    const long long M = a.cells;
     const long long total = M * a.nv * ngrp;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
          e < total; e += (long long)gridDim.x * blockDim.x) {
-        const int m = (int)(e % M);
+        const long long m = e % M;
         const long long rest = e / M;
         const int grp = (int)(rest % ngrp), v = (int)(rest / ngrp);
         const int k0 = grp * G;
@@ -478,6 +482,7 @@ struct NufftPlan {
     float2* a = nullptr;
     float2* bb = nullptr;     // NuArgs::b
     int kp = 0;
+    bool gather = false;      // spreading by the CSR gather (else atomics)
     int* cptr = nullptr;      // 1D gather CSR (NuArgs)
     int* cidx = nullptr;
     float* cwt = nullptr;
@@ -595,9 +600,12 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
     }
     for (long long e = 0; e < (long long)K * N; ++e)
         av[e] = make_float2((float)a[2 * e], (float)a[2 * e + 1]);
-    if (r == 1) {
-        // by source, kp terms a row (the gather reads a source's terms
-        // together), zero past K
+    long long per_source = 2 * kW;
+    if (r == 2) per_source *= 2 * kW;
+    q->gather = r == 1 || N * per_source <= kMaxGatherEntries;
+    if (q->gather) {
+        // for the gather: by source, kp terms a row (it reads a source's
+        // terms together), zero past K
         const int G = gather_group(K);
         q->kp = (K + G - 1) / G * G;
         bv.assign((size_t)N * q->kp, make_float2(0.f, 0.f));
@@ -627,33 +635,55 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
     // deconvolution factor (FP64, stored FP32)
     std::vector<int> cptr, cidx;
     std::vector<float> cwt;
-    if (r == 1) {
-        const long long M = q->Mr[0];
-        const int Mh = q->Mh[0];
-        auto cell_of = [&](long long m) {
-            long long c = m % M;
+    if (q->gather) {
+        // the grid point (mode) of contribution e of source j in dimension
+        // d, its cell index and its FP64 weight (Gaussian of the offset
+        // times the deconvolution factor)
+        auto mode = [&](long long j, int d, int e) -> long long {
+            return (long long)sbase[j * r + d] - kW + 1 + e;
+        };
+        auto cell_d = [&](long long m, int d) -> long long {
+            const long long M = q->Mr[d];
+            const long long c = m % M;
             return c < 0 ? c + M : c;
         };
-        cptr.assign((size_t)M + 1, 0);
+        auto weight = [&](long long j, int d, int e) -> double {
+            const double dd = (double)(e - kW + 1) - (double)sfrac[j * r + d];
+            return std::exp(-dd * dd / b4) *
+                   (double)dec[d][mode(j, d, e) + q->Mh[d]];
+        };
         for (long long j = 0; j < N; ++j)
-            for (int e = 0; e < 2 * kW; ++e)
-                ++cptr[(size_t)cell_of(sbase[j] - kW + 1 + e) + 1];
-        for (long long m = 0; m < M; ++m) cptr[m + 1] += cptr[m];
-        std::vector<int> fill(cptr.begin(), cptr.end() - 1);
-        cidx.resize((size_t)N * 2 * kW);
-        cwt.resize((size_t)N * 2 * kW);
-        for (long long j = 0; j < N; ++j)
-            for (int e = 0; e < 2 * kW; ++e) {
-                const long long m = sbase[j] - kW + 1 + e;   // mode index
-                if (m + Mh < 0 || m + Mh >= 2LL * Mh) {
-                    delete q;
-                    return "a source falls outside the lifted grid";
+            for (int d = 0; d < r; ++d)
+                for (int e = 0; e < 2 * kW; ++e) {
+                    const long long m = mode(j, d, e);
+                    if (m + q->Mh[d] < 0 || m + q->Mh[d] >= 2LL * q->Mh[d]) {
+                        delete q;
+                        return "a source falls outside the lifted grid";
+                    }
                 }
-                const double d = (double)(e - kW + 1) - (double)sfrac[j];
-                const int pos = fill[(size_t)cell_of(m)]++;
-                cidx[pos] = (int)j;
-                cwt[pos] = (float)(std::exp(-d * d / b4) *
-                                   (double)dec[0][m + Mh]);
+        const int E1 = r == 2 ? 2 * kW : 1;     // entries of the 2nd dim
+        auto cell_of = [&](long long j, int e0, int e1) -> long long {
+            const long long c0 = cell_d(mode(j, 0, e0), 0);
+            return r == 1 ? c0
+                          : c0 * q->Mr[1] + cell_d(mode(j, 1, e1), 1);
+        };
+        cptr.assign((size_t)q->cells + 1, 0);
+        for (long long j = 0; j < N; ++j)
+            for (int e0 = 0; e0 < 2 * kW; ++e0)
+                for (int e1 = 0; e1 < E1; ++e1)
+                    ++cptr[(size_t)cell_of(j, e0, e1) + 1];
+        for (long long m = 0; m < q->cells; ++m) cptr[m + 1] += cptr[m];
+        std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+        cidx.resize((size_t)(N * per_source));
+        cwt.resize((size_t)(N * per_source));
+        for (long long j = 0; j < N; ++j)
+            for (int e0 = 0; e0 < 2 * kW; ++e0) {
+                const double w0 = weight(j, 0, e0);
+                for (int e1 = 0; e1 < E1; ++e1) {
+                    const int pos = fill[(size_t)cell_of(j, e0, e1)]++;
+                    cidx[pos] = (int)j;
+                    cwt[pos] = (float)(r == 1 ? w0 : w0 * weight(j, 1, e1));
+                }
             }
     }
     // FFT twiddles for every length the transforms use
@@ -851,7 +881,7 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         const long long gcells = ncols * q.cells;
         // the spectrum: in place, or (four-step) the second half of ws
         float2* const spec = q.n1 ? a.grid + gcells : a.grid;
-        if (q.r == 2) {
+        if (!q.gather) {
             ProfScope ps(p, st);
             hipLaunchKernelGGL(nufft_zero, dim3(blocks_for_n(gcells)),
                                dim3(kNufftThreads), 0, st, a.grid, gcells);
@@ -859,25 +889,24 @@ std::string launch_nufft(Plan& p, int nvec, const float2* f, float2* g,
         }
         {
             ProfScope ps(p, st);
-            if (q.r == 1) {
+            if (q.gather) {
                 const int G = gather_group(q.K);
-                const dim3 grid(
-                    blocks_for_n((long long)q.Mr[0] * nv * (q.kp / G)));
+                const dim3 grid(blocks_for_n(q.cells * nv * (q.kp / G)));
                 switch (G) {
                     case 8:
-                        hipLaunchKernelGGL(nufft_gather1<8>, grid,
+                        hipLaunchKernelGGL(nufft_gather<8>, grid,
                                            dim3(kNufftThreads), 0, st, a);
                         break;
                     case 16:
-                        hipLaunchKernelGGL(nufft_gather1<16>, grid,
+                        hipLaunchKernelGGL(nufft_gather<16>, grid,
                                            dim3(kNufftThreads), 0, st, a);
                         break;
                     case 24:
-                        hipLaunchKernelGGL(nufft_gather1<24>, grid,
+                        hipLaunchKernelGGL(nufft_gather<24>, grid,
                                            dim3(kNufftThreads), 0, st, a);
                         break;
                     default:
-                        hipLaunchKernelGGL(nufft_gather1<32>, grid,
+                        hipLaunchKernelGGL(nufft_gather<32>, grid,
                                            dim3(kNufftThreads), 0, st, a);
                         break;
                 }
