@@ -24,6 +24,7 @@
 // the device arithmetic (FP32) only forms Gaussian weights of fractions.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -602,7 +603,10 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
         av[e] = make_float2((float)a[2 * e], (float)a[2 * e + 1]);
     long long per_source = 2 * kW;
     if (r == 2) per_source *= 2 * kW;
-    q->gather = r == 1 || N * per_source <= kMaxGatherEntries;
+    // BF_NUFFT_ATOMICS=1 at plan time: 2D spreads by atomics at any size
+    const char* aenv = std::getenv("BF_NUFFT_ATOMICS");
+    const bool atomics = r == 2 && aenv && std::atoi(aenv) == 1;
+    q->gather = r == 1 || (!atomics && N * per_source <= kMaxGatherEntries);
     if (q->gather) {
         // for the gather: by source, kp terms a row (it reads a source's
         // terms together), zero past K

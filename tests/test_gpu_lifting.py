@@ -163,6 +163,40 @@ def test_refused_kernel_gets_the_butterfly():
     assert e < TOL
 
 
+def test_2d_atomic_spreading_matches_gather(monkeypatch):
+    # 2D plans spread by their contribution lists, and by float atomics
+    # where the lists would pass 2^28 entries; BF_NUFFT_ATOMICS=1 at plan
+    # time selects the atomic form at a size the test can check: both
+    # against the direct sum and against each other (to rounding: the
+    # atomics add in any order and form their weights in FP32)
+    import paper_1803_04128_amd as bfm
+    N, K = 1800, 3
+    log(f"case lifted 2D spreading, gather and atomics, N={N} K={K}")
+    rng = np.random.default_rng(31)
+    t = rng.uniform(-0.5, 0.5, (N, 2)) * np.sqrt((20.0, 8.0)) + 0.2
+    s = rng.uniform(-0.5, 0.5, (N, 2)) * np.sqrt((20.0, 8.0)) - 0.7
+    a = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    b = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    f = gaussian_vectors(N, 3, 4)
+    f32 = f.astype(np.complex64).astype(np.complex128)
+    outs = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BF_NUFFT_ATOMICS", mode)
+        with bfm.plan_lifted(t, s, a, b, max_nvec=3) as pl:
+            pl.profile(True)
+            outs[mode] = _gpu_apply(pl, f32)
+            names = set(pl.profile_read())
+            pl.profile(False)
+        assert ("nufft_zero" in names) == (mode == "1"), names
+    ref = sum(a[k][None, :] * ol.nufft3_direct(t, s, b[k][None, :] * f32)
+              for k in range(K))
+    e_g, e_a = np.max(rel(outs["0"], ref)), np.max(rel(outs["1"], ref))
+    e_ga = np.max(rel(outs["1"], outs["0"]))
+    log(f"  gather vs direct {e_g:.3e}, atomics vs direct {e_a:.3e}, "
+        f"atomics vs gather {e_ga:.3e}")
+    assert e_g < TOL and e_a < TOL and e_ga < 2e-6
+
+
 def test_lifted_plan_refuses_what_it_cannot_hold():
     import paper_1803_04128_amd as bfm
     from paper_1803_04128_amd import BfError
