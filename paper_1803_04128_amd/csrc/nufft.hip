@@ -35,9 +35,9 @@ namespace bfi {
 namespace {
 
 constexpr int kW = 7;                 // stencil half-width (2 kW points)
+constexpr int kFftMax = 4096;         // longest FFT held in one workgroup
 // 2D spreading gathers while its contribution lists (N (2 kW)^2 entries of
 // 8 bytes) stay within 2 GiB, and spreads by atomics past that
-constexpr int kFftMax = 4096;         // longest FFT held in one workgroup
 constexpr long long kMaxGatherEntries = 1LL << 28;
 constexpr int kNufftThreads = 256;
 constexpr int kFftLds = 80 * 1024;    // FFT workgroup LDS (two per CU)
