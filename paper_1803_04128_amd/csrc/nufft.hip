@@ -155,10 +155,11 @@ __global__ void __launch_bounds__(kNufftThreads) nufft_spread(NuArgs a) {
 // Spreading as a gather: thread per (grid cell, vector, group of G
 // amplitude terms) sums the contributions listed for its cell, in source
 // order, and writes every cell (no atomics, no zeroing, a deterministic
-// sum; cells in row-major order in 2D).  Column c = v K + k carries b_k(xi_j) f_v(xi_j) times the source
-// phase, as in nufft_spread.  b is stored by source, b[j kp + k] with kp =
-// G times the groups (zero past K), so that a contribution's G terms come
-// in 16-byte reads and its index, weight, f and phase reads serve all G.
+// sum; cells in row-major order in 2D).  Column c = v K + k carries
+// b_k(xi_j) f_v(xi_j) times the source phase, as in nufft_spread.  b is
+// stored by source, b[j kp + k] with kp = G times the groups (zero past
+// K), so that a contribution's G terms come in 16-byte reads and its
+// index, weight, f and phase reads serve all G.
 template <int G>
 __global__ void __launch_bounds__(kNufftThreads) nufft_gather(NuArgs a) {
     const int ngrp = a.kp / G;
@@ -680,15 +681,19 @@ std::string nufft_build(Plan& p, int r, const double* P, const double* Q,
         std::vector<int> fill(cptr.begin(), cptr.end() - 1);
         cidx.resize((size_t)(N * per_source));
         cwt.resize((size_t)(N * per_source));
-        for (long long j = 0; j < N; ++j)
+        for (long long j = 0; j < N; ++j) {
+            double w1[2 * kW];
+            for (int e1 = 0; e1 < E1; ++e1)
+                w1[e1] = r == 2 ? weight(j, 1, e1) : 1.0;
             for (int e0 = 0; e0 < 2 * kW; ++e0) {
                 const double w0 = weight(j, 0, e0);
                 for (int e1 = 0; e1 < E1; ++e1) {
                     const int pos = fill[(size_t)cell_of(j, e0, e1)]++;
                     cidx[pos] = (int)j;
-                    cwt[pos] = (float)(r == 1 ? w0 : w0 * weight(j, 1, e1));
+                    cwt[pos] = (float)(r == 1 ? w0 : w0 * w1[e1]);
                 }
             }
+        }
     }
     // FFT twiddles for every length the transforms use
     std::vector<int> lens;
